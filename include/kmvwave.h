@@ -1,0 +1,182 @@
+/*
+ * kmvwave — explicit mass-lumped KMV wave propagation (forward, adjoint, gradient)
+ * on MI355X (gfx950).  C ABI.
+ *
+ * The method (Roberts et al., "Full waveform inversion using triangular waveform
+ * adapted meshes"):
+ *   - acoustic wave equation u_tt + eta u_t - div(c^2 grad u) = f   (section
+ *     "Forward wave simulation", eq. acoustic_pml with only the tr(Psi_1) term
+ *     kept as a quadratic sponge eta; homogeneous Neumann outer boundary);
+ *   - continuous Galerkin on triangles/tetrahedra with mass-lumped KMV elements,
+ *     degree 1..5 on triangles and 1..3 on tetrahedra (section "Higher-order mass
+ *     lumping");
+ *   - central differences in time, the diagonal leading matrix inverted pointwise
+ *     (eqs. Leapfrog, forward3);
+ *   - misfit J = 1/2 sum_n sum_j (d^n_j - dobs^n_j)^2 without a dt factor
+ *     (eq. l2error and the remark after eq. gradient3);
+ *   - discrete adjoint = transposed scheme, gradient dJ/dc_i from eq. gradient3
+ *     (section "The adjoint-state and gradient problems discretized").
+ *
+ * Conventions
+ *   - Every function returns an int status: KMV_OK (0) or a negative code; a
+ *     message for the last failure on the calling thread is kmv_last_error().
+ *     No C++ exception crosses this boundary.
+ *   - Units: km, s, km/s.  Points are (x, z) in 2D, (x, y, z) in 3D.
+ *   - "DOF order" is the library's own numbering of the global degrees of freedom
+ *     (patch-contiguous); kmv_mesh_dof_coords gives the coordinates in that order.
+ *   - Host pointers are read during the call and never retained.  Device pointers
+ *     must be allocations on the current HIP device; work on them is enqueued on
+ *     the given stream (a hipStream_t, NULL = the null stream) and is complete
+ *     only when that stream is synchronised, except for calls that return a host
+ *     scalar (they synchronise the stream before returning).
+ *   - Precision: KMV_FP64 computes everything in float64.  KMV_FP32 keeps the
+ *     wavefields, operators and traces in float32, accumulates the gradient over
+ *     time steps and reduces the misfit in float64.  Trace and observed buffers
+ *     have the problem's element type (float or double); wavespeed and gradient
+ *     buffers are always double.
+ */
+#ifndef KMVWAVE_H
+#define KMVWAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  KMV_OK = 0,
+  KMV_EINVAL = -1,   /* bad argument (null pointer, size, option) */
+  KMV_ENOMEM = -2,   /* host or device allocation failed, or over the memory budget */
+  KMV_EDEGREE = -3,  /* unsupported (dim, degree): tri 1..5, tet 1..3 */
+  KMV_EMESH = -4,    /* invalid mesh: vertex index out of range, degenerate cell */
+  KMV_EOUTSIDE = -5, /* a source or receiver lies outside every cell */
+  KMV_ECFL = -6,     /* dt above the Gershgorin bound 2/sqrt(rho(M^-1 K)) */
+  KMV_ENUMERIC = -7, /* non-finite value detected in a result */
+  KMV_EDEVICE = -8,  /* HIP runtime error */
+  KMV_EBUSY = -9,    /* serving: result not ready yet (not a failure) */
+  KMV_ESTATE = -10   /* call out of order (e.g. no sources set) */
+};
+
+enum { KMV_FP64 = 0, KMV_FP32 = 1 };
+
+typedef struct kmv_mesh_s* kmv_mesh;       /* opaque, library-owned */
+typedef struct kmv_problem_s* kmv_problem; /* opaque, library-owned */
+
+/* Message describing the last failure on this thread ("" if none). */
+const char* kmv_last_error(void);
+
+/* ------------------------------------------------------------------ elements */
+
+/* Reference KMV element tables (section "Higher-order mass lumping"; node
+ * coordinates of figures fig:2dels/fig:3dels, weights = the nodal quadrature rule).
+ * n_nodes: out, nodes per cell.  If nodes/weights/grads are non-NULL they receive
+ * [n*dim] reference coordinates, [n] weights and [n*n*dim] basis gradients
+ * grads[(q*n + a)*dim + r] = d phi_a / d xi_r at node q.  Host only.
+ * Errors: KMV_EDEGREE. */
+int kmv_element_tables(int dim, int degree, int* n_nodes, double* nodes, double* weights,
+                       double* grads);
+
+/* ---------------------------------------------------------------------- mesh */
+
+/* Build the discretisation of a simplicial mesh (host only, no GPU needed):
+ * global DOF numbering (one per distinct node; the local-to-global map g(j,k) of
+ * section "Receivers and sources"), cell patches and colouring, geometry, lumped
+ * mass M_i = sum w_q |det J_e|.
+ *   coords [n_vertices*dim] (copied), cells [n_cells*(dim+1)] 0-based (copied).
+ *   patch_cells: cells per patch (0 = chosen from degree and dimension).
+ * Errors: KMV_EINVAL, KMV_EDEGREE, KMV_EMESH (index out of range, zero volume). */
+int kmv_mesh_create(int dim, int degree, const double* coords, int64_t n_vertices,
+                    const int32_t* cells, int64_t n_cells, int patch_cells, kmv_mesh* out);
+/* Sizes: any output pointer may be NULL. */
+int kmv_mesh_info(kmv_mesh m, int64_t* n_dofs, int64_t* n_cells, int* n_nodes,
+                  int64_t* n_patches, int64_t* n_shared_dofs);
+/* DOF coordinates [n_dofs*dim], caller-owned host buffer. */
+int kmv_mesh_dof_coords(kmv_mesh m, double* out);
+/* Lumped mass [n_dofs] in DOF order (appendix, M_u with the KMV rule). */
+int kmv_mesh_lumped_mass(kmv_mesh m, double* out);
+/* Global DOF of every node of every input cell: out[cell*n_nodes + a], input cell
+ * order, reference node order of kmv_element_tables. */
+int kmv_mesh_cell_dofs(kmv_mesh m, int64_t* out);
+/* Gershgorin estimate of the largest stable step, 2/sqrt(max_i sum_j |K_ij|/M_i)
+ * (eq. spectral), for nodal wavespeed c_host [n_dofs] (host, DOF order).  Host
+ * only.  Errors: KMV_EINVAL. */
+int kmv_cfl_dt(kmv_mesh m, const double* c_host, double* dt_max);
+/* Check the scheduling invariants the kernels rely on: no two cells of one colour
+ * in a patch share a DOF, patch-local maps agree with the global DOF map, every
+ * shared DOF lists the partial slots of exactly the patches that touch it, in
+ * patch order, and every lumped mass is positive.  Host only.
+ * Returns KMV_OK or KMV_EMESH with the first violation in kmv_last_error(). */
+int kmv_mesh_validate(kmv_mesh m);
+int kmv_mesh_destroy(kmv_mesh m);
+
+/* ------------------------------------------------------------------- problem */
+
+typedef struct {
+  int precision;            /* KMV_FP64 or KMV_FP32 */
+  double dt;                /* time step (s) */
+  int64_t n_steps;          /* N_t: steps n = 0..N_t-1 produce u^1..u^N_t */
+  int64_t checkpoint_every; /* reverse sweep: 0 = store every state if it fits
+                               mem_budget, else segments of this many steps */
+  size_t mem_budget;        /* bytes of device memory for stored states (0 = 8 GiB) */
+} kmv_options;
+
+/* Allocate device state for one shot configuration on the current device.
+ * Errors: KMV_EINVAL, KMV_ENOMEM, KMV_EDEVICE. */
+int kmv_problem_create(kmv_mesh m, const kmv_options* opt, kmv_problem* out);
+/* Spectral radius of M^-1 K(c) by a seeded power iteration on the GPU (the step
+ * bound of eq. spectral without the Gershgorin over-estimate).  Synchronises. */
+int kmv_spectral_radius(kmv_problem p, const void* c_dev, int iters, uint64_t seed,
+                        double* rho, void* stream);
+/* Damping eta [n_dofs] in 1/s (host, DOF order; NULL = none).  The step uses
+ * a = eta*dt/2 as the pointwise tr(Psi_1) term of eq. forward3. */
+int kmv_set_damping(kmv_problem p, const double* eta);
+/* Point sources x_s [n_src*dim] firing together with a Ricker wavelet
+ * w(t) = amp (1 - 2 pi^2 f0^2 (t-t0)^2) exp(-pi^2 f0^2 (t-t0)^2) sampled at
+ * t_n = n dt; injected as w(t_n) phi_a(x_s) (section "Receivers and sources").
+ * Errors: KMV_EOUTSIDE. */
+int kmv_set_sources(kmv_problem p, const double* xs, int n_src, double f0, double t0,
+                    double amp);
+/* Replace the wavelet by w[n_steps] (host). */
+int kmv_set_source_wavelet(kmv_problem p, const double* w);
+/* Receivers x_r [n_rec*dim]: d^n_j = sum_a phi_a(x_j) u^n_{g(e_j,a)}.
+ * Errors: KMV_EOUTSIDE. */
+int kmv_set_receivers(kmv_problem p, const double* xr, int n_rec);
+
+/* Forward solve (eqs. Leapfrog/forward3).  c_dev: double [n_dofs] wavespeed (DOF
+ * order).  traces_dev: [n_steps*n_rec] of the problem's type, row n-1 = d^n.
+ * Asynchronous on stream. */
+int kmv_forward(kmv_problem p, const void* c_dev, void* traces_dev, void* stream);
+/* Misfit and gradient: forward with stored or checkpointed states, J (eq.
+ * l2error, no dt), adjoint sweep (eq. acoustic_pml_FEM_adj) fused with the
+ * gradient accumulation (eq. gradient3).  observed_dev: [n_steps*n_rec] of the
+ * problem's type.  grad_dev: double [n_dofs] receives dJ/dc_i (Euclidean; the
+ * mesh-independent gradient is grad/M).  traces_dev: optional [n_steps*n_rec]
+ * output of the forward traces (NULL = not kept).  J_out (host) and the
+ * synchronisation: the stream is synchronised before return. */
+int kmv_misfit_gradient(kmv_problem p, const void* c_dev, const void* observed_dev,
+                        double* J_out, double* grad_dev, void* traces_dev, void* stream);
+/* Adjoint of the forward map for arbitrary receiver data y: lambda from the
+ * transposed scheme, (1+a) lambda^m = 2 lambda^{m+1} - dt^2 M^-1 K lambda^{m+1}
+ * - (1-a) lambda^{m+2} + M^-1 P^T y^m, m = N_t..1 (eq. acoustic_pml_FEM_adj).
+ * adj_src_dev: [n_steps*n_rec] of the problem's type, row m-1 = y^m.
+ * lambda_out_dev (optional): [(n_steps+1)*n_dofs], row m-1 = lambda^m.
+ * src_trace_dev (optional): [n_steps*n_src], row n = lambda^{n+1} sampled at the
+ * source points, so that <y, P u> = dt^2 sum_n w(t_n) sum_s src_trace[n][s]
+ * (the dot-product identity of the discrete adjoint). */
+int kmv_adjoint(kmv_problem p, const void* c_dev, const void* adj_src_dev,
+                void* lambda_out_dev, void* src_trace_dev, void* stream);
+/* Matrix-free stiffness apply y = K(c) u (appendix, matrix K).  u_dev, y_dev of
+ * the problem's type, [n_dofs], DOF order. */
+int kmv_stiffness_apply(kmv_problem p, const void* c_dev, const void* u_dev, void* y_dev,
+                        void* stream);
+/* Sizes of a problem. */
+int kmv_problem_info(kmv_problem p, int64_t* n_dofs, int64_t* n_steps, int* n_rec,
+                     int* precision, int64_t* checkpoint_every);
+int kmv_problem_destroy(kmv_problem p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KMVWAVE_H */

@@ -1,0 +1,160 @@
+"""Object wrappers over the same-name ctypes calls (marshalling only)."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import kmvwave as K
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Mesh:
+    """A simplicial mesh discretised with KMV elements of one degree (host-side
+    preprocessing: DOF numbering, patches, colouring, geometry, lumped mass)."""
+
+    def __init__(self, coords, cells, degree, patch_cells=0):
+        coords = np.asarray(coords, dtype=np.float64)
+        self.dim = coords.shape[1]
+        self.degree = degree
+        self.handle = K.kmv_mesh_create(self.dim, degree, coords, cells, patch_cells)
+        info = K.kmv_mesh_info(self.handle)
+        self.n_dofs = info["n_dofs"]
+        self.n_cells = info["n_cells"]
+        self.n_nodes = info["n_nodes"]
+        self.n_patches = info["n_patches"]
+        self.n_shared_dofs = info["n_shared_dofs"]
+
+    def dof_coords(self):
+        return K.kmv_mesh_dof_coords(self.handle, self.dim)
+
+    def lumped_mass(self):
+        return K.kmv_mesh_lumped_mass(self.handle)
+
+    def cell_dofs(self):
+        return K.kmv_mesh_cell_dofs(self.handle)
+
+    def cfl_dt(self, c):
+        """Gershgorin step bound 2/sqrt(max_i sum_j |K_ij| / M_i) (host)."""
+        return K.kmv_cfl_dt(self.handle, np.asarray(c, dtype=np.float64))
+
+    def validate(self):
+        K.kmv_mesh_validate(self.handle)
+
+    def nodal_values(self, fn):
+        x = self.dof_coords()
+        return fn(*[x[:, r] for r in range(self.dim)])
+
+    def close(self):
+        if getattr(self, "handle", None):
+            K.kmv_mesh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """Device state for one shot layout on one mesh (see kmv_problem_create)."""
+
+    def __init__(self, mesh: Mesh, dt, n_steps, precision="fp64", checkpoint_every=0, mem_budget=0):
+        self.mesh = mesh
+        self.dt = float(dt)
+        self.n_steps = int(n_steps)
+        self.precision = K.KMV_FP32 if precision in ("fp32", K.KMV_FP32) else K.KMV_FP64
+        self.handle = K.kmv_problem_create(mesh.handle, self.precision, self.dt, self.n_steps,
+                                           checkpoint_every, mem_budget)
+        self.n_rec = 0
+        self.n_src = 0
+
+    @property
+    def dtype(self):
+        torch = _torch()
+        return torch.float32 if self.precision == K.KMV_FP32 else torch.float64
+
+    def info(self):
+        return K.kmv_problem_info(self.handle)
+
+    def cfl_dt(self, c):
+        return self.mesh.cfl_dt(c)
+
+    def spectral_radius(self, c, iters=200, seed=0):
+        return K.kmv_spectral_radius(self.handle, self._c(c), iters, seed)
+
+    def set_damping(self, eta):
+        K.kmv_set_damping(self.handle, eta)
+
+    def set_sources(self, xs, f0=5.0, t0=None, amp=1.0):
+        xs = np.atleast_2d(np.asarray(xs, dtype=np.float64))
+        K.kmv_set_sources(self.handle, xs, f0, 1.0 / f0 if t0 is None else t0, amp)
+        self.n_src = len(xs)
+
+    def set_source_wavelet(self, w):
+        K.kmv_set_source_wavelet(self.handle, w)
+
+    def set_receivers(self, xr):
+        xr = np.atleast_2d(np.asarray(xr, dtype=np.float64))
+        K.kmv_set_receivers(self.handle, xr)
+        self.n_rec = len(xr)
+
+    def _c(self, c):
+        torch = _torch()
+        if not (isinstance(c, torch.Tensor) and c.is_cuda and c.dtype == torch.float64):
+            raise TypeError("c must be a float64 CUDA tensor in DOF order")
+        if c.numel() != self.mesh.n_dofs:
+            raise ValueError("c has the wrong length")
+        return c.contiguous()
+
+    def forward(self, c, out=None):
+        torch = _torch()
+        c = self._c(c)
+        tr = out if out is not None else torch.empty((self.n_steps, self.n_rec), dtype=self.dtype,
+                                                      device=c.device)
+        K.kmv_forward(self.handle, c, tr)
+        return tr
+
+    def misfit_gradient(self, c, observed, keep_traces=False):
+        torch = _torch()
+        c = self._c(c)
+        obs = observed.to(dtype=self.dtype).contiguous()
+        if obs.shape != (self.n_steps, self.n_rec):
+            raise ValueError("observed must be [n_steps, n_rec]")
+        g = torch.empty(self.mesh.n_dofs, dtype=torch.float64, device=c.device)
+        tr = torch.empty_like(obs) if keep_traces else None
+        J = K.kmv_misfit_gradient(self.handle, c, obs, g, tr)
+        return J, g, tr
+
+    def adjoint(self, c, adj, keep_lambda=False, src_trace=False):
+        torch = _torch()
+        c = self._c(c)
+        adj = adj.to(dtype=self.dtype).contiguous()
+        lam = (torch.empty((self.n_steps + 1, self.mesh.n_dofs), dtype=self.dtype, device=c.device)
+               if keep_lambda else None)
+        st = (torch.empty((self.n_steps, self.n_src), dtype=self.dtype, device=c.device)
+              if src_trace else None)
+        K.kmv_adjoint(self.handle, c, adj, lam, st)
+        return lam, st
+
+    def stiffness_apply(self, c, u):
+        torch = _torch()
+        c = self._c(c)
+        u = u.to(dtype=self.dtype).contiguous()
+        y = torch.empty_like(u)
+        K.kmv_stiffness_apply(self.handle, c, u, y)
+        return y
+
+    def close(self):
+        if getattr(self, "handle", None):
+            K.kmv_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

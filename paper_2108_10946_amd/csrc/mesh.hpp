@@ -1,0 +1,73 @@
+// Mesh preprocessing for the patch-scheduled GPU kernels (host side).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "element.hpp"
+
+namespace kmv {
+
+constexpr int kMaxColours = 64;
+
+// A point inside the mesh: containing (internal) cell and basis weights.
+struct PointLoc {
+  int64_t cell;              // internal cell index
+  std::vector<double> phi;   // [nd] phi_a(xi)
+};
+
+struct Mesh {
+  int dim = 0, degree = 0, nd = 0, ng = 0;  // ng: geometry entries per cell (3 / 6)
+  const Element* el = nullptr;
+  int64_t n_vertices = 0, n_cells = 0, n_dofs = 0;
+  std::vector<double> coords;        // [n_vertices*dim]
+  std::vector<int32_t> cells_in;     // [n_cells*(dim+1)], input order
+  // internal cell order (patch-major, colour-sorted inside a patch)
+  std::vector<int64_t> cell_input;   // internal -> input cell id
+  std::vector<int64_t> cell_dofs;    // [n_cells*nd] internal order, final DOF ids
+  std::vector<double> x0;            // [n_cells*dim] first vertex (internal order)
+  std::vector<double> jac;           // [n_cells*dim*dim] J (row-major [i][r])
+  std::vector<double> jinv;          // [n_cells*dim*dim] J^-1 (row-major [r][i])
+  std::vector<double> absdet;        // [n_cells]
+  std::vector<double> geom;          // [n_cells*ng] |det J| J^-1 J^-T, upper triangle
+  std::vector<double> dof_coords;    // [n_dofs*dim]
+  std::vector<double> mass;          // [n_dofs]
+  // patches
+  int patch_cells = 0;
+  int64_t n_patches = 0, n_own_total = 0, n_shared = 0, n_shared_refs = 0;
+  int max_nloc = 0, max_patch_cells = 0, max_colours = 0;
+  std::vector<int32_t> patch_cell_start;  // [n_patches+1]
+  std::vector<int32_t> patch_own_start;   // [n_patches+1]
+  std::vector<int32_t> patch_sh_start;    // [n_patches+1] into sh_idx / partial slots
+  std::vector<int32_t> patch_ncol;        // [n_patches]
+  std::vector<int32_t> colour_start;      // [n_patches*(kMaxColours+1)] internal cell ids
+  std::vector<int32_t> sh_idx;            // [n_shared_refs] global DOF id
+  std::vector<int32_t> shp_ptr;           // [n_shared+1]
+  std::vector<int32_t> shp_slot;          // [n_shared_refs]
+  std::vector<uint16_t> lmap;             // [nd*n_cells] SoA patch-local index
+  std::vector<int32_t> dof_patch;         // designated patch of each DOF
+  std::vector<int32_t> dof_local;         // local index inside the designated patch
+  // point location grid
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  int grid_n[3] = {1, 1, 1};
+  std::vector<int64_t> grid_ptr, grid_cells;
+
+  // Find the cell containing x (barycentric >= -tol, lowest input id among ties).
+  // Returns false if none.
+  bool locate(const double* x, PointLoc& out) const;
+};
+
+// Build; throws std::invalid_argument (bad input), kmv::MeshError (bad mesh).
+struct MeshError {
+  const char* what;
+};
+Mesh* build_mesh(int dim, int degree, const double* coords, int64_t nv, const int32_t* cells,
+                 int64_t ne, int patch_cells);
+
+// Row sums of |K(c)| divided by M (Gershgorin radii of M^-1 K).
+double gershgorin_rho(const Mesh& m, const double* c);
+
+// Check the invariants the kernels rely on; false with a reason on violation.
+bool validate_mesh(const Mesh& m, std::string& why);
+
+}  // namespace kmv

@@ -1,0 +1,627 @@
+// Device-side problem state and the forward / adjoint / gradient drivers.
+//
+// Forward (eqs. Leapfrog, forward3): per step n, k_patch + k_shared advance
+// u^n -> u^{n+1} in increment form (du^{n+1} = beta du^n + gamma (b^n - K u^n),
+// u^{n+1} = u^n + du^{n+1}, beta = (1-a)/(1+a), gamma = dt^2 / (M (1+a)), a =
+// eta dt / 2), and k_sample records d^{n+1} = P u^{n+1}.
+// Reverse sweep (eq. acoustic_pml_FEM_adj, transposed scheme): per step m = N_t..1,
+// dlam^m = beta dlam^{m+1} + gamma (P^T y^m / dt^2 - K lambda^{m+1}),
+// lambda^m = lambda^{m+1} + dlam^m, with the same kernels, fused with the gradient
+// pairing of lambda^{m+1} and u^m (eq. gradient3), accumulated in float64.
+// Forward states are either all kept (when they fit the memory budget) or
+// checkpointed every S steps and recomputed segment by segment.
+#include "problem.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <random>
+
+#include "../../include/kmvwave.h"
+#include "kernels.hpp"
+
+namespace kmv {
+namespace {
+
+#define HIPTRY(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t _e = (expr);                                                                \
+    if (_e != hipSuccess)                                                                  \
+      return Status{KMV_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)};      \
+  } while (0)
+
+#define STTRY(expr)                      \
+  do {                                   \
+    Status _s = (expr);                  \
+    if (_s.code != KMV_OK) return _s;    \
+  } while (0)
+
+const Status OK{KMV_OK, ""};
+
+template <typename V>
+Status upload(void** dst, const V* src, size_t count) {
+  if (*dst) {
+    HIPTRY(hipFree(*dst));
+    *dst = nullptr;
+  }
+  if (count == 0) return OK;
+  HIPTRY(hipMalloc(dst, count * sizeof(V)));
+  HIPTRY(hipMemcpy(*dst, src, count * sizeof(V), hipMemcpyHostToDevice));
+  return OK;
+}
+
+template <typename V>
+Status upload_i(V** dst, const std::vector<V>& v) {
+  void* p = *dst;
+  Status s = upload(&p, v.data(), v.size());
+  *dst = (V*)p;
+  return s;
+}
+
+Status upload_real(void** dst, const std::vector<double>& v, int prec) {
+  if (prec == KMV_FP64) return upload(dst, v.data(), v.size());
+  std::vector<float> f(v.begin(), v.end());
+  return upload(dst, f.data(), f.size());
+}
+
+Status alloc(void** dst, size_t bytes) {
+  if (*dst) {
+    HIPTRY(hipFree(*dst));
+    *dst = nullptr;
+  }
+  if (bytes == 0) return OK;
+  if (hipMalloc(dst, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *dst = nullptr;
+    return Status{KMV_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+  }
+  return OK;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+Status upload_coefficients(Problem* p) {
+  const Mesh& m = *p->mesh;
+  std::vector<double> gamma(m.n_dofs), beta;
+  const double dt2 = p->dt * p->dt;
+  if (!p->eta.empty()) beta.resize(m.n_dofs);
+  for (int64_t i = 0; i < m.n_dofs; ++i) {
+    const double a = p->eta.empty() ? 0.0 : p->eta[i] * p->dt / 2.0;
+    gamma[i] = dt2 / (m.mass[i] * (1.0 + a));
+    if (!beta.empty()) beta[i] = (1.0 - a) / (1.0 + a);
+  }
+  STTRY(upload_real(&p->d_gamma, gamma, p->prec));
+  if (beta.empty()) {
+    dfree(p->d_beta);
+    p->d_beta = nullptr;
+  } else {
+    STTRY(upload_real(&p->d_beta, beta, p->prec));
+  }
+  return OK;
+}
+
+// Injection groups: every entry (point j, DOF g, weight phi) is assigned to the
+// designated patch of g and grouped by its patch-local index, entries in point
+// order; sampling rows keep the global DOF ids.
+Status build_points(Problem* p, const double* xyz, int npts, bool same_amp, PointTables& T) {
+  const Mesh& m = *p->mesh;
+  const int nd = m.nd, dim = m.dim;
+  struct Ent {
+    int32_t patch, local, pt;
+    double w;
+  };
+  std::vector<Ent> ents;
+  std::vector<int32_t> sdof((size_t)npts * nd);
+  std::vector<double> sw((size_t)npts * nd);
+  for (int j = 0; j < npts; ++j) {
+    PointLoc loc;
+    if (!m.locate(xyz + (size_t)j * dim, loc))
+      return Status{KMV_EOUTSIDE, "point " + std::to_string(j) + " lies outside the mesh"};
+    for (int a = 0; a < nd; ++a) {
+      const int64_t g = m.cell_dofs[loc.cell * nd + a];
+      sdof[(size_t)j * nd + a] = (int32_t)g;
+      sw[(size_t)j * nd + a] = loc.phi[a];
+      ents.push_back({m.dof_patch[g], m.dof_local[g], same_amp ? 0 : j, loc.phi[a]});
+    }
+  }
+  std::stable_sort(ents.begin(), ents.end(), [](const Ent& x, const Ent& y) {
+    return x.patch < y.patch || (x.patch == y.patch && (x.local < y.local || (x.local == y.local && x.pt < y.pt)));
+  });
+  std::vector<int32_t> gptr(m.n_patches + 1, 0), glocal, geptr{0}, ept;
+  std::vector<double> ew;
+  for (size_t k = 0; k < ents.size(); ++k) {
+    if (k == 0 || ents[k].patch != ents[k - 1].patch || ents[k].local != ents[k - 1].local) {
+      if (k > 0) geptr.push_back((int32_t)ept.size());
+      glocal.push_back(ents[k].local);
+      gptr[ents[k].patch + 1]++;
+    }
+    ept.push_back(ents[k].pt);
+    ew.push_back(ents[k].w);
+  }
+  if (!ents.empty()) geptr.push_back((int32_t)ept.size());
+  for (int64_t q = 0; q < m.n_patches; ++q) gptr[q + 1] += gptr[q];
+  T.npts = npts;
+  T.host_xyz.assign(xyz, xyz + (size_t)npts * dim);
+  STTRY(upload_i(&T.grp_ptr, gptr));
+  STTRY(upload_i(&T.grp_local, glocal));
+  STTRY(upload_i(&T.grp_eptr, geptr));
+  STTRY(upload_i(&T.ent_pt, ept));
+  STTRY(upload_real(&T.ent_w, ew, p->prec));
+  STTRY(upload_i(&T.s_dof, sdof));
+  STTRY(upload_real(&T.s_w, sw, p->prec));
+  return OK;
+}
+
+void free_points(PointTables& T) {
+  dfree(T.grp_ptr);
+  dfree(T.grp_local);
+  dfree(T.grp_eptr);
+  dfree(T.ent_pt);
+  dfree(T.ent_w);
+  dfree(T.s_dof);
+  dfree(T.s_w);
+  T = PointTables();
+}
+
+template <typename T>
+PatchArgs<T> base_args(const Problem* p) {
+  const Mesh& m = *p->mesh;
+  PatchArgs<T> a{};
+  a.lmap = p->d_lmap;
+  a.geom = (const T*)p->d_geom;
+  a.D = (const T*)p->d_D;
+  a.W = (const T*)p->d_W;
+  a.cell_start = p->d_cell_start;
+  a.own_start = p->d_own_start;
+  a.sh_start = p->d_sh_start;
+  a.sh_idx = p->d_sh_idx;
+  a.colour_start = p->d_colour_start;
+  a.ncol = p->d_ncol;
+  a.n_cells = m.n_cells;
+  a.nloc_max = p->nloc;
+  a.c2 = (const T*)p->d_c2;
+  a.gamma = (const T*)p->d_gamma;
+  a.beta = (const T*)p->d_beta;
+  a.partial = (T*)p->d_partial;
+  a.amp_scale = T(1);
+  return a;
+}
+
+template <typename T>
+SharedArgs<T> shared_args(const Problem* p, const PatchArgs<T>& a) {
+  const Mesh& m = *p->mesh;
+  SharedArgs<T> s{};
+  s.n_own = m.n_own_total;
+  s.n_shared = m.n_shared;
+  s.shp_ptr = p->d_shp_ptr;
+  s.shp_slot = p->d_shp_slot;
+  s.mode = a.mode;
+  s.partial = a.partial;
+  s.u_in = a.u_in;
+  s.u_out = a.u_out;
+  s.du = a.du;
+  s.gamma = a.gamma;
+  s.beta = a.beta;
+  s.y_out = a.y_out;
+  s.partial_r = a.partial_r;
+  s.gacc = a.gacc;
+  return s;
+}
+
+template <typename T>
+void set_injection(PatchArgs<T>& a, const PointTables& P, const T* amp, T scale) {
+  a.grp_ptr = P.grp_ptr;
+  a.grp_local = P.grp_local;
+  a.grp_eptr = P.grp_eptr;
+  a.ent_pt = P.ent_pt;
+  a.ent_w = (const T*)P.ent_w;
+  a.amp = amp;
+  a.amp_scale = scale;
+}
+
+template <typename T>
+Status step(Problem* p, const T* u_in, T* u_out, T* du, const PointTables* inj, const T* amp, T scale,
+            const T* uf, hipStream_t s) {
+  const Mesh& m = *p->mesh;
+  PatchArgs<T> a = base_args<T>(p);
+  a.mode = 0;
+  a.u_in = u_in;
+  a.u_out = u_out;
+  a.du = du;
+  if (inj && inj->grp_ptr) set_injection(a, *inj, amp, scale);
+  const bool adj = uf != nullptr;
+  if (adj) {
+    a.uf = uf;
+    a.partial_r = (T*)p->d_partial_r;
+    a.gacc = p->d_gacc;
+  }
+  HIPTRY(launch_patch<T>(m.dim, m.nd, adj, a, (int)m.n_patches, p->block, s));
+  HIPTRY(launch_shared<T>(adj, shared_args(p, a), s));
+  return OK;
+}
+
+template <typename T>
+T* slot_ptr(Problem* p, int64_t k) {
+  return (T*)p->d_slots + k * p->mesh->n_dofs;
+}
+
+Status ensure_slots(Problem* p, int64_t n) {
+  if (p->n_slots >= n) return OK;
+  STTRY(alloc(&p->d_slots, (size_t)n * p->mesh->n_dofs * p->ts));
+  p->n_slots = n;
+  return OK;
+}
+
+// Forward steps n0..n1-1; slot of level n is slot_of(n).
+template <typename T, typename F>
+Status run_forward(Problem* p, int64_t n0, int64_t n1, F slot_of, T* traces, bool save_ck,
+                   hipStream_t s) {
+  const Mesh& m = *p->mesh;
+  const size_t vb = (size_t)m.n_dofs * sizeof(T);
+  for (int64_t n = n0; n < n1; ++n) {
+    if (save_ck && n % p->seg == 0) {
+      const int64_t k = n / p->seg;
+      HIPTRY(hipMemcpyAsync((T*)p->d_ck_u + k * m.n_dofs, slot_of(n), vb, hipMemcpyDeviceToDevice, s));
+      HIPTRY(hipMemcpyAsync((T*)p->d_ck_du + k * m.n_dofs, p->d_du, vb, hipMemcpyDeviceToDevice, s));
+    }
+    STTRY(step<T>(p, slot_of(n), slot_of(n + 1), (T*)p->d_du, &p->src, (const T*)p->d_wavelet + n, T(1),
+                  nullptr, s));
+    if (traces)
+      HIPTRY(launch_sample<T>(slot_of(n + 1), p->rec.s_dof, (const T*)p->rec.s_w, p->rec.npts, m.nd,
+                              traces + n * p->rec.npts, s));
+  }
+  return OK;
+}
+
+template <typename T>
+Status forward_t(Problem* p, const double* c, T* traces, hipStream_t s) {
+  const Mesh& m = *p->mesh;
+  STTRY(ensure_slots(p, 2));
+  HIPTRY(launch_square<T>(c, (T*)p->d_c2, m.n_dofs, s));
+  HIPTRY(launch_fill<T>((T*)p->d_du, T(0), m.n_dofs, s));
+  HIPTRY(launch_fill<T>(slot_ptr<T>(p, 0), T(0), m.n_dofs, s));
+  return run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n & 1); }, traces, false, s);
+}
+
+Status plan_storage(Problem* p) {
+  const Mesh& m = *p->mesh;
+  const size_t vb = (size_t)m.n_dofs * p->ts;
+  const size_t all = (size_t)(p->nt + 1) * vb;
+  if (p->ckpt_every <= 0 && all <= p->budget) {
+    p->store_all = true;
+    p->seg = p->nt;
+    p->n_ck = 0;
+    return ensure_slots(p, p->nt + 1);
+  }
+  p->store_all = false;
+  int64_t seg = p->ckpt_every > 0 ? p->ckpt_every
+                                   : std::max<int64_t>(1, (int64_t)std::ceil(std::sqrt(2.0 * p->nt)));
+  seg = std::min(seg, p->nt);
+  const int64_t nck = (p->nt + seg - 1) / seg;
+  const size_t need = (size_t)(seg + 1) * vb + 2 * (size_t)nck * vb;
+  if (need > p->budget && p->ckpt_every <= 0)
+    return Status{KMV_ENOMEM, "checkpoint storage (" + std::to_string(need) + " B) exceeds mem_budget"};
+  if (p->seg != seg || p->n_ck != nck || !p->d_ck_u) {
+    STTRY(alloc(&p->d_ck_u, (size_t)nck * vb));
+    STTRY(alloc(&p->d_ck_du, (size_t)nck * vb));
+  }
+  p->seg = seg;
+  p->n_ck = nck;
+  return ensure_slots(p, seg + 1);
+}
+
+template <typename T>
+Status adjoint_step(Problem* p, int64_t m, const T* adj_rows, const T* uf, hipStream_t s) {
+  const double inv_dt2 = 1.0 / (p->dt * p->dt);
+  return step<T>(p, (const T*)p->d_lam[(m + 1) & 1], (T*)p->d_lam[m & 1], (T*)p->d_dlam, &p->rec,
+                 adj_rows + (m - 1) * p->rec.npts, (T)inv_dt2, uf, s);
+}
+
+template <typename T>
+Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, double* grad, T* traces_out,
+                         hipStream_t s) {
+  const Mesh& m = *p->mesh;
+  const int64_t N = m.n_dofs;
+  STTRY(plan_storage(p));
+  T* traces = traces_out ? traces_out : (T*)p->d_traces_tmp;
+  HIPTRY(launch_square<T>(c, (T*)p->d_c2, N, s));
+  HIPTRY(launch_fill<T>((T*)p->d_du, T(0), N, s));
+  HIPTRY(launch_fill<T>(slot_ptr<T>(p, 0), T(0), N, s));
+  if (p->store_all) {
+    STTRY(run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n); }, traces, false, s));
+  } else {
+    STTRY(run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n & 1); }, traces, true, s));
+  }
+  HIPTRY(launch_misfit<T>(traces, obs, (T*)p->d_resid, p->nt * p->rec.npts, p->d_red, p->red_blocks,
+                          p->d_red + p->red_blocks, s));
+  HIPTRY(launch_fill<T>((T*)p->d_lam[0], T(0), N, s));
+  HIPTRY(launch_fill<T>((T*)p->d_lam[1], T(0), N, s));
+  HIPTRY(launch_fill<T>((T*)p->d_dlam, T(0), N, s));
+  HIPTRY(launch_fill_f64(p->d_gacc, 0.0, N, s));
+  const T* resid = (const T*)p->d_resid;
+  if (p->store_all) {
+    for (int64_t mm = p->nt; mm >= 1; --mm) STTRY(adjoint_step<T>(p, mm, resid, slot_ptr<T>(p, mm), s));
+  } else {
+    const size_t vb = (size_t)N * sizeof(T);
+    for (int64_t k = p->n_ck - 1; k >= 0; --k) {
+      const int64_t s0 = k * p->seg, s1 = std::min(s0 + p->seg, p->nt);
+      HIPTRY(hipMemcpyAsync(slot_ptr<T>(p, 0), (T*)p->d_ck_u + k * N, vb, hipMemcpyDeviceToDevice, s));
+      HIPTRY(hipMemcpyAsync(p->d_du, (T*)p->d_ck_du + k * N, vb, hipMemcpyDeviceToDevice, s));
+      STTRY(run_forward<T>(p, s0, s1, [p, s0](int64_t n) { return slot_ptr<T>(p, n - s0); }, (T*)nullptr,
+                           false, s));
+      for (int64_t mm = s1; mm > s0; --mm) STTRY(adjoint_step<T>(p, mm, resid, slot_ptr<T>(p, mm - s0), s));
+    }
+  }
+  HIPTRY(launch_finalize_grad(c, p->d_gacc, 2.0 * p->dt * p->dt, grad, N, s));
+  double hJ = 0;
+  HIPTRY(hipMemcpyAsync(&hJ, p->d_red + p->red_blocks, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPTRY(hipStreamSynchronize(s));
+  *J = hJ;
+  if (!std::isfinite(hJ)) return Status{KMV_ENUMERIC, "misfit is not finite"};
+  return OK;
+}
+
+template <typename T>
+Status adjoint_t(Problem* p, const double* c, const T* adj, T* lambda_out, T* src_trace, hipStream_t s) {
+  const Mesh& m = *p->mesh;
+  const int64_t N = m.n_dofs;
+  const size_t vb = (size_t)N * sizeof(T);
+  HIPTRY(launch_square<T>(c, (T*)p->d_c2, N, s));
+  HIPTRY(launch_fill<T>((T*)p->d_lam[0], T(0), N, s));
+  HIPTRY(launch_fill<T>((T*)p->d_lam[1], T(0), N, s));
+  HIPTRY(launch_fill<T>((T*)p->d_dlam, T(0), N, s));
+  if (lambda_out) HIPTRY(launch_fill<T>(lambda_out + p->nt * N, T(0), N, s));
+  const double inv_dt2 = 1.0 / (p->dt * p->dt);
+  for (int64_t mm = p->nt; mm >= 1; --mm) {
+    STTRY(step<T>(p, (const T*)p->d_lam[(mm + 1) & 1], (T*)p->d_lam[mm & 1], (T*)p->d_dlam, &p->rec,
+                  adj + (mm - 1) * p->rec.npts, (T)inv_dt2, nullptr, s));
+    if (lambda_out)
+      HIPTRY(hipMemcpyAsync(lambda_out + (mm - 1) * N, p->d_lam[mm & 1], vb, hipMemcpyDeviceToDevice, s));
+    if (src_trace)
+      HIPTRY(launch_sample<T>((const T*)p->d_lam[mm & 1], p->src.s_dof, (const T*)p->src.s_w, p->src.npts,
+                              m.nd, src_trace + (mm - 1) * p->src.npts, s));
+  }
+  return OK;
+}
+
+template <typename T>
+Status apply_t(Problem* p, const double* c, const T* u, T* y, hipStream_t s) {
+  const Mesh& m = *p->mesh;
+  if (c) HIPTRY(launch_square<T>(c, (T*)p->d_c2, m.n_dofs, s));
+  PatchArgs<T> a = base_args<T>(p);
+  a.mode = 1;
+  a.u_in = u;
+  a.y_out = y;
+  HIPTRY(launch_patch<T>(m.dim, m.nd, false, a, (int)m.n_patches, p->block, s));
+  HIPTRY(launch_shared<T>(false, shared_args(p, a), s));
+  return OK;
+}
+
+template <typename T>
+Status spectral_t(Problem* p, const double* c, int iters, uint64_t seed, double* rho, hipStream_t s) {
+  const Mesh& m = *p->mesh;
+  const int64_t N = m.n_dofs;
+  std::vector<T> v0(N);
+  std::mt19937_64 gen(seed);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  double nrm = 0;
+  std::vector<double> tmp(N);
+  for (int64_t i = 0; i < N; ++i) {
+    tmp[i] = nd(gen);
+    nrm += tmp[i] * tmp[i];
+  }
+  for (int64_t i = 0; i < N; ++i) v0[i] = (T)(tmp[i] / std::sqrt(nrm));
+  void *v = nullptr, *w = nullptr, *y = nullptr;
+  auto cleanup = [&]() {
+    dfree(v);
+    dfree(w);
+    dfree(y);
+  };
+  Status st = upload(&v, v0.data(), N);
+  if (st.code == KMV_OK) st = alloc(&w, N * sizeof(T));
+  if (st.code == KMV_OK) st = alloc(&y, N * sizeof(T));
+  if (st.code != KMV_OK) {
+    cleanup();
+    return st;
+  }
+  HIPTRY(launch_square<T>(c, (T*)p->d_c2, N, s));
+  const T* ms = (const T*)p->d_minv_sqrt;
+  double* dots = p->d_red + p->red_blocks + 1;  // [2]
+  for (int it = 0; it < iters; ++it) {
+    HIPTRY(launch_scale<T>((const T*)v, ms, (T*)w, N, s));
+    STTRY(apply_t<T>(p, nullptr, (const T*)w, (T*)y, s));
+    HIPTRY(launch_scale<T>((const T*)y, ms, (T*)w, N, s));
+    HIPTRY(launch_dot<T>((const T*)v, (const T*)w, N, p->d_red, p->red_blocks, dots, s));
+    HIPTRY(launch_dot<T>((const T*)w, (const T*)w, N, p->d_red, p->red_blocks, dots + 1, s));
+    HIPTRY(launch_axpby_norm<T>((T*)v, (const T*)w, dots + 1, N, s));
+  }
+  double h = 0;
+  HIPTRY(hipMemcpyAsync(&h, dots, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPTRY(hipStreamSynchronize(s));
+  cleanup();
+  *rho = h;
+  return OK;
+}
+
+}  // namespace
+
+Problem::~Problem() {
+  for (void* q : {(void*)d_lmap, d_geom, d_D, d_W, (void*)d_cell_start, (void*)d_own_start, (void*)d_sh_start,
+                  (void*)d_sh_idx, (void*)d_colour_start, (void*)d_ncol, (void*)d_shp_ptr, (void*)d_shp_slot,
+                  d_gamma, d_beta, d_c2, d_minv_sqrt, d_du, d_partial, d_partial_r, d_lam[0], d_lam[1], d_dlam,
+                  (void*)d_gacc, (void*)d_red, d_slots, d_ck_u, d_ck_du, d_resid, d_traces_tmp, d_wavelet})
+    dfree(q);
+  free_points(src);
+  free_points(rec);
+}
+
+Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_every, size_t budget,
+                      Problem** out) {
+  if (prec != KMV_FP64 && prec != KMV_FP32) return Status{KMV_EINVAL, "precision must be KMV_FP64 or KMV_FP32"};
+  if (!(dt > 0) || nt <= 0) return Status{KMV_EINVAL, "dt and n_steps must be positive"};
+  if (m->max_patch_cells > 512) return Status{KMV_EINVAL, "patches larger than 512 cells"};
+  auto p = new Problem();
+  std::unique_ptr<Problem> guard(p);
+  p->mesh = m;
+  p->prec = prec;
+  p->ts = prec == KMV_FP64 ? 8 : 4;
+  p->dt = dt;
+  p->nt = nt;
+  p->ckpt_every = ckpt_every;
+  p->budget = budget ? budget : ((size_t)8 << 30);
+  HIPTRY(hipGetDevice(&p->device));
+  p->block = std::max(64, ((m->max_patch_cells + 63) / 64) * 64);
+  p->nloc = m->max_nloc;
+  for (bool adj : {false, true}) {
+    const int bytes = (adj ? 5 : 3) * p->nloc * (int)p->ts;
+    if (bytes > 160 * 1024) return Status{KMV_EINVAL, "patch LDS footprint above 160 KiB; use smaller patches"};
+    if (bytes > 64 * 1024) {
+      if (prec == KMV_FP64)
+        HIPTRY(set_patch_lds_limit<double>(m->dim, m->nd, adj, bytes));
+      else
+        HIPTRY(set_patch_lds_limit<float>(m->dim, m->nd, adj, bytes));
+    }
+  }
+  const Element& el = *m->el;
+  STTRY(upload_i(&p->d_lmap, m->lmap));
+  {
+    std::vector<double> g((size_t)m->ng * m->n_cells);  // SoA
+    for (int64_t e = 0; e < m->n_cells; ++e)
+      for (int k = 0; k < m->ng; ++k) g[(size_t)k * m->n_cells + e] = m->geom[e * m->ng + k];
+    STTRY(upload_real(&p->d_geom, g, prec));
+  }
+  STTRY(upload_real(&p->d_D, el.grads, prec));
+  STTRY(upload_real(&p->d_W, el.weights, prec));
+  STTRY(upload_i(&p->d_cell_start, m->patch_cell_start));
+  STTRY(upload_i(&p->d_own_start, m->patch_own_start));
+  STTRY(upload_i(&p->d_sh_start, m->patch_sh_start));
+  STTRY(upload_i(&p->d_sh_idx, m->sh_idx));
+  STTRY(upload_i(&p->d_colour_start, m->colour_start));
+  STTRY(upload_i(&p->d_ncol, m->patch_ncol));
+  STTRY(upload_i(&p->d_shp_ptr, m->shp_ptr));
+  STTRY(upload_i(&p->d_shp_slot, m->shp_slot));
+  STTRY(upload_coefficients(p));
+  {
+    std::vector<double> ms(m->n_dofs);
+    for (int64_t i = 0; i < m->n_dofs; ++i) ms[i] = 1.0 / std::sqrt(m->mass[i]);
+    STTRY(upload_real(&p->d_minv_sqrt, ms, prec));
+  }
+  const size_t vb = (size_t)m->n_dofs * p->ts;
+  const size_t pb = std::max<size_t>(1, m->n_shared_refs) * p->ts;
+  STTRY(alloc(&p->d_c2, vb));
+  STTRY(alloc(&p->d_du, vb));
+  STTRY(alloc(&p->d_partial, pb));
+  STTRY(alloc(&p->d_partial_r, pb));
+  STTRY(alloc(&p->d_lam[0], vb));
+  STTRY(alloc(&p->d_lam[1], vb));
+  STTRY(alloc(&p->d_dlam, vb));
+  STTRY(alloc((void**)&p->d_gacc, (size_t)m->n_dofs * 8));
+  STTRY(alloc((void**)&p->d_red, (size_t)(p->red_blocks + 8) * 8));
+  *out = guard.release();
+  return OK;
+}
+
+Status set_damping(Problem* p, const double* eta) {
+  DeviceGuard dg(p->device);
+  if (eta) {
+    for (int64_t i = 0; i < p->mesh->n_dofs; ++i)
+      if (!(eta[i] >= 0) || !std::isfinite(eta[i])) return Status{KMV_EINVAL, "damping must be finite and >= 0"};
+    p->eta.assign(eta, eta + p->mesh->n_dofs);
+  } else {
+    p->eta.clear();
+  }
+  return upload_coefficients(p);
+}
+
+Status set_wavelet(Problem* p, const double* w) {
+  DeviceGuard dg(p->device);
+  p->wavelet.assign(w, w + p->nt);
+  return upload_real(&p->d_wavelet, p->wavelet, p->prec);
+}
+
+Status set_sources(Problem* p, const double* xs, int nsrc, double f0, double t0, double amp) {
+  DeviceGuard dg(p->device);
+  if (nsrc <= 0 || !xs) return Status{KMV_EINVAL, "need at least one source"};
+  free_points(p->src);
+  STTRY(build_points(p, xs, nsrc, true, p->src));
+  p->f0 = f0;
+  p->t0 = t0;
+  p->amp = amp;
+  std::vector<double> w(p->nt);
+  const double pi = 3.14159265358979323846;
+  for (int64_t n = 0; n < p->nt; ++n) {
+    const double t = n * p->dt - t0;
+    const double arg = pi * pi * f0 * f0 * t * t;
+    w[n] = amp * (1.0 - 2.0 * arg) * std::exp(-arg);
+  }
+  p->has_src = true;
+  return set_wavelet(p, w.data());
+}
+
+Status set_receivers(Problem* p, const double* xr, int nrec) {
+  DeviceGuard dg(p->device);
+  if (nrec <= 0 || !xr) return Status{KMV_EINVAL, "need at least one receiver"};
+  free_points(p->rec);
+  STTRY(build_points(p, xr, nrec, false, p->rec));
+  const size_t tb = (size_t)p->nt * nrec * p->ts;
+  STTRY(alloc(&p->d_resid, tb));
+  STTRY(alloc(&p->d_traces_tmp, tb));
+  return OK;
+}
+
+Status forward(Problem* p, const double* c, void* traces, hipStream_t s) {
+  DeviceGuard dg(p->device);
+  if (!p->has_src || p->rec.npts == 0) return Status{KMV_ESTATE, "sources and receivers must be set first"};
+  if (!c || !traces) return Status{KMV_EINVAL, "null device pointer"};
+  return p->prec == KMV_FP64 ? forward_t<double>(p, c, (double*)traces, s) : forward_t<float>(p, c, (float*)traces, s);
+}
+
+Status misfit_gradient(Problem* p, const double* c, const void* obs, double* J, double* grad, void* traces,
+                       hipStream_t s) {
+  DeviceGuard dg(p->device);
+  if (!p->has_src || p->rec.npts == 0) return Status{KMV_ESTATE, "sources and receivers must be set first"};
+  if (!c || !obs || !J || !grad) return Status{KMV_EINVAL, "null pointer"};
+  return p->prec == KMV_FP64
+             ? misfit_gradient_t<double>(p, c, (const double*)obs, J, grad, (double*)traces, s)
+             : misfit_gradient_t<float>(p, c, (const float*)obs, J, grad, (float*)traces, s);
+}
+
+Status adjoint(Problem* p, const double* c, const void* adj, void* lambda_out, void* src_trace, hipStream_t s) {
+  DeviceGuard dg(p->device);
+  if (p->rec.npts == 0) return Status{KMV_ESTATE, "receivers must be set first"};
+  if (src_trace && !p->has_src) return Status{KMV_ESTATE, "sources must be set to record at them"};
+  if (!c || !adj) return Status{KMV_EINVAL, "null device pointer"};
+  return p->prec == KMV_FP64
+             ? adjoint_t<double>(p, c, (const double*)adj, (double*)lambda_out, (double*)src_trace, s)
+             : adjoint_t<float>(p, c, (const float*)adj, (float*)lambda_out, (float*)src_trace, s);
+}
+
+Status stiffness_apply(Problem* p, const double* c, const void* u, void* y, hipStream_t s) {
+  DeviceGuard dg(p->device);
+  if (!c || !u || !y) return Status{KMV_EINVAL, "null device pointer"};
+  return p->prec == KMV_FP64 ? apply_t<double>(p, c, (const double*)u, (double*)y, s)
+                             : apply_t<float>(p, c, (const float*)u, (float*)y, s);
+}
+
+Status spectral_radius(Problem* p, const double* c, int iters, uint64_t seed, double* rho, hipStream_t s) {
+  DeviceGuard dg(p->device);
+  if (!c || !rho || iters <= 0) return Status{KMV_EINVAL, "bad argument"};
+  return p->prec == KMV_FP64 ? spectral_t<double>(p, c, iters, seed, rho, s)
+                             : spectral_t<float>(p, c, iters, seed, rho, s);
+}
+
+}  // namespace kmv

@@ -1,0 +1,256 @@
+"""ctypes binding of the kmvwave C ABI (include/kmvwave.h), same names.
+
+Argument marshalling only: every numerical step runs in the HIP library
+``libkmvwave.so`` next to this file.  If the library is missing, importing the
+binding works but the first call raises ``RuntimeError`` (there is no fallback).
+
+Device buffers are torch tensors on the current HIP device (torch is used for
+device memory and streams only); the stream is torch's current stream unless one
+is passed.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkmvwave.so")
+
+KMV_OK, KMV_EINVAL, KMV_ENOMEM, KMV_EDEGREE, KMV_EMESH = 0, -1, -2, -3, -4
+KMV_EOUTSIDE, KMV_ECFL, KMV_ENUMERIC, KMV_EDEVICE, KMV_EBUSY, KMV_ESTATE = -5, -6, -7, -8, -9, -10
+KMV_FP64, KMV_FP32 = 0, 1
+
+ERROR_NAMES = {0: "KMV_OK", -1: "KMV_EINVAL", -2: "KMV_ENOMEM", -3: "KMV_EDEGREE", -4: "KMV_EMESH",
+               -5: "KMV_EOUTSIDE", -6: "KMV_ECFL", -7: "KMV_ENUMERIC", -8: "KMV_EDEVICE",
+               -9: "KMV_EBUSY", -10: "KMV_ESTATE"}
+
+# every symbol include/kmvwave.h declares
+DECLARED = [
+    "kmv_last_error", "kmv_element_tables", "kmv_mesh_create", "kmv_mesh_info",
+    "kmv_mesh_dof_coords", "kmv_mesh_lumped_mass", "kmv_mesh_cell_dofs", "kmv_mesh_validate",
+    "kmv_mesh_destroy",
+    "kmv_problem_create", "kmv_cfl_dt", "kmv_spectral_radius", "kmv_set_damping",
+    "kmv_set_sources", "kmv_set_source_wavelet", "kmv_set_receivers", "kmv_forward",
+    "kmv_misfit_gradient", "kmv_adjoint", "kmv_stiffness_apply", "kmv_problem_info",
+    "kmv_problem_destroy",
+]
+
+
+class KMVError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class kmv_options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("dt", C.c_double), ("n_steps", C.c_int64),
+                ("checkpoint_every", C.c_int64), ("mem_budget", C.c_size_t)]
+
+
+_lib = None
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+
+
+def lib():
+    """Load the HIP library (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2108_10946_amd.build`"
+                           " (there is no CPU fallback)")
+    L = C.CDLL(LIB_PATH)
+    sig = {
+        "kmv_last_error": (C.c_char_p, []),
+        "kmv_element_tables": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int), _D, _D, _D]),
+        "kmv_mesh_create": (C.c_int, [C.c_int, C.c_int, _D, C.c_int64, C.POINTER(C.c_int32), C.c_int64,
+                                      C.c_int, C.POINTER(_P)]),
+        "kmv_mesh_info": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int),
+                                    C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+        "kmv_mesh_dof_coords": (C.c_int, [_P, _D]),
+        "kmv_mesh_lumped_mass": (C.c_int, [_P, _D]),
+        "kmv_mesh_cell_dofs": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+        "kmv_mesh_validate": (C.c_int, [_P]),
+        "kmv_mesh_destroy": (C.c_int, [_P]),
+        "kmv_problem_create": (C.c_int, [_P, C.POINTER(kmv_options), C.POINTER(_P)]),
+        "kmv_cfl_dt": (C.c_int, [_P, _D, _D]),
+        "kmv_spectral_radius": (C.c_int, [_P, _P, C.c_int, C.c_uint64, _D, _P]),
+        "kmv_set_damping": (C.c_int, [_P, _D]),
+        "kmv_set_sources": (C.c_int, [_P, _D, C.c_int, C.c_double, C.c_double, C.c_double]),
+        "kmv_set_source_wavelet": (C.c_int, [_P, _D]),
+        "kmv_set_receivers": (C.c_int, [_P, _D, C.c_int]),
+        "kmv_forward": (C.c_int, [_P, _P, _P, _P]),
+        "kmv_misfit_gradient": (C.c_int, [_P, _P, _P, _D, _P, _P, _P]),
+        "kmv_adjoint": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+        "kmv_stiffness_apply": (C.c_int, [_P, _P, _P, _P, _P]),
+        "kmv_problem_info": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int),
+                                       C.POINTER(C.c_int), C.POINTER(C.c_int64)]),
+        "kmv_problem_destroy": (C.c_int, [_P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != KMV_OK:
+        raise KMVError(rc, lib().kmv_last_error().decode())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_D)
+
+
+def _tptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("device buffers must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# --------------------------------------------------------------- same-name calls
+def kmv_last_error():
+    return lib().kmv_last_error().decode()
+
+
+def kmv_element_tables(dim, degree):
+    n = C.c_int()
+    _check(lib().kmv_element_tables(dim, degree, C.byref(n), None, None, None))
+    nodes = np.zeros(n.value * dim)
+    w = np.zeros(n.value)
+    g = np.zeros(n.value * n.value * dim)
+    _check(lib().kmv_element_tables(dim, degree, C.byref(n), _dptr(nodes), _dptr(w), _dptr(g)))
+    return nodes.reshape(n.value, dim), w, g.reshape(n.value, n.value, dim)
+
+
+def kmv_mesh_create(dim, degree, coords, cells, patch_cells=0):
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    cells = np.ascontiguousarray(cells, dtype=np.int32)
+    h = _P()
+    _check(lib().kmv_mesh_create(dim, degree, _dptr(coords), len(coords),
+                                 cells.ctypes.data_as(C.POINTER(C.c_int32)), len(cells), patch_cells,
+                                 C.byref(h)))
+    return h
+
+
+def kmv_mesh_info(m):
+    v = [C.c_int64(), C.c_int64(), C.c_int(), C.c_int64(), C.c_int64()]
+    _check(lib().kmv_mesh_info(m, *[C.byref(x) for x in v]))
+    return dict(n_dofs=v[0].value, n_cells=v[1].value, n_nodes=v[2].value, n_patches=v[3].value,
+                n_shared_dofs=v[4].value)
+
+
+def kmv_mesh_dof_coords(m, dim):
+    n = kmv_mesh_info(m)["n_dofs"]
+    out = np.zeros(n * dim)
+    _check(lib().kmv_mesh_dof_coords(m, _dptr(out)))
+    return out.reshape(n, dim)
+
+
+def kmv_mesh_lumped_mass(m):
+    out = np.zeros(kmv_mesh_info(m)["n_dofs"])
+    _check(lib().kmv_mesh_lumped_mass(m, _dptr(out)))
+    return out
+
+
+def kmv_mesh_cell_dofs(m):
+    info = kmv_mesh_info(m)
+    out = np.zeros(info["n_cells"] * info["n_nodes"], dtype=np.int64)
+    _check(lib().kmv_mesh_cell_dofs(m, out.ctypes.data_as(C.POINTER(C.c_int64))))
+    return out.reshape(info["n_cells"], info["n_nodes"])
+
+
+def kmv_mesh_destroy(m):
+    _check(lib().kmv_mesh_destroy(m))
+
+
+def kmv_problem_create(m, precision, dt, n_steps, checkpoint_every=0, mem_budget=0):
+    opt = kmv_options(precision, dt, n_steps, checkpoint_every, mem_budget)
+    h = _P()
+    _check(lib().kmv_problem_create(m, C.byref(opt), C.byref(h)))
+    return h
+
+
+def kmv_problem_info(p):
+    v = [C.c_int64(), C.c_int64(), C.c_int(), C.c_int(), C.c_int64()]
+    _check(lib().kmv_problem_info(p, *[C.byref(x) for x in v]))
+    return dict(n_dofs=v[0].value, n_steps=v[1].value, n_rec=v[2].value, precision=v[3].value,
+                checkpoint_every=v[4].value)
+
+
+def kmv_cfl_dt(m, c_host):
+    c_host = np.ascontiguousarray(c_host, dtype=np.float64)
+    out = C.c_double()
+    _check(lib().kmv_cfl_dt(m, _dptr(c_host), C.byref(out)))
+    return out.value
+
+
+def kmv_mesh_validate(m):
+    _check(lib().kmv_mesh_validate(m))
+
+
+def kmv_spectral_radius(p, c_dev, iters=200, seed=0, stream=None):
+    out = C.c_double()
+    _check(lib().kmv_spectral_radius(p, _tptr(c_dev), iters, seed, C.byref(out), _stream(stream)))
+    return out.value
+
+
+def kmv_set_damping(p, eta):
+    if eta is None:
+        _check(lib().kmv_set_damping(p, None))
+    else:
+        eta = np.ascontiguousarray(eta, dtype=np.float64)
+        _check(lib().kmv_set_damping(p, _dptr(eta)))
+
+
+def kmv_set_sources(p, xs, f0, t0, amp=1.0):
+    xs = np.ascontiguousarray(np.atleast_2d(xs), dtype=np.float64)
+    _check(lib().kmv_set_sources(p, _dptr(xs), len(xs), f0, t0, amp))
+
+
+def kmv_set_source_wavelet(p, w):
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    _check(lib().kmv_set_source_wavelet(p, _dptr(w)))
+
+
+def kmv_set_receivers(p, xr):
+    xr = np.ascontiguousarray(np.atleast_2d(xr), dtype=np.float64)
+    _check(lib().kmv_set_receivers(p, _dptr(xr), len(xr)))
+
+
+def kmv_forward(p, c_dev, traces_dev, stream=None):
+    _check(lib().kmv_forward(p, _tptr(c_dev), _tptr(traces_dev), _stream(stream)))
+
+
+def kmv_misfit_gradient(p, c_dev, observed_dev, grad_dev, traces_dev=None, stream=None):
+    J = C.c_double()
+    _check(lib().kmv_misfit_gradient(p, _tptr(c_dev), _tptr(observed_dev), C.byref(J), _tptr(grad_dev),
+                                     _tptr(traces_dev), _stream(stream)))
+    return J.value
+
+
+def kmv_adjoint(p, c_dev, adj_src_dev, lambda_out_dev=None, src_trace_dev=None, stream=None):
+    _check(lib().kmv_adjoint(p, _tptr(c_dev), _tptr(adj_src_dev), _tptr(lambda_out_dev),
+                             _tptr(src_trace_dev), _stream(stream)))
+
+
+def kmv_stiffness_apply(p, c_dev, u_dev, y_dev, stream=None):
+    _check(lib().kmv_stiffness_apply(p, _tptr(c_dev), _tptr(u_dev), _tptr(y_dev), _stream(stream)))
+
+
+def kmv_problem_destroy(p):
+    _check(lib().kmv_problem_destroy(p))
