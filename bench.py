@@ -1,0 +1,262 @@
+#!/usr/bin/env python3
+"""Benchmark: DOF-timesteps/s of one full misfit + gradient evaluation
+(forward + stored/checkpointed states + float64 misfit + adjoint fused with the
+float64 gradient accumulation) on the layered KMV4 workload, on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+A "step" is one complete evaluation of J and dJ/dc for one shot over the whole
+time window (every time step counted once):  value = N_dofs * N_t / seconds.
+Prints one JSON line (plus progress lines on stderr).  The roofline object is
+computed live from HIP events around sampled launches of the dominant kernel;
+cpu_baseline times the FP64 oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "DOF-timesteps/s fwd+adj+grad (FP32 vs FP64 oracle-matched); p50/p99 shot latency"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2108_10946_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(variant, n_dofs, n_cells, dim, ts):
+    """Bytes the method must move per launch ('Algorithmic bytes'):
+    per DOF  forward step: read u^n, du^n, c^2, gamma, beta; write u^{n+1}, du^{n+1}
+             adjoint step: the same for lambda, plus read u^m and a float64
+                           read-modify-write of the gradient accumulator
+    per cell compact topology (vertex + edge [+ face] ids, 4 B each) and the
+             symmetric geometry factor |det J| J^-1 J^-T (3 or 6 values)."""
+    topo = 4 * (6 if dim == 2 else 14)
+    geom = (3 if dim == 2 else 6) * ts
+    per_cell = n_cells * (topo + geom)
+    if variant == "patch_forward":
+        return n_dofs * 7 * ts + per_cell
+    if variant == "patch_adjoint":
+        return n_dofs * (8 * ts + 16) + per_cell
+    raise ValueError(variant)
+
+
+def traffic_from_profiles(variant, hash_):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    rec = d.get(variant)
+    if not rec or rec.get("kernels_hip_sha") != hash_:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def setup_workload(precision, budget_frac=0.75, mesh_cache={}):
+    import torch
+    from paper_2108_10946_amd import Mesh, Problem
+    from synth import configs
+    w = configs.layered_kmv4()
+    if "mesh" not in mesh_cache:
+        t = time.time()
+        mesh_cache["mesh"] = Mesh(w.coords, w.cells, w.degree)
+        log(f"mesh: {len(w.cells)} cells, {mesh_cache['mesh'].n_dofs} DOFs, "
+            f"{mesh_cache['mesh'].n_patches} patches ({time.time() - t:.1f}s)")
+    m = mesh_cache["mesh"]
+    x = m.dof_coords()
+    c_cur = torch.tensor(w.vp(x[:, 0], x[:, 1]), dtype=torch.float64, device="cuda")
+    c_obs = torch.tensor(w.vp_obs(x[:, 0], x[:, 1]), dtype=torch.float64, device="cuda")
+    eta = w.eta(x[:, 0], x[:, 1])
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(free * budget_frac)
+    if "dt" not in mesh_cache:
+        probe = Problem(m, 1e-4, 4, precision="fp64")
+        rho = max(probe.spectral_radius(c_cur, iters=300), probe.spectral_radius(c_obs, iters=300))
+        probe.close()
+        nt = int(np.ceil(w.T / (w.cfl_fraction * 2.0 / np.sqrt(rho)) - 1e-12))
+        mesh_cache["dt"] = (w.T / nt, nt)
+        log(f"CFL: rho={rho:.6g}, dt={w.T / nt * 1e3:.4f} ms, N_t={nt}")
+    dt, nt = mesh_cache["dt"]
+    prob = Problem(m, dt, nt, precision=precision, mem_budget=budget)
+    prob.set_damping(eta)
+    prob.set_sources(w.sources, f0=w.f0, t0=w.t0, amp=w.amp)
+    prob.set_receivers(w.receivers)
+    obs = prob.forward(c_obs)
+    torch.cuda.synchronize()
+    return w, m, prob, c_cur, obs, dt, nt
+
+
+def time_gpu(precision, steps, warmup, every):
+    import torch
+    from paper_2108_10946_amd import kmvwave as K
+    w, m, prob, c, obs, dt, nt = setup_workload(precision)
+    K.kmv_profile_enable(prob.handle, every)
+    for i in range(warmup):
+        t = time.time()
+        J, g, _ = prob.misfit_gradient(c, obs)
+        log(f"{precision} warmup {i}: J={J:.6g} ({time.time() - t:.2f}s)")
+    K.kmv_profile_enable(prob.handle, every)  # reset counters, keep events
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        J, g, _ = prob.misfit_gradient(c, obs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec = (t1 - t0) / steps
+    log(f"{precision}: {sec * 1e3:.1f} ms per misfit+gradient, J={J:.6g}, "
+        f"|g|={float(torch.linalg.vector_norm(g)):.6g}")
+    prof = {K.PROFILE_VARIANTS[v]: K.kmv_profile_read(prob.handle, v) for v in K.PROFILE_VARIANTS}
+    info = prob.info()
+    out = dict(sec=sec, J=J, n_dofs=m.n_dofs, n_cells=m.n_cells, nt=nt, dt=dt, prof=prof,
+               checkpoint_every=info["checkpoint_every"], n_patches=m.n_patches,
+               n_shared=m.n_shared_dofs)
+    prob.close()
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
+def roofline(res, ts, dim=2):
+    hash_ = kernel_hash()
+    best = None
+    for variant in ("patch_forward", "patch_adjoint"):
+        p = res["prof"][variant]
+        if p["timed"] == 0:
+            continue
+        total = p["launches"] * p["mean_ms"]
+        b = algorithmic_bytes(variant, res["n_dofs"], res["n_cells"], dim, ts)
+        achieved = b / (p["mean_ms"] * 1e-3) / 1e9
+        r = {"kernel": f"k_patch ({variant})", "bound": "hbm", "achieved": round(achieved, 1),
+             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+             "traffic": traffic_from_profiles(variant, hash_), "algorithmic_bytes": int(b),
+             "mean_launch_us": round(p["mean_ms"] * 1e3, 3), "launches": p["launches"],
+             "timed_launches": p["timed"], "total_ms": total}
+        if best is None or total > best["total_ms"]:
+            best = r
+        res.setdefault("rooflines", {})[variant] = r
+    return best
+
+
+def cpu_baseline(n_sample=20):
+    """FP64 oracle (one thread) on the first n_sample forward and adjoint steps of
+    the same workload; setup (DOF numbering, assembly) is not timed."""
+    from threadpoolctl import threadpool_limits
+    from oracle.fem import Discretization
+    from oracle import solver
+    from synth import configs
+    w = configs.layered_kmv4()
+    with threadpool_limits(1):
+        t = time.time()
+        d = Discretization(w.coords, w.cells, w.degree)
+        c = d.nodal_values(w.vp)
+        K = d.stiffness(c)
+        M = d.lumped_mass()
+        P = d.interpolation_matrix(w.receivers)
+        s = np.asarray(d.interpolation_matrix(w.sources).sum(0)).ravel()
+        eta = d.nodal_values(w.eta)
+        log(f"oracle setup {time.time() - t:.1f}s (not timed)")
+        dt = 2.5e-4
+        a = eta * dt / 2
+        wav = solver.ricker(np.arange(n_sample) * dt, w.f0, w.t0, w.amp)
+        t0 = time.perf_counter()
+        tr, st = solver.forward(K, M, a, dt, n_sample, solver.point_source_load(s, wav), P=P,
+                                keep_states=True)
+        J, g, _ = solver.gradient(d, c, K, M, a, dt, P, 1.01 * tr, st)
+        sec = time.perf_counter() - t0
+    value = d.n_dofs * n_sample / sec
+    log(f"oracle: {n_sample} steps fwd+adj+grad in {sec:.1f}s -> {value:.3g} DOF-timesteps/s")
+    return {"value": round(value, 1), "unit": "DOF-timesteps/s", "cores": 1, "kind": "oracle",
+            "sample": f"layered_kmv4 mesh (N={d.n_dofs}), first {n_sample} steps of forward + "
+                      f"adjoint + gradient, FP64 assembled CSR, one thread; {sec:.1f}s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--profile-every", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); shots shard "
+              "across GPUs with one float64 all-reduce of the gradient, which this build does "
+              "not run", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    import paper_2108_10946_amd as kmv
+    kmv.lib()
+
+    res32 = time_gpu("fp32", args.steps, args.warmup, args.profile_every)
+    rl = roofline(res32, 4)
+    res64 = None
+    if not args.no_fp64:
+        res64 = time_gpu("fp64", max(1, args.steps // 2), min(1, args.warmup), args.profile_every)
+        roofline(res64, 8)
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
+
+    N, nt = res32["n_dofs"], res32["nt"]
+    value = N * nt / res32["sec"]
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "DOF-timesteps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res32["sec"] * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "layered_kmv4: 2D 8x3 km, 8 layers 1.5-4.5 km/s + 3 seeded anomalies, "
+                        "750 m sponge, graded NVB mesh, KMV4, 1 Ricker shot (5 Hz), 300 receivers, "
+                        "T=4 s at 0.9x the power-iteration CFL step",
+            "n_cells": res32["n_cells"], "n_dofs": N, "n_steps": nt, "dt_s": res32["dt"],
+            "precision": "fp32 wavefields/operators, fp64 misfit and gradient accumulation",
+            "state_storage": ("all states kept in HBM" if res32["checkpoint_every"] == 0
+                              else f"checkpoints every {res32['checkpoint_every']} steps + recompute"),
+            "n_patches": res32["n_patches"], "n_shared_dofs": res32["n_shared"],
+        },
+        "roofline": {k: v for k, v in rl.items() if k != "total_ms"} if rl else None,
+        "rooflines": {k: {kk: vv for kk, vv in v.items() if kk != "total_ms"}
+                      for k, v in res32.get("rooflines", {}).items()},
+        "kernel_mean_us": {k: round(v["mean_ms"] * 1e3, 3) for k, v in res32["prof"].items()},
+        "cpu_baseline": cpu,
+    }
+    if res64:
+        out["fp64"] = {"value": round(N * nt / res64["sec"], 1), "ms_per_step": round(res64["sec"] * 1e3, 3),
+                       "state_storage": ("all states kept in HBM" if res64["checkpoint_every"] == 0
+                                         else f"checkpoints every {res64['checkpoint_every']} steps"),
+                       "rooflines": {k: {kk: vv for kk, vv in v.items() if kk != "total_ms"}
+                                     for k, v in res64.get("rooflines", {}).items()}}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -171,6 +171,17 @@ int kmv_adjoint(kmv_problem p, const void* c_dev, const void* adj_src_dev,
  * the problem's type, [n_dofs], DOF order. */
 int kmv_stiffness_apply(kmv_problem p, const void* c_dev, const void* u_dev, void* y_dev,
                         void* stream);
+/* Kernel timing probe.  After kmv_profile_enable(p, every) (every >= 1; 0 turns it
+ * off and clears the counters), every `every`-th launch of each kernel variant is
+ * bracketed by HIP events recorded on the launch stream.  Variants:
+ *   0 patch kernel, forward step      1 patch kernel, adjoint + gradient step
+ *   2 shared-DOF finisher, forward    3 shared-DOF finisher, adjoint
+ *   4 receiver sampling
+ * kmv_profile_read synchronises the recorded events and returns the number of
+ * launches, the number timed and their mean duration in milliseconds. */
+int kmv_profile_enable(kmv_problem p, int every);
+int kmv_profile_read(kmv_problem p, int variant, int64_t* n_launches, int64_t* n_timed,
+                     double* mean_ms);
 /* Sizes of a problem. */
 int kmv_problem_info(kmv_problem p, int64_t* n_dofs, int64_t* n_steps, int* n_rec,
                      int* precision, int64_t* checkpoint_every);

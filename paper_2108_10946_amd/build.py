@@ -24,7 +24,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("KMV_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result"]
+          "-I", os.path.join(ROOT, "include"), "-I", BUILD, "-Wall", "-Wno-unused-result"]
 
 
 def _compile(src):
@@ -37,8 +37,22 @@ def _compile(src):
     return src, r.returncode, "\n".join(noise), obj
 
 
+def generate_tables():
+    """Compile and run gen_tables (host) -> _build/kmv_tables.inc."""
+    exe = os.path.join(BUILD, "gen_tables")
+    cmd = [os.environ.get("CXX", "g++"), "-O2", "-std=c++17", "-o", exe,
+           os.path.join(CSRC, "gen_tables.cpp"), os.path.join(CSRC, "element.cpp")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"table generator failed to compile:\n{r.stderr}")
+    out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    with open(os.path.join(BUILD, "kmv_tables.inc"), "w") as f:
+        f.write(out)
+
+
 def build(jobs: int = 0, verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    generate_tables()
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 4)
     objs = []
     with cf.ThreadPoolExecutor(jobs) as ex:

@@ -234,6 +234,20 @@ int kmv_stiffness_apply(kmv_problem h, const void* c_dev, const void* u_dev, voi
   });
 }
 
+int kmv_profile_enable(kmv_problem h, int every) {
+  return guarded([&]() {
+    if (!h) return fail(KMV_EINVAL, "problem is NULL");
+    return done(kmv::profile_enable(h->p, every));
+  });
+}
+
+int kmv_profile_read(kmv_problem h, int variant, int64_t* n_launches, int64_t* n_timed, double* mean_ms) {
+  return guarded([&]() {
+    if (!h) return fail(KMV_EINVAL, "problem is NULL");
+    return done(kmv::profile_read(h->p, variant, n_launches, n_timed, mean_ms));
+  });
+}
+
 int kmv_problem_destroy(kmv_problem h) {
   if (!h) return KMV_OK;
   delete h->p;

@@ -446,6 +446,11 @@ Element build(int dim, int k) {
       }
     }
   }
+  // entries that vanish by symmetry come out as round-off; make them exact zeros
+  double gmax = 0;
+  for (double v : el.grads) gmax = std::max(gmax, std::fabs(v));
+  for (double& v : el.grads)
+    if (std::fabs(v) < 1e-14 * gmax) v = 0.0;
   // entity of each node from its zero barycentric coordinates
   static const int edges2[3][2] = {{0, 1}, {0, 2}, {1, 2}};
   static const int edges3[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};

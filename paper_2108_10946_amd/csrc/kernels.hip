@@ -1,63 +1,214 @@
-// HIP kernels for gfx950 (CDNA4): matrix-free KMV stiffness apply fused with the
-// leapfrog/sponge update, the reverse-time adjoint fused with the gradient
-// accumulation, point injection/sampling, misfit and helpers.
+// HIP kernels for gfx950 (CDNA4): one fused launch per time step for the forward
+// and for the reverse-time adjoint (fused with the float64 gradient accumulation),
+// plus a small finisher, point sampling, misfit and helpers.
 //
-// Work decomposition (one workgroup = one patch of cells, one thread = one cell):
-//   1. coalesced loads of the patch-owned DOF values (a contiguous range) and
-//      gathers of the DOFs the patch shares with neighbours, into LDS;
-//   2. per cell, the reference-gradient contraction at the nodal quadrature
-//      points, g_q = sum_b D[q][b] u_b, z_q = w_q c^2_q G_e g_q,
-//      y_a = sum_q D[q][a] . z_q  (appendix, matrix K, with the KMV rule as
-//      quadrature) -- the tables are kernel-uniform, so they live in scalar
-//      registers, and the contraction runs on the VALU (fp32: 157 TF vector = the
-//      fp32 MFMA rate on this part, so MFMA buys nothing at these shapes);
-//   3. deterministic LDS scatter: cells are sorted by colour inside the patch and
-//      colour c adds its y_a after colour c-1 (barrier in between), so every sum
-//      has a fixed order and no atomics are needed;
-//   4. leapfrog + sponge on the DOFs only this patch touches (eq. forward3 with a
-//      diagonal leading matrix):  du <- beta du - gamma (K u - b),  u <- u + du;
-//   5. partial sums of the shared DOFs to a buffer, finished by k_shared.
+// Work decomposition of k_step (one workgroup = one patch of cells, one thread =
+// one cell):
+//   * every global load is issued up front: patch-owned DOF data is a contiguous
+//     range (coalesced, kept in registers for the update), DOFs shared with
+//     neighbouring patches are gathered and finished from the previous step's
+//     partial sums in a fixed order, the patch's gather lists are staged in LDS;
+//   * per cell, the reference-gradient contraction at the nodal quadrature
+//     points, g_q = sum_b D[q][b] u_b, z_q = w_q c^2_q G_e g_q,
+//     y_a = sum_q D[q][a] . z_q (appendix, matrix K, with the KMV rule as the
+//     quadrature).  The tables are compile-time constants (instruction literals,
+//     zero entries dropped) and the contraction runs on the VALU;
+//   * deterministic assembly: every cell writes its n_d contributions to its own
+//     LDS slots, then each DOF sums its slots in a fixed (cell, node) order;
+//   * leapfrog + sponge for the DOFs only this patch touches (eq. forward3 with a
+//     diagonal leading matrix): du <- beta du - gamma (K u - b), u <- u + du.
 #include "kernels.hpp"
+#include "kmv_tables.inc"
 
 namespace kmv {
 
+__host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) / 16 * 16; }
+
+// LDS layout of k_step: su[L], sc[L], sx[cells*nd] (element type), then the
+// gather pointers gp[L+8] and entries ge[cells*nd+8] (uint16).
+struct StepLds {
+  size_t gp, ge, total;
+  __host__ __device__ StepLds(int L, int cells, int nd, size_t ts) {
+    gp = align16((2 * (size_t)L + (size_t)cells * nd) * ts);
+    ge = gp + align16(((size_t)L + 8) * 2);
+    total = ge + align16(((size_t)cells * nd + 8) * 2);
+  }
+};
+
+// Items per thread whose global loads are issued together (latency hiding).
+template <typename T>
+struct Batch {
+  static constexpr int kOwned = sizeof(T) == 4 ? 16 : 8;    // owned items kept in registers
+  static constexpr int kUpdate = sizeof(T) == 4 ? 12 : 6;   // prefetched update operands
+  static constexpr int kShared = 2;                         // shared refs per pass
+  static constexpr int kList = 4;                           // 16-byte list words per pass
+};
+
 template <typename T, int DIM, int ND, bool ADJ>
-__global__ void __launch_bounds__(512) k_patch(const PatchArgs<T> A) {
+__global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
+  using Tab = KmvTab<T, DIM, ND>;  // compile-time reference gradients and weights
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* su = reinterpret_cast<T*>(smem_raw);
-  T* sc = su + A.nloc_max;
-  T* sy = sc + A.nloc_max;
-  T* sf = sy + A.nloc_max;   // ADJ only
-  T* sr = sf + A.nloc_max;   // ADJ only
+  const int L = A.nloc_max;
+  const StepLds lay(L, A.cells_max, ND, sizeof(T));
+  T* su = reinterpret_cast<T*>(smem_raw);  // level n, then K u - b
+  T* sc = su + L;                          // c^2, then the gradient pairing (ADJ)
+  T* sx = sc + L;                          // cell-node contributions (shared u^m before, ADJ)
+  uint16_t* gp = reinterpret_cast<uint16_t*>(smem_raw + lay.gp);
+  uint16_t* ge = reinterpret_cast<uint16_t*>(smem_raw + lay.ge);
   const int p = blockIdx.x, tid = threadIdx.x, bs = blockDim.x;
   const int own0 = A.own_start[p], nown = A.own_start[p + 1] - own0;
   const int sh0 = A.sh_start[p], nsh = A.sh_start[p + 1] - sh0;
+  const int nloc = nown + nsh;
+  const bool step = A.mode == 0;
 
-  for (int i = tid; i < nown; i += bs) {
-    su[i] = A.u_in[own0 + i];
-    sc[i] = A.c2[own0 + i];
-    sy[i] = T(0);
-    if (ADJ) {
-      sf[i] = A.uf[own0 + i];
-      sr[i] = T(0);
-    }
-  }
-  for (int j = tid; j < nsh; j += bs) {
-    const int g = A.sh_idx[sh0 + j];
-    su[nown + j] = A.u_in[g];
-    sc[nown + j] = A.c2[g];
-    sy[nown + j] = T(0);
-    if (ADJ) {
-      sf[nown + j] = A.uf[g];
-      sr[nown + j] = T(0);
-    }
-  }
-  __syncthreads();
-
+  // ---- every global load first
   const int c0 = A.cell_start[p], c1 = A.cell_start[p + 1];
   const int e = c0 + tid;
   const bool active = e < c1;
+  constexpr int NG = DIM == 2 ? 3 : 6;
   int m[ND];
+  T G[NG];
+  if (active) {
+#pragma unroll
+    for (int a = 0; a < ND; ++a) m[a] = A.lmap[(int64_t)a * A.n_cells + e];
+#pragma unroll
+    for (int k = 0; k < NG; ++k) G[k] = A.geom[(int64_t)k * A.n_cells + e];
+  }
+  constexpr int KO = Batch<T>::kOwned;
+  T vu[KO], vc[KO];
+#pragma unroll
+  for (int k = 0; k < KO; ++k) {
+    const int i = tid + k * bs;
+    if (i < nown) {
+      vu[k] = A.u_in[own0 + i];
+      vc[k] = A.c2[own0 + i];
+    }
+  }
+  // update operands of the first owned items: in flight during the element work
+  const bool damped = A.beta != nullptr && A.damp_patch[p] != 0;
+  constexpr int KU = Batch<T>::kUpdate;
+  T pdu[KU], pg[KU], pb[KU];
+  if (step) {
+#pragma unroll
+    for (int k = 0; k < KU; ++k) {
+      const int i = tid + k * bs;
+      if (i < nown) {
+        pdu[k] = A.du[own0 + i];
+        pg[k] = A.gamma[own0 + i];
+        pb[k] = damped ? A.beta[own0 + i] : T(1);
+      }
+    }
+  }
+  const int gpo = A.gl_ptr_off[p], gpn = (A.gl_ptr_off[p + 1] - gpo) / 8;
+  const int geo = A.gl_ent_off[p], gen = (A.gl_ent_off[p + 1] - geo) / 8;
+  const uint4* gsrc_p = reinterpret_cast<const uint4*>(A.gl_ptr + gpo);
+  const uint4* gsrc_e = reinterpret_cast<const uint4*>(A.gl_ent + geo);
+  constexpr int KL = Batch<T>::kList;
+  uint4 lw[KL];
+#pragma unroll
+  for (int k = 0; k < KL; ++k) {
+    const int v = tid + k * bs;
+    const uint4* src = v < gpn ? gsrc_p + v : gsrc_e + (v - gpn);
+    lw[k] = v < gpn + gen ? *src : make_uint4(0, 0, 0, 0);
+  }
+  // shared refs: level-1 loads (global id, inline partial slots) then level 2
+  constexpr int KH = Batch<T>::kShared;
+  for (int j0 = tid; j0 < nsh; j0 += KH * bs) {
+    int gg[KH];
+    int2 sl[KH];
+#pragma unroll
+    for (int t = 0; t < KH; ++t) {
+      const int j = j0 + t * bs;
+      if (j < nsh) {
+        gg[t] = A.sh_idx[sh0 + j];
+        if (A.prev) sl[t] = reinterpret_cast<const int2*>(A.ref_slots)[sh0 + j];
+      }
+    }
+    T uu[KH], cc[KH], ff[KH];
+#pragma unroll
+    for (int t = 0; t < KH; ++t) {
+      const int j = j0 + t * bs;
+      if (j >= nsh) continue;
+      const int g = gg[t];
+      cc[t] = A.c2[g];
+      if (ADJ) ff[t] = A.uf[g];
+      if (A.prev) {
+        const int64_t s = g - A.n_own;
+        const bool pair = sl[t].y >= 0;  // else: three or more patches, CSR list
+        T y;
+        if (pair) {
+          y = A.part_prev[sl[t].x] + A.part_prev[sl[t].y];
+        } else {
+          y = T(0);
+          for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) y += A.part_prev[A.shp_slot[k]];
+        }
+        const T b = damped ? A.beta[g] : T(1);
+        const T dn = b * A.dsh_prev[s] - A.gamma[g] * y;
+        uu[t] = A.u_prev[g] + dn;
+        if (sl[t].x == sh0 + j) {  // the first touching patch stores the level
+          A.u_in_sh[g] = uu[t];
+          A.dsh_cur[s] = dn;
+          if (ADJ) {
+            T r;
+            if (pair) {
+              r = A.partr_prev[sl[t].x] + A.partr_prev[sl[t].y];
+            } else {
+              r = T(0);
+              for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) r += A.partr_prev[A.shp_slot[k]];
+            }
+            A.gacc[g] += (double)r;
+          }
+        }
+      } else {
+        uu[t] = A.u_in[g];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < KH; ++t) {
+      const int j = j0 + t * bs;
+      if (j >= nsh) continue;
+      su[nown + j] = uu[t];
+      sc[nown + j] = cc[t];
+      if (ADJ) sx[j] = ff[t];
+    }
+  }
+  // ---- the staged stores
+#pragma unroll
+  for (int k = 0; k < KO; ++k) {
+    const int i = tid + k * bs;
+    if (i < nown) {
+      su[i] = vu[k];
+      sc[i] = vc[k];
+    }
+  }
+  for (int i = tid + KO * bs; i < nown; i += bs) {
+    su[i] = A.u_in[own0 + i];
+    sc[i] = A.c2[own0 + i];
+  }
+  uint4* gdst_p = reinterpret_cast<uint4*>(gp);
+  uint4* gdst_e = reinterpret_cast<uint4*>(ge);
+#pragma unroll
+  for (int k = 0; k < KL; ++k) {
+    const int v = tid + k * bs;
+    uint4* dst = v < gpn ? gdst_p + v : gdst_e + (v - gpn);
+    if (v < gpn + gen) *dst = lw[k];
+  }
+  for (int v = tid + KL * bs; v < gpn + gen; v += bs) {
+    if (v < gpn) gdst_p[v] = gsrc_p[v];
+    else gdst_e[v - gpn] = gsrc_e[v - gpn];
+  }
+  __syncthreads();
+
+  // receivers whose cell lies in this patch: d^n from the staged level
+  if (A.trace_row != nullptr) {
+    for (int r = A.rp_ptr[p] + tid; r < A.rp_ptr[p + 1]; r += bs) {
+      T s = T(0);
+      for (int a = 0; a < ND; ++a) s += A.rp_w[r * ND + a] * su[A.rp_loc[r * ND + a]];
+      A.trace_row[A.rp_rec[r]] = s;
+    }
+  }
+
+  // ---- element stiffness (and the gradient pairing) per cell
   T ye[ND];
   T re[ADJ ? ND : 1];
   if (active) {
@@ -65,14 +216,14 @@ __global__ void __launch_bounds__(512) k_patch(const PatchArgs<T> A) {
     T fe[ADJ ? ND : 1];
 #pragma unroll
     for (int a = 0; a < ND; ++a) {
-      m[a] = A.lmap[(int64_t)a * A.n_cells + e];
       ue[a] = su[m[a]];
-      if (ADJ) fe[a] = sf[m[a]];
       ye[a] = T(0);
     }
-    T G[DIM == 2 ? 3 : 6];
+    if (ADJ) {
+      // forward state u^m: owned nodes from global memory, shared ones staged
 #pragma unroll
-    for (int k = 0; k < (DIM == 2 ? 3 : 6); ++k) G[k] = A.geom[(int64_t)k * A.n_cells + e];
+      for (int a = 0; a < ND; ++a) fe[ADJ ? a : 0] = m[a] < nown ? A.uf[own0 + m[a]] : sx[m[a] - nown];
+    }
 #pragma unroll
     for (int q = 0; q < ND; ++q) {
       T g[DIM];
@@ -81,9 +232,12 @@ __global__ void __launch_bounds__(512) k_patch(const PatchArgs<T> A) {
 #pragma unroll
       for (int b = 0; b < ND; ++b)
 #pragma unroll
-        for (int r = 0; r < DIM; ++r) g[r] += A.D[(q * ND + b) * DIM + r] * ue[b];
+        for (int r = 0; r < DIM; ++r) {
+          const T dv = Tab::D[(q * ND + b) * DIM + r];
+          if (dv != T(0)) g[r] += dv * ue[b];
+        }
       T v[DIM];
-      if (DIM == 2) {
+      if constexpr (DIM == 2) {
         v[0] = G[0] * g[0] + G[1] * g[1];
         v[1] = G[1] * g[0] + G[2] * g[1];
       } else {
@@ -91,7 +245,7 @@ __global__ void __launch_bounds__(512) k_patch(const PatchArgs<T> A) {
         v[1] = G[1] * g[0] + G[3] * g[1] + G[4] * g[2];
         v[2] = G[2] * g[0] + G[4] * g[1] + G[5] * g[2];
       }
-      const T wq = A.W[q];
+      const T wq = Tab::W[q];
       const T cw = wq * sc[m[q]];
       T z[DIM];
 #pragma unroll
@@ -99,7 +253,10 @@ __global__ void __launch_bounds__(512) k_patch(const PatchArgs<T> A) {
 #pragma unroll
       for (int b = 0; b < ND; ++b)
 #pragma unroll
-        for (int r = 0; r < DIM; ++r) ye[b] += A.D[(q * ND + b) * DIM + r] * z[r];
+        for (int r = 0; r < DIM; ++r) {
+          const T dv = Tab::D[(q * ND + b) * DIM + r];
+          if (dv != T(0)) ye[b] += dv * z[r];
+        }
       if (ADJ) {
         T gf[DIM];
 #pragma unroll
@@ -107,7 +264,10 @@ __global__ void __launch_bounds__(512) k_patch(const PatchArgs<T> A) {
 #pragma unroll
         for (int b = 0; b < ND; ++b)
 #pragma unroll
-          for (int r = 0; r < DIM; ++r) gf[r] += A.D[(q * ND + b) * DIM + r] * fe[b];
+          for (int r = 0; r < DIM; ++r) {
+            const T dv = Tab::D[(q * ND + b) * DIM + r];
+            if (dv != T(0)) gf[r] += dv * fe[ADJ ? b : 0];
+          }
         T s = T(0);
 #pragma unroll
         for (int r = 0; r < DIM; ++r) s += gf[r] * v[r];
@@ -115,85 +275,124 @@ __global__ void __launch_bounds__(512) k_patch(const PatchArgs<T> A) {
       }
     }
   }
+  if (ADJ) __syncthreads();  // staged shared u^m is read; sx is free
 
-  // colour-ordered scatter into LDS
-  const int ncol = A.ncol[p];
-  int myc = -1;
+  // ---- deterministic assembly: own slots, then a fixed-order sum per DOF
   if (active) {
-    const int32_t* cs = A.colour_start + (int64_t)p * kColStride;
-    for (int c = 0; c < ncol; ++c)
-      if (e >= cs[c] && e < cs[c + 1]) myc = c;
-  }
-  for (int c = 0; c < ncol; ++c) {
-    if (myc == c) {
 #pragma unroll
-      for (int a = 0; a < ND; ++a) {
-        sy[m[a]] += ye[a];
-        if (ADJ) sr[m[a]] += re[ADJ ? a : 0];
-      }
+    for (int a = 0; a < ND; ++a) sx[(e - c0) * ND + a] = ye[a];
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int i = tid; i < nloc; i += bs) {
+    T y = T(0);
+    for (int k = gp[i]; k < gp[i + 1]; ++k) y += sx[ge[k]];
+    su[i] = y;
+  }
+  if (ADJ) {
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int a = 0; a < ND; ++a) sx[(e - c0) * ND + a] = re[ADJ ? a : 0];
     }
     __syncthreads();
+#pragma unroll 4
+    for (int i = tid; i < nloc; i += bs) {
+      T r = T(0);
+      for (int k = gp[i]; k < gp[i + 1]; ++k) r += sx[ge[k]];
+      sc[i] = r;
+    }
   }
+  __syncthreads();
 
   // point injection: one thread per target DOF, entries in a fixed order
-  if (A.grp_ptr != nullptr) {
+  if (A.grp_ptr != nullptr && A.grp_ptr[p] < A.grp_ptr[p + 1]) {
     for (int gi = A.grp_ptr[p] + tid; gi < A.grp_ptr[p + 1]; gi += bs) {
       T acc = T(0);
       for (int k = A.grp_eptr[gi]; k < A.grp_eptr[gi + 1]; ++k) acc += A.ent_w[k] * A.amp[A.ent_pt[k]];
-      sy[A.grp_local[gi]] -= acc * A.amp_scale;
+      su[A.grp_local[gi]] -= acc * A.amp_scale;
     }
     __syncthreads();
   }
 
-  if (A.mode == 1) {
-    for (int i = tid; i < nown; i += bs) A.y_out[own0 + i] = sy[i];
+  if (!step) {
+    for (int i = tid; i < nown; i += bs) A.y_out[own0 + i] = su[i];
   } else {
-    for (int i = tid; i < nown; i += bs) {
+#pragma unroll
+    for (int k = 0; k < KO; ++k) {
+      const int i = tid + k * bs;
+      if (i < nown) {
+        const int gi = own0 + i;
+        T dn;
+        if (k < KU) {
+          dn = pb[k < KU ? k : 0] * pdu[k < KU ? k : 0] - pg[k < KU ? k : 0] * su[i];
+        } else {
+          const T b = damped ? A.beta[gi] : T(1);
+          dn = b * A.du[gi] - A.gamma[gi] * su[i];
+        }
+        A.du[gi] = dn;
+        A.u_out[gi] = vu[k] + dn;
+        if (ADJ) A.gacc[gi] += (double)sc[i];
+      }
+    }
+    for (int i = tid + KO * bs; i < nown; i += bs) {
       const int gi = own0 + i;
-      const T b = A.beta ? A.beta[gi] : T(1);
-      const T dn = b * A.du[gi] - A.gamma[gi] * sy[i];
+      const T b = damped ? A.beta[gi] : T(1);
+      const T dn = b * A.du[gi] - A.gamma[gi] * su[i];
       A.du[gi] = dn;
-      A.u_out[gi] = su[i] + dn;
-      if (ADJ) A.gacc[gi] += (double)sr[i];
+      A.u_out[gi] = A.u_in[gi] + dn;
+      if (ADJ) A.gacc[gi] += (double)sc[i];
     }
   }
   for (int j = tid; j < nsh; j += bs) {
-    A.partial[sh0 + j] = sy[nown + j];
-    if (ADJ) A.partial_r[sh0 + j] = sr[nown + j];
+    A.part_cur[sh0 + j] = su[nown + j];
+    if (ADJ) A.partr_cur[sh0 + j] = sc[nown + j];
   }
 }
 
 template <typename T, bool ADJ>
-__global__ void __launch_bounds__(256) k_shared(const SharedArgs<T> A) {
+__global__ void __launch_bounds__(256) k_finish(const FinishArgs<T> A) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= A.n_shared) return;
-  T y = T(0);
+  const int64_t g = A.n_own + s;
   const int k0 = A.shp_ptr[s], k1 = A.shp_ptr[s + 1];
-  for (int k = k0; k < k1; ++k) y += A.partial[A.shp_slot[k]];
-  const int64_t i = A.n_own + s;
+  T y = T(0);
+  for (int k = k0; k < k1; ++k) y += A.part_prev[A.shp_slot[k]];
   if (A.mode == 1) {
-    A.y_out[i] = y;
+    A.y_out[g] = y;
     return;
   }
-  const T b = A.beta ? A.beta[i] : T(1);
-  const T dn = b * A.du[i] - A.gamma[i] * y;
-  A.du[i] = dn;
-  A.u_out[i] = A.u_in[i] + dn;
+  const T b = A.beta ? A.beta[g] : T(1);
+  const T dn = b * A.dsh_prev[s] - A.gamma[g] * y;
+  A.u_cur[g] = A.u_prev[g] + dn;
+  A.dsh_cur[s] = dn;
   if (ADJ) {
     T r = T(0);
-    for (int k = k0; k < k1; ++k) r += A.partial_r[A.shp_slot[k]];
-    A.gacc[i] += (double)r;
+    for (int k = k0; k < k1; ++k) r += A.partr_prev[A.shp_slot[k]];
+    A.gacc[g] += (double)r;
   }
 }
 
+// One thread per (point, node) pair, then a fixed-order sum per point: the
+// dependent index/value loads of a point are issued in parallel.
 template <typename T>
-__global__ void k_sample(const T* __restrict__ u, const int32_t* __restrict__ dof,
-                         const T* __restrict__ w, int npts, int nd, T* __restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= npts) return;
-  T s = T(0);
-  for (int a = 0; a < nd; ++a) s += w[j * nd + a] * u[dof[j * nd + a]];
-  out[j] = s;
+__global__ void __launch_bounds__(256) k_sample(const T* __restrict__ u, const int32_t* __restrict__ dof,
+                                                const T* __restrict__ w, int npts, int nd, T* __restrict__ out) {
+  __shared__ T prod[256];
+  const int per = 256 / nd;  // points per block
+  const int j0 = blockIdx.x * per;
+  const int t = threadIdx.x;
+  const int jl = t / nd, a = t % nd;
+  const int j = j0 + jl;
+  T v = T(0);
+  if (jl < per && j < npts) v = w[(int64_t)j * nd + a] * u[dof[(int64_t)j * nd + a]];
+  prod[t] = v;
+  __syncthreads();
+  if (t < per && j0 + t < npts) {
+    T s = T(0);
+    for (int b = 0; b < nd; ++b) s += prod[t * nd + b];
+    out[j0 + t] = s;
+  }
 }
 
 template <typename T>
@@ -281,52 +480,55 @@ namespace {
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 template <typename T, int DIM, int ND, bool ADJ>
-hipError_t launch_patch_t(const PatchArgs<T>& a, int np, int block, hipStream_t s) {
-  const int narr = ADJ ? 5 : 3;
-  const size_t lds = (size_t)narr * a.nloc_max * sizeof(T);
-  hipLaunchKernelGGL((k_patch<T, DIM, ND, ADJ>), dim3(np), dim3(block), lds, s, a);
+hipError_t launch_step_t(const StepArgs<T>& a, int np, int block, hipStream_t s) {
+  const size_t lds = StepLds(a.nloc_max, a.cells_max, ND, sizeof(T)).total;
+  hipLaunchKernelGGL((k_step<T, DIM, ND, ADJ>), dim3(np), dim3(block), lds, s, a);
   return hipGetLastError();
 }
 
 template <typename T, int DIM, int ND, bool ADJ>
 hipError_t set_lds_t(int bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_patch<T, DIM, ND, ADJ>),
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step<T, DIM, ND, ADJ>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-#define KMV_DISPATCH(FN, ...)                                                            \
-  switch (dim * 100 + nd) {                                                              \
-    case 203: return adjoint ? FN<T, 2, 3, true>(__VA_ARGS__) : FN<T, 2, 3, false>(__VA_ARGS__);     \
-    case 207: return adjoint ? FN<T, 2, 7, true>(__VA_ARGS__) : FN<T, 2, 7, false>(__VA_ARGS__);     \
-    case 212: return adjoint ? FN<T, 2, 12, true>(__VA_ARGS__) : FN<T, 2, 12, false>(__VA_ARGS__);   \
-    case 218: return adjoint ? FN<T, 2, 18, true>(__VA_ARGS__) : FN<T, 2, 18, false>(__VA_ARGS__);   \
-    case 230: return adjoint ? FN<T, 2, 30, true>(__VA_ARGS__) : FN<T, 2, 30, false>(__VA_ARGS__);   \
-    case 304: return adjoint ? FN<T, 3, 4, true>(__VA_ARGS__) : FN<T, 3, 4, false>(__VA_ARGS__);     \
-    case 315: return adjoint ? FN<T, 3, 15, true>(__VA_ARGS__) : FN<T, 3, 15, false>(__VA_ARGS__);   \
-    case 332: return adjoint ? FN<T, 3, 32, true>(__VA_ARGS__) : FN<T, 3, 32, false>(__VA_ARGS__);   \
-    default: return hipErrorInvalidValue;                                                \
+#define KMV_DISPATCH(FN, ...)                                                                      \
+  switch (dim * 100 + nd) {                                                                        \
+    case 203: return adjoint ? FN<T, 2, 3, true>(__VA_ARGS__) : FN<T, 2, 3, false>(__VA_ARGS__);   \
+    case 207: return adjoint ? FN<T, 2, 7, true>(__VA_ARGS__) : FN<T, 2, 7, false>(__VA_ARGS__);   \
+    case 212: return adjoint ? FN<T, 2, 12, true>(__VA_ARGS__) : FN<T, 2, 12, false>(__VA_ARGS__); \
+    case 218: return adjoint ? FN<T, 2, 18, true>(__VA_ARGS__) : FN<T, 2, 18, false>(__VA_ARGS__); \
+    case 230: return adjoint ? FN<T, 2, 30, true>(__VA_ARGS__) : FN<T, 2, 30, false>(__VA_ARGS__); \
+    case 304: return adjoint ? FN<T, 3, 4, true>(__VA_ARGS__) : FN<T, 3, 4, false>(__VA_ARGS__);   \
+    case 315: return adjoint ? FN<T, 3, 15, true>(__VA_ARGS__) : FN<T, 3, 15, false>(__VA_ARGS__); \
+    case 332: return adjoint ? FN<T, 3, 32, true>(__VA_ARGS__) : FN<T, 3, 32, false>(__VA_ARGS__); \
+    default: return hipErrorInvalidValue;                                                          \
   }
 }  // namespace
 
-template <typename T>
-hipError_t launch_patch(int dim, int nd, bool adjoint, const PatchArgs<T>& a, int n_patches,
-                        int block, hipStream_t s) {
-  KMV_DISPATCH(launch_patch_t, a, n_patches, block, s)
+size_t step_lds_bytes(int nloc_max, int cells_max, int nd, size_t elem_size) {
+  return StepLds(nloc_max, cells_max, nd, elem_size).total;
 }
 
 template <typename T>
-hipError_t set_patch_lds_limit(int dim, int nd, bool adjoint, int bytes) {
+hipError_t launch_step(int dim, int nd, bool adjoint, const StepArgs<T>& a, int n_patches, int block,
+                       hipStream_t s) {
+  KMV_DISPATCH(launch_step_t, a, n_patches, block, s)
+}
+
+template <typename T>
+hipError_t set_step_lds_limit(int dim, int nd, bool adjoint, int bytes) {
   KMV_DISPATCH(set_lds_t, bytes)
 }
 
 template <typename T>
-hipError_t launch_shared(bool adjoint, const SharedArgs<T>& a, hipStream_t s) {
+hipError_t launch_finish(bool adjoint, const FinishArgs<T>& a, hipStream_t s) {
   if (a.n_shared == 0) return hipSuccess;
   const unsigned nb = blocks_for(a.n_shared, 256);
   if (adjoint)
-    hipLaunchKernelGGL((k_shared<T, true>), dim3(nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_finish<T, true>), dim3(nb), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((k_shared<T, false>), dim3(nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_finish<T, false>), dim3(nb), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -334,7 +536,9 @@ template <typename T>
 hipError_t launch_sample(const T* u, const int32_t* dof, const T* w, int npts, int nd, T* out,
                          hipStream_t s) {
   if (npts <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_sample<T>), dim3(blocks_for(npts, 256)), dim3(256), 0, s, u, dof, w, npts, nd, out);
+  if (nd > 256) return hipErrorInvalidValue;
+  const int per = 256 / nd;
+  hipLaunchKernelGGL((k_sample<T>), dim3(blocks_for(npts, per)), dim3(256), 0, s, u, dof, w, npts, nd, out);
   return hipGetLastError();
 }
 
@@ -386,15 +590,15 @@ hipError_t launch_dot(const T* x, const T* y, int64_t n, double* scratch, int nb
 }
 
 template <typename T>
-hipError_t launch_axpby_norm(T* v, const T* w, const double* dot_ww, int64_t n, hipStream_t s) {
+hipError_t launch_normalize(T* v, const T* w, const double* dot_ww, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL((k_normalize<T>), dim3(blocks_for(n, 256)), dim3(256), 0, s, v, w, dot_ww, n);
   return hipGetLastError();
 }
 
 #define KMV_INST(T)                                                                                    \
-  template hipError_t launch_patch<T>(int, int, bool, const PatchArgs<T>&, int, int, hipStream_t);     \
-  template hipError_t set_patch_lds_limit<T>(int, int, bool, int);                                     \
-  template hipError_t launch_shared<T>(bool, const SharedArgs<T>&, hipStream_t);                      \
+  template hipError_t launch_step<T>(int, int, bool, const StepArgs<T>&, int, int, hipStream_t);       \
+  template hipError_t set_step_lds_limit<T>(int, int, bool, int);                                      \
+  template hipError_t launch_finish<T>(bool, const FinishArgs<T>&, hipStream_t);                      \
   template hipError_t launch_sample<T>(const T*, const int32_t*, const T*, int, int, T*, hipStream_t); \
   template hipError_t launch_square<T>(const double*, T*, int64_t, hipStream_t);                      \
   template hipError_t launch_fill<T>(T*, T, int64_t, hipStream_t);                                    \
@@ -402,7 +606,7 @@ hipError_t launch_axpby_norm(T* v, const T* w, const double* dot_ww, int64_t n, 
                                        hipStream_t);                                                  \
   template hipError_t launch_scale<T>(const T*, const T*, T*, int64_t, hipStream_t);                  \
   template hipError_t launch_dot<T>(const T*, const T*, int64_t, double*, int, double*, hipStream_t); \
-  template hipError_t launch_axpby_norm<T>(T*, const T*, const double*, int64_t, hipStream_t);
+  template hipError_t launch_normalize<T>(T*, const T*, const double*, int64_t, hipStream_t);
 KMV_INST(float)
 KMV_INST(double)
 

@@ -405,6 +405,37 @@ Mesh* build_mesh(int dim, int degree, const double* coords, int64_t nv, const in
       loc[g] = -1;
     }
   }
+  // gather lists (inverse of lmap per patch), entries in (cell, node) order
+  if ((int64_t)m->max_patch_cells * nd > 65535) throw std::invalid_argument("patch too large for 16-bit slots");
+  m->gl_ptr_off.assign(np + 1, 0);
+  m->gl_ent_off.assign(np + 1, 0);
+  auto pad8 = [](int64_t x) { return (x + 7) / 8 * 8; };
+  for (int64_t p = 0; p < np; ++p) {
+    const int32_t nloc = (m->patch_own_start[p + 1] - m->patch_own_start[p]) +
+                         ((p + 1 < np ? m->patch_sh_start[p + 1] : (int32_t)sh_list.size()) - m->patch_sh_start[p]);
+    m->gl_ptr_off[p + 1] = (int32_t)(m->gl_ptr_off[p] + pad8(nloc + 1));
+    m->gl_ent_off[p + 1] = (int32_t)(m->gl_ent_off[p] + pad8((leaf_start[p + 1] - leaf_start[p]) * nd));
+  }
+  m->gl_ptr.assign(m->gl_ptr_off[np], 0);
+  m->gl_ent.assign(m->gl_ent_off[np], 0);
+  for (int64_t p = 0; p < np; ++p) {
+    const int32_t c0 = (int32_t)leaf_start[p], c1 = (int32_t)leaf_start[p + 1];
+    const int32_t nloc = (m->patch_own_start[p + 1] - m->patch_own_start[p]) +
+                         ((p + 1 < np ? m->patch_sh_start[p + 1] : (int32_t)sh_list.size()) - m->patch_sh_start[p]);
+    uint16_t* gp = &m->gl_ptr[m->gl_ptr_off[p]];
+    uint16_t* ge = &m->gl_ent[m->gl_ent_off[p]];
+    std::vector<int32_t> cnt(nloc + 1, 0);
+    for (int32_t e = c0; e < c1; ++e)
+      for (int a = 0; a < nd; ++a) cnt[m->lmap[(size_t)a * ne + e] + 1]++;
+    for (int32_t i = 0; i < nloc; ++i) cnt[i + 1] += cnt[i];
+    for (int32_t i = 0; i <= nloc; ++i) gp[i] = (uint16_t)cnt[i];
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int32_t e = c0; e < c1; ++e)
+      for (int a = 0; a < nd; ++a) {
+        const int li = m->lmap[(size_t)a * ne + e];
+        ge[fill[li]++] = (uint16_t)((e - c0) * nd + a);
+      }
+  }
   // designated patch of a shared DOF: the first patch touching it
   for (int64_t g = 0; g < ndof; ++g)
     if (m->dof_patch[g] < 0) {
@@ -423,6 +454,18 @@ Mesh* build_mesh(int dim, int degree, const double* coords, int64_t nv, const in
       const int64_t s = sh_list[k] - m->n_own_total;
       m->shp_slot[fill[s]++] = (int32_t)k;  // patches visited in order -> slots increase
     }
+  }
+  // inline copy of each shared ref's slot list (first entry = designated patch)
+  for (int64_t s = 0; s < m->n_shared; ++s)
+    m->max_share = std::max(m->max_share, m->shp_ptr[s + 1] - m->shp_ptr[s]);
+  // inline pair {first slot, second slot} for DOFs on the interface of two
+  // patches; {first slot, -count} otherwise (the kernels then walk the CSR list)
+  m->ref_slots.assign(sh_list.size() * kMaxShare, -1);
+  for (size_t r = 0; r < sh_list.size(); ++r) {
+    const int64_t s = sh_list[r] - m->n_own_total;
+    const int32_t k0 = m->shp_ptr[s], k1 = m->shp_ptr[s + 1];
+    m->ref_slots[r * kMaxShare + 0] = m->shp_slot[k0];
+    m->ref_slots[r * kMaxShare + 1] = k1 - k0 == 2 ? m->shp_slot[k0 + 1] : -(k1 - k0);
   }
 
   // ---- point location grid (bucket by cell bounding boxes)
@@ -654,6 +697,42 @@ bool validate_mesh(const Mesh& m, std::string& why) {
         why = "partial slots of shared DOF " + std::to_string(g) + " are wrong or unordered";
         return false;
       }
+    }
+  }
+  // gather lists: per patch a permutation of the cell-node slots, grouped by DOF
+  for (int64_t p = 0; p < m.n_patches; ++p) {
+    const int32_t c0 = m.patch_cell_start[p], c1 = m.patch_cell_start[p + 1];
+    const int32_t nloc = (m.patch_own_start[p + 1] - m.patch_own_start[p]) +
+                         (m.patch_sh_start[p + 1] - m.patch_sh_start[p]);
+    const uint16_t* gp = &m.gl_ptr[m.gl_ptr_off[p]];
+    const uint16_t* ge = &m.gl_ent[m.gl_ent_off[p]];
+    const int nslot = (c1 - c0) * nd;
+    if (m.gl_ptr_off[p] % 8 || m.gl_ent_off[p] % 8 || m.gl_ptr_off[p + 1] - m.gl_ptr_off[p] < nloc + 1 ||
+        m.gl_ent_off[p + 1] - m.gl_ent_off[p] < nslot || gp[0] != 0 || gp[nloc] != nslot) {
+      why = "gather list of patch " + std::to_string(p) + " does not cover its cells";
+      return false;
+    }
+    std::vector<char> seen(nslot, 0);
+    for (int32_t i = 0; i < nloc; ++i)
+      for (int k = gp[i]; k < gp[i + 1]; ++k) {
+        const int slot = ge[k];
+        const int e = c0 + slot / nd, a = slot % nd;
+        if (slot >= nslot || seen[slot] || m.lmap[(size_t)a * ne + e] != i || (k > gp[i] && slot <= ge[k - 1])) {
+          why = "gather list of patch " + std::to_string(p) + " is not the inverse of the local map";
+          return false;
+        }
+        seen[slot] = 1;
+      }
+  }
+  // inline slot lists of every shared ref agree with the CSR lists
+  for (int64_t r = 0; r < m.n_shared_refs; ++r) {
+    const int64_t s = m.sh_idx[r] - m.n_own_total;
+    const int32_t k0 = m.shp_ptr[s], k1 = m.shp_ptr[s + 1];
+    const int32_t* rs = &m.ref_slots[r * kMaxShare];
+    const bool ok = rs[0] == m.shp_slot[k0] && rs[1] == (k1 - k0 == 2 ? m.shp_slot[k0 + 1] : -(k1 - k0));
+    if (!ok) {
+      why = "inline partial slots of shared ref " + std::to_string(r) + " disagree with the CSR list";
+      return false;
     }
   }
   return true;

@@ -9,6 +9,7 @@
 namespace kmv {
 
 constexpr int kMaxColours = 64;
+constexpr int kMaxShare = 2;  // inline partial slots per shared ref (DOFs on one patch interface)
 
 // A point inside the mesh: containing (internal) cell and basis weights.
 struct PointLoc {
@@ -44,7 +45,18 @@ struct Mesh {
   std::vector<int32_t> sh_idx;            // [n_shared_refs] global DOF id
   std::vector<int32_t> shp_ptr;           // [n_shared+1]
   std::vector<int32_t> shp_slot;          // [n_shared_refs]
+  // per shared ref: {first slot (the designated patch's), second slot} when two
+  // patches touch the DOF, else {first slot, -count} (walk the CSR list)
+  std::vector<int32_t> ref_slots;         // [n_shared_refs*kMaxShare]
+  int max_share = 0;                      // most patches touching one DOF
   std::vector<uint16_t> lmap;             // [nd*n_cells] SoA patch-local index
+  // per-patch gather lists, the inverse of lmap: local DOF i of patch p collects
+  // the cell-node slots (e - c0)*nd + a listed in
+  //   gl_ent[gl_ent_off[p] + gl_ptr[gl_ptr_off[p] + i] .. + gl_ptr[gl_ptr_off[p] + i + 1])
+  // in (e, a) order.  Each patch's regions start on a 16-byte boundary.
+  std::vector<uint16_t> gl_ptr;           // [per patch nloc_p + 1, padded to 8]
+  std::vector<uint16_t> gl_ent;           // [per patch ncells_p*nd, padded to 8]
+  std::vector<int32_t> gl_ptr_off, gl_ent_off;  // [n_patches+1]
   std::vector<int32_t> dof_patch;         // designated patch of each DOF
   std::vector<int32_t> dof_local;         // local index inside the designated patch
   // point location grid

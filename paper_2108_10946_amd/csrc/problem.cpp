@@ -111,12 +111,24 @@ Status upload_coefficients(Problem* p) {
   } else {
     STTRY(upload_real(&p->d_beta, beta, p->prec));
   }
+  // patches that touch a damped DOF (owned or shared)
+  std::vector<int32_t> flag(m.n_patches, 0);
+  if (!beta.empty()) {
+    for (int64_t q = 0; q < m.n_patches; ++q) {
+      for (int32_t i = m.patch_own_start[q]; i < m.patch_own_start[q + 1] && !flag[q]; ++i)
+        if (p->eta[i] != 0.0) flag[q] = 1;
+      for (int32_t r = m.patch_sh_start[q]; r < m.patch_sh_start[q + 1] && !flag[q]; ++r)
+        if (p->eta[m.sh_idx[r]] != 0.0) flag[q] = 1;
+    }
+  }
+  STTRY(upload_i(&p->d_damp_patch, flag));
   return OK;
 }
 
 // Injection groups: every entry (point j, DOF g, weight phi) is assigned to the
 // designated patch of g and grouped by its patch-local index, entries in point
-// order; sampling rows keep the global DOF ids.
+// order.  Sampling rows: global DOF ids, and patch-local ids in the patch that
+// holds the point's cell.
 Status build_points(Problem* p, const double* xyz, int npts, bool same_amp, PointTables& T) {
   const Mesh& m = *p->mesh;
   const int nd = m.nd, dim = m.dim;
@@ -127,10 +139,12 @@ Status build_points(Problem* p, const double* xyz, int npts, bool same_amp, Poin
   std::vector<Ent> ents;
   std::vector<int32_t> sdof((size_t)npts * nd);
   std::vector<double> sw((size_t)npts * nd);
+  std::vector<int64_t> cell_of(npts);
   for (int j = 0; j < npts; ++j) {
     PointLoc loc;
     if (!m.locate(xyz + (size_t)j * dim, loc))
       return Status{KMV_EOUTSIDE, "point " + std::to_string(j) + " lies outside the mesh"};
+    cell_of[j] = loc.cell;
     for (int a = 0; a < nd; ++a) {
       const int64_t g = m.cell_dofs[loc.cell * nd + a];
       sdof[(size_t)j * nd + a] = (int32_t)g;
@@ -154,8 +168,41 @@ Status build_points(Problem* p, const double* xyz, int npts, bool same_amp, Poin
   }
   if (!ents.empty()) geptr.push_back((int32_t)ept.size());
   for (int64_t q = 0; q < m.n_patches; ++q) gptr[q + 1] += gptr[q];
+  // per-patch sampling rows
+  std::vector<int32_t> order(npts);
+  std::vector<int32_t> patch_of(npts);
+  for (int j = 0; j < npts; ++j) {
+    order[j] = j;
+    patch_of[j] = (int32_t)(std::upper_bound(m.patch_cell_start.begin(), m.patch_cell_start.end(),
+                                             (int32_t)cell_of[j]) - m.patch_cell_start.begin() - 1);
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return patch_of[a] < patch_of[b]; });
+  std::vector<int32_t> rptr(m.n_patches + 1, 0), rrec(npts);
+  std::vector<uint16_t> rloc((size_t)npts * nd);
+  std::vector<double> rw((size_t)npts * nd);
+  for (int k = 0; k < npts; ++k) {
+    const int j = order[k];
+    const int32_t q = patch_of[j];
+    rptr[q + 1]++;
+    rrec[k] = j;
+    const int32_t own0 = m.patch_own_start[q], own1 = m.patch_own_start[q + 1];
+    const int32_t sh0 = m.patch_sh_start[q], sh1 = m.patch_sh_start[q + 1];
+    for (int a = 0; a < nd; ++a) {
+      const int32_t g = sdof[(size_t)j * nd + a];
+      int32_t loc = -1;
+      if (g >= own0 && g < own1) {
+        loc = g - own0;
+      } else {
+        for (int32_t t = sh0; t < sh1; ++t)
+          if (m.sh_idx[t] == g) loc = (own1 - own0) + (t - sh0);
+      }
+      if (loc < 0) return Status{KMV_EINVAL, "point DOF not found in its patch"};
+      rloc[(size_t)k * nd + a] = (uint16_t)loc;
+      rw[(size_t)k * nd + a] = sw[(size_t)j * nd + a];
+    }
+  }
+  for (int64_t q = 0; q < m.n_patches; ++q) rptr[q + 1] += rptr[q];
   T.npts = npts;
-  T.host_xyz.assign(xyz, xyz + (size_t)npts * dim);
   STTRY(upload_i(&T.grp_ptr, gptr));
   STTRY(upload_i(&T.grp_local, glocal));
   STTRY(upload_i(&T.grp_eptr, geptr));
@@ -163,96 +210,167 @@ Status build_points(Problem* p, const double* xyz, int npts, bool same_amp, Poin
   STTRY(upload_real(&T.ent_w, ew, p->prec));
   STTRY(upload_i(&T.s_dof, sdof));
   STTRY(upload_real(&T.s_w, sw, p->prec));
+  STTRY(upload_i(&T.rp_ptr, rptr));
+  STTRY(upload_i(&T.rp_rec, rrec));
+  STTRY(upload_i(&T.rp_loc, rloc));
+  STTRY(upload_real(&T.rp_w, rw, p->prec));
   return OK;
 }
 
 void free_points(PointTables& T) {
-  dfree(T.grp_ptr);
-  dfree(T.grp_local);
-  dfree(T.grp_eptr);
-  dfree(T.ent_pt);
-  dfree(T.ent_w);
-  dfree(T.s_dof);
-  dfree(T.s_w);
+  for (void* q : {(void*)T.grp_ptr, (void*)T.grp_local, (void*)T.grp_eptr, (void*)T.ent_pt, T.ent_w,
+                  (void*)T.s_dof, T.s_w, (void*)T.rp_ptr, (void*)T.rp_rec, (void*)T.rp_loc, T.rp_w})
+    dfree(q);
   T = PointTables();
 }
 
+// Launch through the timing probe: every probe.every-th launch of a variant is
+// bracketed by events on the launch stream (resolved in profile_read).
+template <typename F>
+Status probed(Problem* p, int variant, hipStream_t s, F&& launch) {
+  Probe& pr = p->probe;
+  const bool timed = pr.every > 0 && (pr.launches[variant] % pr.every) == 0;
+  pr.launches[variant]++;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (timed) {
+    for (hipEvent_t* ev : {&a, &b}) {
+      if (!pr.pool.empty()) {
+        *ev = pr.pool.back();
+        pr.pool.pop_back();
+      } else {
+        HIPTRY(hipEventCreate(ev));
+      }
+    }
+    HIPTRY(hipEventRecord(a, s));
+  }
+  HIPTRY(launch());
+  if (timed) {
+    HIPTRY(hipEventRecord(b, s));
+    pr.pending.push_back({variant, a, b});
+  }
+  return OK;
+}
+
+Status resolve_probe(Problem* p) {
+  Probe& pr = p->probe;
+  for (auto& q : pr.pending) {
+    HIPTRY(hipEventSynchronize(q.b));
+    float ms = 0;
+    HIPTRY(hipEventElapsedTime(&ms, q.a, q.b));
+    pr.total_ms[q.variant] += ms;
+    pr.timed[q.variant]++;
+    pr.pool.push_back(q.a);
+    pr.pool.push_back(q.b);
+  }
+  pr.pending.clear();
+  return OK;
+}
+
 template <typename T>
-PatchArgs<T> base_args(const Problem* p) {
+StepArgs<T> base_args(const Problem* p) {
   const Mesh& m = *p->mesh;
-  PatchArgs<T> a{};
+  StepArgs<T> a{};
   a.lmap = p->d_lmap;
   a.geom = (const T*)p->d_geom;
-  a.D = (const T*)p->d_D;
-  a.W = (const T*)p->d_W;
   a.cell_start = p->d_cell_start;
   a.own_start = p->d_own_start;
   a.sh_start = p->d_sh_start;
   a.sh_idx = p->d_sh_idx;
-  a.colour_start = p->d_colour_start;
-  a.ncol = p->d_ncol;
+  a.gl_ptr = p->d_gl_ptr;
+  a.gl_ent = p->d_gl_ent;
+  a.gl_ptr_off = p->d_gl_ptr_off;
+  a.gl_ent_off = p->d_gl_ent_off;
+  a.shp_ptr = p->d_shp_ptr;
+  a.shp_slot = p->d_shp_slot;
+  a.ref_slots = p->d_ref_slots;
   a.n_cells = m.n_cells;
+  a.n_own = m.n_own_total;
   a.nloc_max = p->nloc;
+  a.cells_max = m.max_patch_cells;
   a.c2 = (const T*)p->d_c2;
   a.gamma = (const T*)p->d_gamma;
   a.beta = (const T*)p->d_beta;
-  a.partial = (T*)p->d_partial;
+  a.damp_patch = p->d_damp_patch;
   a.amp_scale = T(1);
   return a;
 }
 
-template <typename T>
-SharedArgs<T> shared_args(const Problem* p, const PatchArgs<T>& a) {
-  const Mesh& m = *p->mesh;
-  SharedArgs<T> s{};
-  s.n_own = m.n_own_total;
-  s.n_shared = m.n_shared;
-  s.shp_ptr = p->d_shp_ptr;
-  s.shp_slot = p->d_shp_slot;
-  s.mode = a.mode;
-  s.partial = a.partial;
-  s.u_in = a.u_in;
-  s.u_out = a.u_out;
-  s.du = a.du;
-  s.gamma = a.gamma;
-  s.beta = a.beta;
-  s.y_out = a.y_out;
-  s.partial_r = a.partial_r;
-  s.gacc = a.gacc;
-  return s;
-}
+// Parities of one launch: the level finished in it (cur) and the one before it
+// (prev), and the step whose partial sums it reads (prev) and writes (cur).
+struct Par {
+  int lvl_prev, lvl_cur, step_prev, step_cur;
+};
 
 template <typename T>
-void set_injection(PatchArgs<T>& a, const PointTables& P, const T* amp, T scale) {
-  a.grp_ptr = P.grp_ptr;
-  a.grp_local = P.grp_local;
-  a.grp_eptr = P.grp_eptr;
-  a.ent_pt = P.ent_pt;
-  a.ent_w = (const T*)P.ent_w;
-  a.amp = amp;
-  a.amp_scale = scale;
-}
-
-template <typename T>
-Status step(Problem* p, const T* u_in, T* u_out, T* du, const PointTables* inj, const T* amp, T scale,
-            const T* uf, hipStream_t s) {
+Status step(Problem* p, Sweep& S, bool grad, bool prev, const T* u_in, const T* u_prev, T* u_out, Par q,
+            const PointTables* inj, const T* amp, T scale, const T* uf, T* trace_row, hipStream_t s) {
   const Mesh& m = *p->mesh;
-  PatchArgs<T> a = base_args<T>(p);
+  StepArgs<T> a = base_args<T>(p);
   a.mode = 0;
+  a.prev = prev ? 1 : 0;
   a.u_in = u_in;
+  a.u_in_sh = const_cast<T*>(u_in);
+  a.u_prev = u_prev;
   a.u_out = u_out;
-  a.du = du;
-  if (inj && inj->grp_ptr) set_injection(a, *inj, amp, scale);
-  const bool adj = uf != nullptr;
-  if (adj) {
+  a.du = (T*)S.d;
+  a.dsh_prev = (const T*)S.dsh[q.lvl_prev];
+  a.dsh_cur = (T*)S.dsh[q.lvl_cur];
+  a.part_prev = (const T*)S.part[q.step_prev];
+  a.part_cur = (T*)S.part[q.step_cur];
+  if (inj && inj->grp_ptr) {
+    a.grp_ptr = inj->grp_ptr;
+    a.grp_local = inj->grp_local;
+    a.grp_eptr = inj->grp_eptr;
+    a.ent_pt = inj->ent_pt;
+    a.ent_w = (const T*)inj->ent_w;
+    a.amp = amp;
+    a.amp_scale = scale;
+  }
+  if (trace_row) {
+    a.rp_ptr = p->rec.rp_ptr;
+    a.rp_rec = p->rec.rp_rec;
+    a.rp_loc = p->rec.rp_loc;
+    a.rp_w = (const T*)p->rec.rp_w;
+    a.trace_row = trace_row;
+  }
+  if (grad) {
     a.uf = uf;
-    a.partial_r = (T*)p->d_partial_r;
+    a.partr_prev = (const T*)S.partr[q.step_prev];
+    a.partr_cur = (T*)S.partr[q.step_cur];
     a.gacc = p->d_gacc;
   }
-  HIPTRY(launch_patch<T>(m.dim, m.nd, adj, a, (int)m.n_patches, p->block, s));
-  HIPTRY(launch_shared<T>(adj, shared_args(p, a), s));
-  return OK;
+  return probed(p, grad ? 1 : 0, s,
+                [&]() { return launch_step<T>(m.dim, m.nd, grad, a, (int)m.n_patches, p->block, s); });
 }
+
+// Finish the shared DOFs of one level (u_cur, S.dsh[q.lvl_cur]) from the partials
+// of the step that produced it.
+template <typename T>
+Status finish(Problem* p, Sweep& S, bool grad, const T* u_prev, T* u_cur, Par q, hipStream_t s) {
+  const Mesh& m = *p->mesh;
+  FinishArgs<T> f{};
+  f.n_own = m.n_own_total;
+  f.n_shared = m.n_shared;
+  f.shp_ptr = p->d_shp_ptr;
+  f.shp_slot = p->d_shp_slot;
+  f.mode = 0;
+  f.part_prev = (const T*)S.part[q.step_prev];
+  f.u_prev = u_prev;
+  f.u_cur = u_cur;
+  f.dsh_prev = (const T*)S.dsh[q.lvl_prev];
+  f.dsh_cur = (T*)S.dsh[q.lvl_cur];
+  f.gamma = (const T*)p->d_gamma;
+  f.beta = (const T*)p->d_beta;
+  if (grad) {
+    f.partr_prev = (const T*)S.partr[q.step_prev];
+    f.gacc = p->d_gacc;
+  }
+  return probed(p, grad ? 3 : 2, s, [&]() { return launch_finish<T>(grad, f, s); });
+}
+
+Par fwd_par(int64_t n) { return Par{(int)((n + 1) & 1), (int)(n & 1), (int)((n + 1) & 1), (int)(n & 1)}; }
+// adjoint launch m finishes level m+1 from level m+2 and the partials of launch m+1
+Par adj_par(int64_t m) { return Par{(int)(m & 1), (int)((m + 1) & 1), (int)((m + 1) & 1), (int)(m & 1)}; }
 
 template <typename T>
 T* slot_ptr(Problem* p, int64_t k) {
@@ -266,23 +384,48 @@ Status ensure_slots(Problem* p, int64_t n) {
   return OK;
 }
 
-// Forward steps n0..n1-1; slot of level n is slot_of(n).
-template <typename T, typename F>
-Status run_forward(Problem* p, int64_t n0, int64_t n1, F slot_of, T* traces, bool save_ck,
-                   hipStream_t s) {
+template <typename T>
+Status zero_level(Problem* p, Sweep& S, T* u, int lvl_par, hipStream_t s) {
   const Mesh& m = *p->mesh;
+  HIPTRY(launch_fill<T>(u, T(0), m.n_dofs, s));
+  HIPTRY(launch_fill<T>((T*)S.d, T(0), m.n_dofs, s));
+  HIPTRY(launch_fill<T>((T*)S.dsh[lvl_par], T(0), m.n_shared, s));
+  return OK;
+}
+
+// Forward launches n0..n1-1 from a complete level n0 (u in slot_of(n0), owned
+// increments in fwd.d, shared increments in fwd.dsh[n0&1]); ends with level n1
+// complete.  traces: rows n-1 = d^n.  save_ck: checkpoints at multiples of seg.
+template <typename T, typename F>
+Status run_forward(Problem* p, int64_t n0, int64_t n1, F slot_of, T* traces, bool save_ck, hipStream_t s) {
+  const Mesh& m = *p->mesh;
+  Sweep& S = p->fwd;
   const size_t vb = (size_t)m.n_dofs * sizeof(T);
+  const size_t ob = (size_t)m.n_own_total * sizeof(T), shb = (size_t)m.n_shared * sizeof(T);
+  bool fresh = true;
   for (int64_t n = n0; n < n1; ++n) {
     if (save_ck && n % p->seg == 0) {
+      if (!fresh) STTRY(finish<T>(p, S, false, slot_of(n - 1), slot_of(n), fwd_par(n), s));
       const int64_t k = n / p->seg;
-      HIPTRY(hipMemcpyAsync((T*)p->d_ck_u + k * m.n_dofs, slot_of(n), vb, hipMemcpyDeviceToDevice, s));
-      HIPTRY(hipMemcpyAsync((T*)p->d_ck_du + k * m.n_dofs, p->d_du, vb, hipMemcpyDeviceToDevice, s));
+      T* cu = (T*)p->d_ck_u + k * m.n_dofs;
+      T* cd = (T*)p->d_ck_du + k * m.n_dofs;
+      HIPTRY(hipMemcpyAsync(cu, slot_of(n), vb, hipMemcpyDeviceToDevice, s));
+      HIPTRY(hipMemcpyAsync(cd, S.d, ob, hipMemcpyDeviceToDevice, s));
+      if (shb) HIPTRY(hipMemcpyAsync(cd + m.n_own_total, S.dsh[n & 1], shb, hipMemcpyDeviceToDevice, s));
+      fresh = true;
     }
-    STTRY(step<T>(p, slot_of(n), slot_of(n + 1), (T*)p->d_du, &p->src, (const T*)p->d_wavelet + n, T(1),
-                  nullptr, s));
-    if (traces)
-      HIPTRY(launch_sample<T>(slot_of(n + 1), p->rec.s_dof, (const T*)p->rec.s_w, p->rec.npts, m.nd,
-                              traces + n * p->rec.npts, s));
+    T* row = (traces && n >= 1) ? traces + (n - 1) * p->rec.npts : nullptr;
+    STTRY(step<T>(p, S, false, !fresh, slot_of(n), n > n0 ? slot_of(n - 1) : nullptr, slot_of(n + 1),
+                  fwd_par(n), &p->src, (const T*)p->d_wavelet + n, T(1), nullptr, row, s));
+    fresh = false;
+  }
+  if (n1 > n0) STTRY(finish<T>(p, S, false, slot_of(n1 - 1), slot_of(n1), fwd_par(n1), s));
+  if (traces && n1 >= 1) {
+    T* un = slot_of(n1);
+    STTRY(probed(p, 4, s, [&]() {
+      return launch_sample<T>(un, p->rec.s_dof, (const T*)p->rec.s_w, p->rec.npts, m.nd,
+                              traces + (n1 - 1) * p->rec.npts, s);
+    }));
   }
   return OK;
 }
@@ -292,8 +435,7 @@ Status forward_t(Problem* p, const double* c, T* traces, hipStream_t s) {
   const Mesh& m = *p->mesh;
   STTRY(ensure_slots(p, 2));
   HIPTRY(launch_square<T>(c, (T*)p->d_c2, m.n_dofs, s));
-  HIPTRY(launch_fill<T>((T*)p->d_du, T(0), m.n_dofs, s));
-  HIPTRY(launch_fill<T>(slot_ptr<T>(p, 0), T(0), m.n_dofs, s));
+  STTRY(zero_level<T>(p, p->fwd, slot_ptr<T>(p, 0), 0, s));
   return run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n & 1); }, traces, false, s);
 }
 
@@ -324,11 +466,28 @@ Status plan_storage(Problem* p) {
   return ensure_slots(p, seg + 1);
 }
 
+// One reverse launch m (lambda^{m+1} -> lambda^m); uf = u^m when grad.
 template <typename T>
-Status adjoint_step(Problem* p, int64_t m, const T* adj_rows, const T* uf, hipStream_t s) {
+Status adjoint_launch(Problem* p, int64_t m, bool grad, const T* adj_rows, const T* uf, hipStream_t s) {
   const double inv_dt2 = 1.0 / (p->dt * p->dt);
-  return step<T>(p, (const T*)p->d_lam[(m + 1) & 1], (T*)p->d_lam[m & 1], (T*)p->d_dlam, &p->rec,
-                 adj_rows + (m - 1) * p->rec.npts, (T)inv_dt2, uf, s);
+  T* lam_in = (T*)p->d_lam[(m + 1) & 1];
+  T* lam_out = (T*)p->d_lam[m & 1];
+  return step<T>(p, p->adj, grad, m != p->nt, lam_in, lam_out, lam_out, adj_par(m), &p->rec,
+                 adj_rows + (m - 1) * p->rec.npts, (T)inv_dt2, uf, nullptr, s);
+}
+
+template <typename T>
+Status adjoint_start(Problem* p, hipStream_t s) {
+  const Mesh& m = *p->mesh;
+  STTRY(zero_level<T>(p, p->adj, (T*)p->d_lam[(p->nt + 1) & 1], (int)((p->nt + 1) & 1), s));
+  HIPTRY(launch_fill<T>((T*)p->d_lam[p->nt & 1], T(0), m.n_dofs, s));
+  return OK;
+}
+
+// After launch 1: finish lambda^1 (level 1) from level 2 and launch 1's partials.
+template <typename T>
+Status adjoint_end(Problem* p, bool grad, hipStream_t s) {
+  return finish<T>(p, p->adj, grad, (const T*)p->d_lam[0], (T*)p->d_lam[1], adj_par(0), s);
 }
 
 template <typename T>
@@ -339,8 +498,7 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
   STTRY(plan_storage(p));
   T* traces = traces_out ? traces_out : (T*)p->d_traces_tmp;
   HIPTRY(launch_square<T>(c, (T*)p->d_c2, N, s));
-  HIPTRY(launch_fill<T>((T*)p->d_du, T(0), N, s));
-  HIPTRY(launch_fill<T>(slot_ptr<T>(p, 0), T(0), N, s));
+  STTRY(zero_level<T>(p, p->fwd, slot_ptr<T>(p, 0), 0, s));
   if (p->store_all) {
     STTRY(run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n); }, traces, false, s));
   } else {
@@ -348,24 +506,27 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
   }
   HIPTRY(launch_misfit<T>(traces, obs, (T*)p->d_resid, p->nt * p->rec.npts, p->d_red, p->red_blocks,
                           p->d_red + p->red_blocks, s));
-  HIPTRY(launch_fill<T>((T*)p->d_lam[0], T(0), N, s));
-  HIPTRY(launch_fill<T>((T*)p->d_lam[1], T(0), N, s));
-  HIPTRY(launch_fill<T>((T*)p->d_dlam, T(0), N, s));
+  STTRY(adjoint_start<T>(p, s));
   HIPTRY(launch_fill_f64(p->d_gacc, 0.0, N, s));
   const T* resid = (const T*)p->d_resid;
   if (p->store_all) {
-    for (int64_t mm = p->nt; mm >= 1; --mm) STTRY(adjoint_step<T>(p, mm, resid, slot_ptr<T>(p, mm), s));
+    for (int64_t mm = p->nt; mm >= 1; --mm) STTRY(adjoint_launch<T>(p, mm, true, resid, slot_ptr<T>(p, mm), s));
   } else {
     const size_t vb = (size_t)N * sizeof(T);
+    const size_t ob = (size_t)m.n_own_total * sizeof(T), shb = (size_t)m.n_shared * sizeof(T);
     for (int64_t k = p->n_ck - 1; k >= 0; --k) {
       const int64_t s0 = k * p->seg, s1 = std::min(s0 + p->seg, p->nt);
+      const T* cd = (const T*)p->d_ck_du + k * N;
       HIPTRY(hipMemcpyAsync(slot_ptr<T>(p, 0), (T*)p->d_ck_u + k * N, vb, hipMemcpyDeviceToDevice, s));
-      HIPTRY(hipMemcpyAsync(p->d_du, (T*)p->d_ck_du + k * N, vb, hipMemcpyDeviceToDevice, s));
+      HIPTRY(hipMemcpyAsync(p->fwd.d, cd, ob, hipMemcpyDeviceToDevice, s));
+      if (shb) HIPTRY(hipMemcpyAsync(p->fwd.dsh[s0 & 1], cd + m.n_own_total, shb, hipMemcpyDeviceToDevice, s));
       STTRY(run_forward<T>(p, s0, s1, [p, s0](int64_t n) { return slot_ptr<T>(p, n - s0); }, (T*)nullptr,
                            false, s));
-      for (int64_t mm = s1; mm > s0; --mm) STTRY(adjoint_step<T>(p, mm, resid, slot_ptr<T>(p, mm - s0), s));
+      for (int64_t mm = s1; mm > s0; --mm)
+        STTRY(adjoint_launch<T>(p, mm, true, resid, slot_ptr<T>(p, mm - s0), s));
     }
   }
+  STTRY(adjoint_end<T>(p, true, s));
   HIPTRY(launch_finalize_grad(c, p->d_gacc, 2.0 * p->dt * p->dt, grad, N, s));
   double hJ = 0;
   HIPTRY(hipMemcpyAsync(&hJ, p->d_red + p->red_blocks, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -381,34 +542,46 @@ Status adjoint_t(Problem* p, const double* c, const T* adj, T* lambda_out, T* sr
   const int64_t N = m.n_dofs;
   const size_t vb = (size_t)N * sizeof(T);
   HIPTRY(launch_square<T>(c, (T*)p->d_c2, N, s));
-  HIPTRY(launch_fill<T>((T*)p->d_lam[0], T(0), N, s));
-  HIPTRY(launch_fill<T>((T*)p->d_lam[1], T(0), N, s));
-  HIPTRY(launch_fill<T>((T*)p->d_dlam, T(0), N, s));
+  STTRY(adjoint_start<T>(p, s));
   if (lambda_out) HIPTRY(launch_fill<T>(lambda_out + p->nt * N, T(0), N, s));
-  const double inv_dt2 = 1.0 / (p->dt * p->dt);
-  for (int64_t mm = p->nt; mm >= 1; --mm) {
-    STTRY(step<T>(p, (const T*)p->d_lam[(mm + 1) & 1], (T*)p->d_lam[mm & 1], (T*)p->d_dlam, &p->rec,
-                  adj + (mm - 1) * p->rec.npts, (T)inv_dt2, nullptr, s));
-    if (lambda_out)
-      HIPTRY(hipMemcpyAsync(lambda_out + (mm - 1) * N, p->d_lam[mm & 1], vb, hipMemcpyDeviceToDevice, s));
+  auto record = [&](int64_t lvl) -> Status {  // level lvl is complete: row lvl-1
+    const T* lam = (const T*)p->d_lam[lvl & 1];
+    if (lambda_out) HIPTRY(hipMemcpyAsync(lambda_out + (lvl - 1) * N, lam, vb, hipMemcpyDeviceToDevice, s));
     if (src_trace)
-      HIPTRY(launch_sample<T>((const T*)p->d_lam[mm & 1], p->src.s_dof, (const T*)p->src.s_w, p->src.npts,
-                              m.nd, src_trace + (mm - 1) * p->src.npts, s));
+      STTRY(probed(p, 4, s, [&]() {
+        return launch_sample<T>(lam, p->src.s_dof, (const T*)p->src.s_w, p->src.npts, m.nd,
+                                src_trace + (lvl - 1) * p->src.npts, s);
+      }));
+    return OK;
+  };
+  for (int64_t mm = p->nt; mm >= 1; --mm) {
+    STTRY(adjoint_launch<T>(p, mm, false, adj, nullptr, s));
+    if (mm + 1 <= p->nt) STTRY(record(mm + 1));
   }
-  return OK;
+  STTRY(adjoint_end<T>(p, false, s));
+  return record(1);
 }
 
 template <typename T>
 Status apply_t(Problem* p, const double* c, const T* u, T* y, hipStream_t s) {
   const Mesh& m = *p->mesh;
   if (c) HIPTRY(launch_square<T>(c, (T*)p->d_c2, m.n_dofs, s));
-  PatchArgs<T> a = base_args<T>(p);
+  StepArgs<T> a = base_args<T>(p);
   a.mode = 1;
+  a.prev = 0;
   a.u_in = u;
   a.y_out = y;
-  HIPTRY(launch_patch<T>(m.dim, m.nd, false, a, (int)m.n_patches, p->block, s));
-  HIPTRY(launch_shared<T>(false, shared_args(p, a), s));
-  return OK;
+  a.part_cur = (T*)p->fwd.part[0];
+  STTRY(probed(p, 0, s, [&]() { return launch_step<T>(m.dim, m.nd, false, a, (int)m.n_patches, p->block, s); }));
+  FinishArgs<T> f{};
+  f.n_own = m.n_own_total;
+  f.n_shared = m.n_shared;
+  f.shp_ptr = p->d_shp_ptr;
+  f.shp_slot = p->d_shp_slot;
+  f.mode = 1;
+  f.part_prev = (const T*)p->fwd.part[0];
+  f.y_out = y;
+  return probed(p, 2, s, [&]() { return launch_finish<T>(false, f, s); });
 }
 
 template <typename T>
@@ -447,7 +620,7 @@ Status spectral_t(Problem* p, const double* c, int iters, uint64_t seed, double*
     HIPTRY(launch_scale<T>((const T*)y, ms, (T*)w, N, s));
     HIPTRY(launch_dot<T>((const T*)v, (const T*)w, N, p->d_red, p->red_blocks, dots, s));
     HIPTRY(launch_dot<T>((const T*)w, (const T*)w, N, p->d_red, p->red_blocks, dots + 1, s));
-    HIPTRY(launch_axpby_norm<T>((T*)v, (const T*)w, dots + 1, N, s));
+    HIPTRY(launch_normalize<T>((T*)v, (const T*)w, dots + 1, N, s));
   }
   double h = 0;
   HIPTRY(hipMemcpyAsync(&h, dots, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -457,16 +630,65 @@ Status spectral_t(Problem* p, const double* c, int iters, uint64_t seed, double*
   return OK;
 }
 
+void free_sweep(Sweep& S) {
+  for (void* q : {S.d, S.dsh[0], S.dsh[1], S.part[0], S.part[1], S.partr[0], S.partr[1]}) dfree(q);
+  S = Sweep();
+}
+
+Status alloc_sweep(Sweep& S, const Mesh& m, size_t ts, bool with_r) {
+  const size_t pb = std::max<size_t>(1, m.n_shared_refs) * ts;
+  const size_t shb = std::max<int64_t>(1, m.n_shared) * ts;
+  STTRY(alloc(&S.d, (size_t)m.n_dofs * ts));
+  for (int i = 0; i < 2; ++i) {
+    STTRY(alloc(&S.dsh[i], shb));
+    STTRY(alloc(&S.part[i], pb));
+    if (with_r) STTRY(alloc(&S.partr[i], pb));
+  }
+  return OK;
+}
+
 }  // namespace
 
 Problem::~Problem() {
-  for (void* q : {(void*)d_lmap, d_geom, d_D, d_W, (void*)d_cell_start, (void*)d_own_start, (void*)d_sh_start,
-                  (void*)d_sh_idx, (void*)d_colour_start, (void*)d_ncol, (void*)d_shp_ptr, (void*)d_shp_slot,
-                  d_gamma, d_beta, d_c2, d_minv_sqrt, d_du, d_partial, d_partial_r, d_lam[0], d_lam[1], d_dlam,
-                  (void*)d_gacc, (void*)d_red, d_slots, d_ck_u, d_ck_du, d_resid, d_traces_tmp, d_wavelet})
+  for (void* q : {(void*)d_lmap, d_geom, (void*)d_cell_start, (void*)d_own_start, (void*)d_sh_start,
+                  (void*)d_sh_idx, (void*)d_shp_ptr, (void*)d_shp_slot, (void*)d_ref_slots, (void*)d_gl_ptr,
+                  (void*)d_gl_ent, (void*)d_gl_ptr_off, (void*)d_gl_ent_off, (void*)d_damp_patch, d_gamma, d_beta, d_c2, d_minv_sqrt, d_lam[0], d_lam[1], (void*)d_gacc, (void*)d_red, d_slots,
+                  d_ck_u, d_ck_du, d_resid, d_traces_tmp, d_wavelet})
     dfree(q);
+  free_sweep(fwd);
+  free_sweep(adj);
   free_points(src);
   free_points(rec);
+  for (auto& q : probe.pending) {
+    (void)hipEventDestroy(q.a);
+    (void)hipEventDestroy(q.b);
+  }
+  for (hipEvent_t e : probe.pool) (void)hipEventDestroy(e);
+}
+
+Status profile_enable(Problem* p, int every) {
+  DeviceGuard dg(p->device);
+  if (every < 0) return Status{KMV_EINVAL, "every must be >= 0"};
+  STTRY(resolve_probe(p));
+  Probe& pr = p->probe;
+  pr.every = every;
+  for (int v = 0; v < Probe::kVariants; ++v) {
+    pr.launches[v] = 0;
+    pr.timed[v] = 0;
+    pr.total_ms[v] = 0;
+  }
+  return OK;
+}
+
+Status profile_read(Problem* p, int variant, int64_t* launches, int64_t* timed, double* mean_ms) {
+  DeviceGuard dg(p->device);
+  if (variant < 0 || variant >= Probe::kVariants) return Status{KMV_EINVAL, "variant out of range"};
+  STTRY(resolve_probe(p));
+  const Probe& pr = p->probe;
+  if (launches) *launches = pr.launches[variant];
+  if (timed) *timed = pr.timed[variant];
+  if (mean_ms) *mean_ms = pr.timed[variant] ? pr.total_ms[variant] / pr.timed[variant] : 0.0;
+  return OK;
 }
 
 Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_every, size_t budget,
@@ -486,17 +708,20 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
   HIPTRY(hipGetDevice(&p->device));
   p->block = std::max(64, ((m->max_patch_cells + 63) / 64) * 64);
   p->nloc = m->max_nloc;
-  for (bool adj : {false, true}) {
-    const int bytes = (adj ? 5 : 3) * p->nloc * (int)p->ts;
+  for (int64_t q = 0; q < m->n_patches; ++q)
+    p->nown = std::max(p->nown, m->patch_own_start[q + 1] - m->patch_own_start[q]);
+  {
+    const size_t bytes = step_lds_bytes(p->nloc, m->max_patch_cells, m->nd, p->ts);
     if (bytes > 160 * 1024) return Status{KMV_EINVAL, "patch LDS footprint above 160 KiB; use smaller patches"};
     if (bytes > 64 * 1024) {
-      if (prec == KMV_FP64)
-        HIPTRY(set_patch_lds_limit<double>(m->dim, m->nd, adj, bytes));
-      else
-        HIPTRY(set_patch_lds_limit<float>(m->dim, m->nd, adj, bytes));
+      for (bool adjv : {false, true}) {
+        if (prec == KMV_FP64)
+          HIPTRY(set_step_lds_limit<double>(m->dim, m->nd, adjv, (int)bytes));
+        else
+          HIPTRY(set_step_lds_limit<float>(m->dim, m->nd, adjv, (int)bytes));
+      }
     }
   }
-  const Element& el = *m->el;
   STTRY(upload_i(&p->d_lmap, m->lmap));
   {
     std::vector<double> g((size_t)m->ng * m->n_cells);  // SoA
@@ -504,16 +729,17 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
       for (int k = 0; k < m->ng; ++k) g[(size_t)k * m->n_cells + e] = m->geom[e * m->ng + k];
     STTRY(upload_real(&p->d_geom, g, prec));
   }
-  STTRY(upload_real(&p->d_D, el.grads, prec));
-  STTRY(upload_real(&p->d_W, el.weights, prec));
   STTRY(upload_i(&p->d_cell_start, m->patch_cell_start));
   STTRY(upload_i(&p->d_own_start, m->patch_own_start));
   STTRY(upload_i(&p->d_sh_start, m->patch_sh_start));
   STTRY(upload_i(&p->d_sh_idx, m->sh_idx));
-  STTRY(upload_i(&p->d_colour_start, m->colour_start));
-  STTRY(upload_i(&p->d_ncol, m->patch_ncol));
+  STTRY(upload_i(&p->d_gl_ptr, m->gl_ptr));
+  STTRY(upload_i(&p->d_gl_ent, m->gl_ent));
+  STTRY(upload_i(&p->d_gl_ptr_off, m->gl_ptr_off));
+  STTRY(upload_i(&p->d_gl_ent_off, m->gl_ent_off));
   STTRY(upload_i(&p->d_shp_ptr, m->shp_ptr));
   STTRY(upload_i(&p->d_shp_slot, m->shp_slot));
+  if (!m->ref_slots.empty()) STTRY(upload_i(&p->d_ref_slots, m->ref_slots));
   STTRY(upload_coefficients(p));
   {
     std::vector<double> ms(m->n_dofs);
@@ -521,14 +747,11 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
     STTRY(upload_real(&p->d_minv_sqrt, ms, prec));
   }
   const size_t vb = (size_t)m->n_dofs * p->ts;
-  const size_t pb = std::max<size_t>(1, m->n_shared_refs) * p->ts;
   STTRY(alloc(&p->d_c2, vb));
-  STTRY(alloc(&p->d_du, vb));
-  STTRY(alloc(&p->d_partial, pb));
-  STTRY(alloc(&p->d_partial_r, pb));
+  STTRY(alloc_sweep(p->fwd, *m, p->ts, false));
+  STTRY(alloc_sweep(p->adj, *m, p->ts, true));
   STTRY(alloc(&p->d_lam[0], vb));
   STTRY(alloc(&p->d_lam[1], vb));
-  STTRY(alloc(&p->d_dlam, vb));
   STTRY(alloc((void**)&p->d_gacc, (size_t)m->n_dofs * 8));
   STTRY(alloc((void**)&p->d_red, (size_t)(p->red_blocks + 8) * 8));
   *out = guard.release();
@@ -558,9 +781,6 @@ Status set_sources(Problem* p, const double* xs, int nsrc, double f0, double t0,
   if (nsrc <= 0 || !xs) return Status{KMV_EINVAL, "need at least one source"};
   free_points(p->src);
   STTRY(build_points(p, xs, nsrc, true, p->src));
-  p->f0 = f0;
-  p->t0 = t0;
-  p->amp = amp;
   std::vector<double> w(p->nt);
   const double pi = 3.14159265358979323846;
   for (int64_t n = 0; n < p->nt; ++n) {

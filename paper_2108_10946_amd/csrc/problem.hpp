@@ -15,7 +15,8 @@ struct Status {
   std::string msg;
 };
 
-// Point tables on the device: injection groups (per patch) and sampling rows.
+// Point tables on the device: injection groups (per designated patch), global
+// sampling rows, and per-patch sampling rows with patch-local DOF indices.
 struct PointTables {
   int npts = 0;
   int32_t* grp_ptr = nullptr;   // [np+1]
@@ -23,12 +24,40 @@ struct PointTables {
   int32_t* grp_eptr = nullptr;
   int32_t* ent_pt = nullptr;
   void* ent_w = nullptr;
-  int32_t* s_dof = nullptr;     // [npts*nd] sampling
+  int32_t* s_dof = nullptr;     // [npts*nd] global DOFs
   void* s_w = nullptr;          // [npts*nd]
-  std::vector<double> host_xyz;
+  int32_t* rp_ptr = nullptr;    // [np+1] points whose cell lies in each patch
+  int32_t* rp_rec = nullptr;    // point index
+  uint16_t* rp_loc = nullptr;   // [npts*nd] patch-local DOFs
+  void* rp_w = nullptr;         // [npts*nd]
+};
+
+// Event-based timing of sampled kernel launches (see kmv_profile_enable).
+struct Probe {
+  static constexpr int kVariants = 5;
+  int every = 0;
+  int64_t launches[kVariants] = {0, 0, 0, 0, 0};
+  int64_t timed[kVariants] = {0, 0, 0, 0, 0};
+  double total_ms[kVariants] = {0, 0, 0, 0, 0};
+  struct Pending {
+    int variant;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+};
+
+// Lagged state of one sweep: owned increments, the shared increments of the two
+// most recent levels and the partial sums of the two most recent steps.
+struct Sweep {
+  void* d = nullptr;           // [n_dofs] owned increments
+  void* dsh[2] = {nullptr, nullptr};   // [n_shared] by level parity
+  void* part[2] = {nullptr, nullptr};  // [n_shared_refs] by step parity
+  void* partr[2] = {nullptr, nullptr}; // adjoint pairing partials
 };
 
 struct Problem {
+  Probe probe;
   Mesh* mesh = nullptr;
   int prec = 0;        // 0 fp64, 1 fp32
   size_t ts = 8;       // element size
@@ -38,30 +67,28 @@ struct Problem {
   size_t budget = 0;
   int device = 0;
   int block = 64;
-  int nloc = 0;
+  int nloc = 0, nown = 0;
   // mesh data
   uint16_t* d_lmap = nullptr;
   void* d_geom = nullptr;
-  void* d_D = nullptr;
-  void* d_W = nullptr;
   int32_t *d_cell_start = nullptr, *d_own_start = nullptr, *d_sh_start = nullptr, *d_sh_idx = nullptr,
-          *d_colour_start = nullptr, *d_ncol = nullptr, *d_shp_ptr = nullptr, *d_shp_slot = nullptr;
+          *d_shp_ptr = nullptr, *d_shp_slot = nullptr, *d_ref_slots = nullptr, *d_gl_ptr_off = nullptr,
+          *d_gl_ent_off = nullptr;
+  uint16_t *d_gl_ptr = nullptr, *d_gl_ent = nullptr;
   // coefficients
   std::vector<double> eta;      // host damping (empty = none)
   void* d_gamma = nullptr;
   void* d_beta = nullptr;
+  int32_t* d_damp_patch = nullptr;  // [np] patch touches a damped DOF
   void* d_c2 = nullptr;
   void* d_minv_sqrt = nullptr;  // for the power iteration
-  // state
-  void* d_du = nullptr;
-  void* d_partial = nullptr;
-  void* d_partial_r = nullptr;
+  // sweeps
+  Sweep fwd, adj;
   void* d_lam[2] = {nullptr, nullptr};
-  void* d_dlam = nullptr;
   double* d_gacc = nullptr;
   double* d_red = nullptr;      // reduction scratch
   int red_blocks = 256;
-  void* d_slots = nullptr;      // state slots
+  void* d_slots = nullptr;      // forward state slots
   int64_t n_slots = 0;
   void* d_ck_u = nullptr;
   void* d_ck_du = nullptr;
@@ -74,7 +101,6 @@ struct Problem {
   PointTables src, rec;
   void* d_wavelet = nullptr;    // [nt]
   std::vector<double> wavelet;
-  double f0 = 0, t0 = 0, amp = 0;
 
   ~Problem();
 };
@@ -93,5 +119,7 @@ Status adjoint(Problem* p, const double* c_dev, const void* adj_dev, void* lambd
 Status stiffness_apply(Problem* p, const double* c_dev, const void* u_dev, void* y_dev, hipStream_t s);
 Status spectral_radius(Problem* p, const double* c_dev, int iters, uint64_t seed, double* rho,
                        hipStream_t s);
+Status profile_enable(Problem* p, int every);
+Status profile_read(Problem* p, int variant, int64_t* launches, int64_t* timed, double* mean_ms);
 
 }  // namespace kmv

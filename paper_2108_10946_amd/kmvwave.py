@@ -33,7 +33,7 @@ DECLARED = [
     "kmv_problem_create", "kmv_cfl_dt", "kmv_spectral_radius", "kmv_set_damping",
     "kmv_set_sources", "kmv_set_source_wavelet", "kmv_set_receivers", "kmv_forward",
     "kmv_misfit_gradient", "kmv_adjoint", "kmv_stiffness_apply", "kmv_problem_info",
-    "kmv_problem_destroy",
+    "kmv_profile_enable", "kmv_profile_read", "kmv_problem_destroy",
 ]
 
 
@@ -87,6 +87,9 @@ def lib():
         "kmv_stiffness_apply": (C.c_int, [_P, _P, _P, _P, _P]),
         "kmv_problem_info": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int),
                                        C.POINTER(C.c_int), C.POINTER(C.c_int64)]),
+        "kmv_profile_enable": (C.c_int, [_P, C.c_int]),
+        "kmv_profile_read": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_double)]),
         "kmv_problem_destroy": (C.c_int, [_P]),
     }
     for name, (res, args) in sig.items():
@@ -250,6 +253,20 @@ def kmv_adjoint(p, c_dev, adj_src_dev, lambda_out_dev=None, src_trace_dev=None, 
 
 def kmv_stiffness_apply(p, c_dev, u_dev, y_dev, stream=None):
     _check(lib().kmv_stiffness_apply(p, _tptr(c_dev), _tptr(u_dev), _tptr(y_dev), _stream(stream)))
+
+
+PROFILE_VARIANTS = {0: "patch_forward", 1: "patch_adjoint", 2: "shared_forward", 3: "shared_adjoint",
+                    4: "receivers"}
+
+
+def kmv_profile_enable(p, every):
+    _check(lib().kmv_profile_enable(p, every))
+
+
+def kmv_profile_read(p, variant):
+    n, t, ms = C.c_int64(), C.c_int64(), C.c_double()
+    _check(lib().kmv_profile_read(p, variant, C.byref(n), C.byref(t), C.byref(ms)))
+    return dict(launches=n.value, timed=t.value, mean_ms=ms.value)
 
 
 def kmv_problem_destroy(p):
