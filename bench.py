@@ -71,7 +71,7 @@ def traffic_from_profiles(variant, hash_):
     return rec.get("bytes_per_launch")
 
 
-def setup_workload(precision, budget_frac=0.75, mesh_cache={}):
+def setup_workload(precision, budget_frac=0.75, window=0, mesh_cache={}):
     import torch
     from paper_2108_10946_amd import Mesh, Problem
     from synth import configs
@@ -96,6 +96,8 @@ def setup_workload(precision, budget_frac=0.75, mesh_cache={}):
         mesh_cache["dt"] = (w.T / nt, nt)
         log(f"CFL: rho={rho:.6g}, dt={w.T / nt * 1e3:.4f} ms, N_t={nt}")
     dt, nt = mesh_cache["dt"]
+    if window:
+        nt = window
     prob = Problem(m, dt, nt, precision=precision, mem_budget=budget)
     prob.set_damping(eta)
     prob.set_sources(w.sources, f0=w.f0, t0=w.t0, amp=w.amp)
@@ -105,10 +107,10 @@ def setup_workload(precision, budget_frac=0.75, mesh_cache={}):
     return w, m, prob, c_cur, obs, dt, nt
 
 
-def time_gpu(precision, steps, warmup, every):
+def time_gpu(precision, steps, warmup, every, window=0):
     import torch
     from paper_2108_10946_amd import kmvwave as K
-    w, m, prob, c, obs, dt, nt = setup_workload(precision)
+    w, m, prob, c, obs, dt, nt = setup_workload(precision, window=window)
     K.kmv_profile_enable(prob.handle, every)
     for i in range(warmup):
         t = time.time()
@@ -156,7 +158,7 @@ def roofline(res, ts, dim=2):
     return best
 
 
-def cpu_baseline(n_sample=20):
+def cpu_baseline(n_sample=120):
     """FP64 oracle (one thread) on the first n_sample forward and adjoint steps of
     the same workload; setup (DOF numbering, assembly) is not timed."""
     from threadpoolctl import threadpool_limits
@@ -189,6 +191,19 @@ def cpu_baseline(n_sample=20):
                       f"adjoint + gradient, FP64 assembled CSR, one thread; {sec:.1f}s"}
 
 
+def copy_calibration(n_bytes=1 << 30, reps=3):
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE
+    counters of a profiled run to bytes."""
+    import torch
+    a = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": n_bytes, "bytes_written": n_bytes,
+                                           "dispatches": reps}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +212,11 @@ def main():
     ap.add_argument("--profile-every", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--window", type=int, default=0,
+                    help="run only the first WINDOW time steps (hardware-counter runs: the "
+                         "per-launch traffic does not depend on the window); not a bench line")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); shots shard "
@@ -207,14 +227,18 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import paper_2108_10946_amd as kmv
     kmv.lib()
 
-    res32 = time_gpu("fp32", args.steps, args.warmup, args.profile_every)
+    res32 = time_gpu("fp32", args.steps, args.warmup, args.profile_every, args.window)
     rl = roofline(res32, 4)
     res64 = None
     if not args.no_fp64:
-        res64 = time_gpu("fp64", max(1, args.steps // 2), min(1, args.warmup), args.profile_every)
+        res64 = time_gpu("fp64", max(1, args.steps // 2), min(1, args.warmup), args.profile_every,
+                         args.window)
         roofline(res64, 8)
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 
@@ -249,6 +273,9 @@ def main():
         "kernel_mean_us": {k: round(v["mean_ms"] * 1e3, 3) for k, v in res32["prof"].items()},
         "cpu_baseline": cpu,
     }
+    if args.window:
+        out["window"] = args.window
+        out["note"] = "time window cut for a hardware-counter run: not a bench line"
     if res64:
         out["fp64"] = {"value": round(N * nt / res64["sec"], 1), "ms_per_step": round(res64["sec"] * 1e3, 3),
                        "state_storage": ("all states kept in HBM" if res64["checkpoint_every"] == 0

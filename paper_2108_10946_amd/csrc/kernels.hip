@@ -17,6 +17,8 @@
 //     LDS slots, then each DOF sums its slots in a fixed (cell, node) order;
 //   * leapfrog + sponge for the DOFs only this patch touches (eq. forward3 with a
 //     diagonal leading matrix): du <- beta du - gamma (K u - b), u <- u + du.
+#include <hip/hip_ext.h>
+
 #include "kernels.hpp"
 #include "kmv_tables.inc"
 
@@ -479,10 +481,22 @@ __global__ void k_normalize(T* __restrict__ v, const T* __restrict__ w, const do
 namespace {
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// Launch with optional start/stop events recorded by the dispatch itself, so a
+// sampled launch is timed without the event packets' own dispatch gaps.
+template <typename K, typename... Args>
+void launch_ev(K kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, hipEvent_t e0,
+               hipEvent_t e1, Args... args) {
+  if (e0)
+    hipExtLaunchKernelGGL(kernel, grid, block, lds, s, e0, e1, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+}
+
 template <typename T, int DIM, int ND, bool ADJ>
-hipError_t launch_step_t(const StepArgs<T>& a, int np, int block, hipStream_t s) {
+hipError_t launch_step_t(const StepArgs<T>& a, int np, int block, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1) {
   const size_t lds = StepLds(a.nloc_max, a.cells_max, ND, sizeof(T)).total;
-  hipLaunchKernelGGL((k_step<T, DIM, ND, ADJ>), dim3(np), dim3(block), lds, s, a);
+  launch_ev(k_step<T, DIM, ND, ADJ>, dim3(np), dim3(block), (uint32_t)lds, s, e0, e1, a);
   return hipGetLastError();
 }
 
@@ -512,8 +526,8 @@ size_t step_lds_bytes(int nloc_max, int cells_max, int nd, size_t elem_size) {
 
 template <typename T>
 hipError_t launch_step(int dim, int nd, bool adjoint, const StepArgs<T>& a, int n_patches, int block,
-                       hipStream_t s) {
-  KMV_DISPATCH(launch_step_t, a, n_patches, block, s)
+                       hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  KMV_DISPATCH(launch_step_t, a, n_patches, block, s, e0, e1)
 }
 
 template <typename T>
@@ -522,23 +536,25 @@ hipError_t set_step_lds_limit(int dim, int nd, bool adjoint, int bytes) {
 }
 
 template <typename T>
-hipError_t launch_finish(bool adjoint, const FinishArgs<T>& a, hipStream_t s) {
+hipError_t launch_finish(bool adjoint, const FinishArgs<T>& a, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1) {
   if (a.n_shared == 0) return hipSuccess;
   const unsigned nb = blocks_for(a.n_shared, 256);
   if (adjoint)
-    hipLaunchKernelGGL((k_finish<T, true>), dim3(nb), dim3(256), 0, s, a);
+    launch_ev(k_finish<T, true>, dim3(nb), dim3(256), 0u, s, e0, e1, a);
   else
-    hipLaunchKernelGGL((k_finish<T, false>), dim3(nb), dim3(256), 0, s, a);
+    launch_ev(k_finish<T, false>, dim3(nb), dim3(256), 0u, s, e0, e1, a);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_sample(const T* u, const int32_t* dof, const T* w, int npts, int nd, T* out,
-                         hipStream_t s) {
+                         hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (npts <= 0) return hipSuccess;
   if (nd > 256) return hipErrorInvalidValue;
   const int per = 256 / nd;
-  hipLaunchKernelGGL((k_sample<T>), dim3(blocks_for(npts, per)), dim3(256), 0, s, u, dof, w, npts, nd, out);
+  launch_ev(k_sample<T>, dim3(blocks_for(npts, per)), dim3(256), 0u, s, e0, e1, u, dof, w, npts, nd,
+            out);
   return hipGetLastError();
 }
 
@@ -596,10 +612,13 @@ hipError_t launch_normalize(T* v, const T* w, const double* dot_ww, int64_t n, h
 }
 
 #define KMV_INST(T)                                                                                    \
-  template hipError_t launch_step<T>(int, int, bool, const StepArgs<T>&, int, int, hipStream_t);       \
+  template hipError_t launch_step<T>(int, int, bool, const StepArgs<T>&, int, int, hipStream_t,        \
+                                     hipEvent_t, hipEvent_t);                                         \
   template hipError_t set_step_lds_limit<T>(int, int, bool, int);                                      \
-  template hipError_t launch_finish<T>(bool, const FinishArgs<T>&, hipStream_t);                      \
-  template hipError_t launch_sample<T>(const T*, const int32_t*, const T*, int, int, T*, hipStream_t); \
+  template hipError_t launch_finish<T>(bool, const FinishArgs<T>&, hipStream_t, hipEvent_t,           \
+                                       hipEvent_t);                                                   \
+  template hipError_t launch_sample<T>(const T*, const int32_t*, const T*, int, int, T*, hipStream_t,  \
+                                      hipEvent_t, hipEvent_t);                                       \
   template hipError_t launch_square<T>(const double*, T*, int64_t, hipStream_t);                      \
   template hipError_t launch_fill<T>(T*, T, int64_t, hipStream_t);                                    \
   template hipError_t launch_misfit<T>(const T*, const T*, T*, int64_t, double*, int, double*,         \

@@ -101,15 +101,17 @@ struct FinishArgs {
 };
 
 template <typename T>
+// e0/e1: optional events recorded by the dispatch itself at kernel start and end.
 hipError_t launch_step(int dim, int nd, bool adjoint, const StepArgs<T>& a, int n_patches, int block,
-                       hipStream_t s);
+                       hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Dynamic LDS bytes of one k_step workgroup.
 size_t step_lds_bytes(int nloc_max, int cells_max, int nd, size_t elem_size);
 template <typename T>
-hipError_t launch_finish(bool adjoint, const FinishArgs<T>& a, hipStream_t s);
+hipError_t launch_finish(bool adjoint, const FinishArgs<T>& a, hipStream_t s, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr);
 template <typename T>
 hipError_t launch_sample(const T* u, const int32_t* dof, const T* w, int npts, int nd, T* out,
-                         hipStream_t s);
+                         hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 template <typename T>
 hipError_t launch_square(const double* c, T* c2, int64_t n, hipStream_t s);
 template <typename T>

@@ -224,8 +224,9 @@ void free_points(PointTables& T) {
   T = PointTables();
 }
 
-// Launch through the timing probe: every probe.every-th launch of a variant is
-// bracketed by events on the launch stream (resolved in profile_read).
+// Launch through the timing probe: every probe.every-th launch of a variant gets
+// start/stop events recorded by its own dispatch (resolved in profile_read).  The
+// launcher is called as launch(e0, e1) with null events for untimed launches.
 template <typename F>
 Status probed(Problem* p, int variant, hipStream_t s, F&& launch) {
   Probe& pr = p->probe;
@@ -241,13 +242,9 @@ Status probed(Problem* p, int variant, hipStream_t s, F&& launch) {
         HIPTRY(hipEventCreate(ev));
       }
     }
-    HIPTRY(hipEventRecord(a, s));
   }
-  HIPTRY(launch());
-  if (timed) {
-    HIPTRY(hipEventRecord(b, s));
-    pr.pending.push_back({variant, a, b});
-  }
+  HIPTRY(launch(a, b));
+  if (timed) pr.pending.push_back({variant, a, b});
   return OK;
 }
 
@@ -339,8 +336,9 @@ Status step(Problem* p, Sweep& S, bool grad, bool prev, const T* u_in, const T* 
     a.partr_cur = (T*)S.partr[q.step_cur];
     a.gacc = p->d_gacc;
   }
-  return probed(p, grad ? 1 : 0, s,
-                [&]() { return launch_step<T>(m.dim, m.nd, grad, a, (int)m.n_patches, p->block, s); });
+  return probed(p, grad ? 1 : 0, s, [&](hipEvent_t e0, hipEvent_t e1) {
+    return launch_step<T>(m.dim, m.nd, grad, a, (int)m.n_patches, p->block, s, e0, e1);
+  });
 }
 
 // Finish the shared DOFs of one level (u_cur, S.dsh[q.lvl_cur]) from the partials
@@ -365,7 +363,8 @@ Status finish(Problem* p, Sweep& S, bool grad, const T* u_prev, T* u_cur, Par q,
     f.partr_prev = (const T*)S.partr[q.step_prev];
     f.gacc = p->d_gacc;
   }
-  return probed(p, grad ? 3 : 2, s, [&]() { return launch_finish<T>(grad, f, s); });
+  return probed(p, grad ? 3 : 2, s,
+                [&](hipEvent_t e0, hipEvent_t e1) { return launch_finish<T>(grad, f, s, e0, e1); });
 }
 
 Par fwd_par(int64_t n) { return Par{(int)((n + 1) & 1), (int)(n & 1), (int)((n + 1) & 1), (int)(n & 1)}; }
@@ -422,9 +421,9 @@ Status run_forward(Problem* p, int64_t n0, int64_t n1, F slot_of, T* traces, boo
   if (n1 > n0) STTRY(finish<T>(p, S, false, slot_of(n1 - 1), slot_of(n1), fwd_par(n1), s));
   if (traces && n1 >= 1) {
     T* un = slot_of(n1);
-    STTRY(probed(p, 4, s, [&]() {
+    STTRY(probed(p, 4, s, [&](hipEvent_t e0, hipEvent_t e1) {
       return launch_sample<T>(un, p->rec.s_dof, (const T*)p->rec.s_w, p->rec.npts, m.nd,
-                              traces + (n1 - 1) * p->rec.npts, s);
+                              traces + (n1 - 1) * p->rec.npts, s, e0, e1);
     }));
   }
   return OK;
@@ -548,9 +547,9 @@ Status adjoint_t(Problem* p, const double* c, const T* adj, T* lambda_out, T* sr
     const T* lam = (const T*)p->d_lam[lvl & 1];
     if (lambda_out) HIPTRY(hipMemcpyAsync(lambda_out + (lvl - 1) * N, lam, vb, hipMemcpyDeviceToDevice, s));
     if (src_trace)
-      STTRY(probed(p, 4, s, [&]() {
+      STTRY(probed(p, 4, s, [&](hipEvent_t e0, hipEvent_t e1) {
         return launch_sample<T>(lam, p->src.s_dof, (const T*)p->src.s_w, p->src.npts, m.nd,
-                                src_trace + (lvl - 1) * p->src.npts, s);
+                                src_trace + (lvl - 1) * p->src.npts, s, e0, e1);
       }));
     return OK;
   };
@@ -572,7 +571,9 @@ Status apply_t(Problem* p, const double* c, const T* u, T* y, hipStream_t s) {
   a.u_in = u;
   a.y_out = y;
   a.part_cur = (T*)p->fwd.part[0];
-  STTRY(probed(p, 0, s, [&]() { return launch_step<T>(m.dim, m.nd, false, a, (int)m.n_patches, p->block, s); }));
+  STTRY(probed(p, 0, s, [&](hipEvent_t e0, hipEvent_t e1) {
+    return launch_step<T>(m.dim, m.nd, false, a, (int)m.n_patches, p->block, s, e0, e1);
+  }));
   FinishArgs<T> f{};
   f.n_own = m.n_own_total;
   f.n_shared = m.n_shared;
@@ -581,7 +582,8 @@ Status apply_t(Problem* p, const double* c, const T* u, T* y, hipStream_t s) {
   f.mode = 1;
   f.part_prev = (const T*)p->fwd.part[0];
   f.y_out = y;
-  return probed(p, 2, s, [&]() { return launch_finish<T>(false, f, s); });
+  return probed(p, 2, s,
+                [&](hipEvent_t e0, hipEvent_t e1) { return launch_finish<T>(false, f, s, e0, e1); });
 }
 
 template <typename T>
