@@ -126,7 +126,9 @@ typedef struct {
  * Errors: KMV_EINVAL, KMV_ENOMEM, KMV_EDEVICE. */
 int kmv_problem_create(kmv_mesh m, const kmv_options* opt, kmv_problem* out);
 /* Spectral radius of M^-1 K(c) by a seeded power iteration on the GPU (the step
- * bound of eq. spectral without the Gershgorin over-estimate).  Synchronises. */
+ * bound of eq. spectral without the Gershgorin over-estimate).  The start vector
+ * is a normal deviate per DOF hashed from the seed and the DOF coordinates, so the
+ * result does not depend on the internal DOF numbering.  Synchronises. */
 int kmv_spectral_radius(kmv_problem p, const void* c_dev, int iters, uint64_t seed,
                         double* rho, void* stream);
 /* Damping eta [n_dofs] in 1/s (host, DOF order; NULL = none).  The step uses

@@ -4,19 +4,24 @@
 //
 // Work decomposition of k_step (one workgroup = one patch of cells, one thread =
 // one cell):
-//   * every global load is issued up front: patch-owned DOF data is a contiguous
-//     range (coalesced, kept in registers for the update), DOFs shared with
-//     neighbouring patches are gathered and finished from the previous step's
-//     partial sums in a fixed order, the patch's gather lists are staged in LDS;
+//   * every global load is issued up front.  A cell's interior DOFs (nodes inside
+//     the cell: their DOF belongs to it alone) sit at own_start + j*nc + t, so the
+//     thread of cell t loads them coalesced into registers and finishes them
+//     itself.  The patch's other owned DOFs are one contiguous range, staged in
+//     LDS; DOFs shared with neighbouring patches are finished from the previous
+//     step's partial sums in a fixed order and staged too;
 //   * per cell, the reference-gradient contraction at the nodal quadrature
 //     points, g_q = sum_b D[q][b] u_b, z_q = w_q c^2_q G_e g_q,
 //     y_a = sum_q D[q][a] . z_q (appendix, matrix K, with the KMV rule as the
 //     quadrature).  The tables are compile-time constants (instruction literals,
-//     zero entries dropped) and the contraction runs on the VALU;
-//   * deterministic assembly: every cell writes its n_d contributions to its own
-//     LDS slots, then each DOF sums its slots in a fixed (cell, node) order;
-//   * leapfrog + sponge for the DOFs only this patch touches (eq. forward3 with a
-//     diagonal leading matrix): du <- beta du - gamma (K u - b), u <- u + du.
+//     zero entries dropped) and the contraction runs on the VALU; the point
+//     sources of the cell enter the element vector;
+//   * deterministic assembly of the non-interior DOFs: each cell writes its
+//     contributions to its own LDS slots, then each DOF sums its slots in a fixed
+//     (cell, node) order, read from one 32-bit gather word (one or two slots) or
+//     a short list;
+//   * leapfrog + sponge (eq. forward3 with a diagonal leading matrix):
+//     du <- beta du - gamma (K u - b), u <- u + du.
 #include <hip/hip_ext.h>
 
 #include "kernels.hpp"
@@ -26,205 +31,301 @@ namespace kmv {
 
 __host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) / 16 * 16; }
 
-// LDS layout of k_step: su[L], sc[L], sx[cells*nd] (element type), then the
-// gather pointers gp[L+8] and entries ge[cells*nd+8] (uint16).
+// LDS layout of k_step (element type first): su, sc [and sf] hold the level,
+// c^2 [and the forward state] of the patch's non-interior DOFs; sx [and sr] the
+// cell-node contributions, slot b*CS + t for node b of cell t plus a zero slot;
+// then the gather lists (uint16).
 struct StepLds {
-  size_t gp, ge, total;
-  __host__ __device__ StepLds(int L, int cells, int nd, size_t ts) {
-    gp = align16((2 * (size_t)L + (size_t)cells * nd) * ts);
-    ge = gp + align16(((size_t)L + 8) * 2);
-    total = ge + align16(((size_t)cells * nd + 8) * 2);
+  size_t sx, gl, total;
+  __host__ __device__ StepLds(int LB, int cs, int nb, int glmax, bool adj, size_t ts) {
+    const size_t nslot = (size_t)nb * cs + 1;
+    sx = align16((size_t)(adj ? 3 : 2) * LB * ts);
+    gl = sx + align16((adj ? 2 : 1) * nslot * ts);
+    total = gl + align16((size_t)glmax * 2);
   }
 };
 
 // Items per thread whose global loads are issued together (latency hiding).
 template <typename T>
 struct Batch {
-  static constexpr int kOwned = sizeof(T) == 4 ? 16 : 8;    // owned items kept in registers
-  static constexpr int kUpdate = sizeof(T) == 4 ? 12 : 6;   // prefetched update operands
-  static constexpr int kShared = 2;                         // shared refs per pass
-  static constexpr int kList = 4;                           // 16-byte list words per pass
+  static constexpr int kOwned = sizeof(T) == 4 ? 5 : 2;   // owned non-interior DOFs in registers
+  static constexpr int kWords = sizeof(T) == 4 ? 6 : 4;   // gather words in registers
+  static constexpr int kShared = 2;                       // shared refs in the first batch
+  static constexpr int kList = 1;                         // 16-byte gather-list words
 };
+
+// Sum of the cell-node contributions of one local DOF, in its fixed slot order.
+template <typename T>
+__device__ __forceinline__ T gather_sum(uint32_t w, const T* x, const uint16_t* gl) {
+  const uint32_t lo = w & 0xFFFFu, hi = w >> 16;
+  if (hi != kGatherList) return x[lo] + x[hi];
+  const int k = gl[lo];
+  T y = x[gl[lo + 1]];
+  for (int q = 1; q < k; ++q) y += x[gl[lo + 1 + q]];
+  return y;
+}
 
 template <typename T, int DIM, int ND, bool ADJ>
 __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
-  using Tab = KmvTab<T, DIM, ND>;  // compile-time reference gradients and weights
+  using Tab = KmvTab<T, DIM, ND>;  // compile-time reference gradients, weights, node classes
+  constexpr int NI = Tab::NI, NB = Tab::NB;
+  constexpr int NIa = NI > 0 ? NI : 1, NBa = NB > 0 ? NB : 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int L = A.nloc_max;
-  const StepLds lay(L, A.cells_max, ND, sizeof(T));
-  T* su = reinterpret_cast<T*>(smem_raw);  // level n, then K u - b
-  T* sc = su + L;                          // c^2, then the gradient pairing (ADJ)
-  T* sx = sc + L;                          // cell-node contributions (shared u^m before, ADJ)
-  uint16_t* gp = reinterpret_cast<uint16_t*>(smem_raw + lay.gp);
-  uint16_t* ge = reinterpret_cast<uint16_t*>(smem_raw + lay.ge);
-  const int p = blockIdx.x, tid = threadIdx.x, bs = blockDim.x;
-  const int own0 = A.own_start[p], nown = A.own_start[p + 1] - own0;
+  const int LB = A.nbl_max, CS = A.slot_stride;
+  const StepLds lay(LB, CS, NB, A.glist_max, ADJ, sizeof(T));
+  T* su = reinterpret_cast<T*>(smem_raw);  // level n of the non-interior DOFs
+  T* sc = su + LB;                         // c^2
+  T* sf = sc + LB;                         // forward state u^m (ADJ)
+  T* sx = reinterpret_cast<T*>(smem_raw + lay.sx);  // K u - b per cell node
+  T* sr = sx + (NB * CS + 1);                       // gradient pairing per cell node (ADJ)
+  uint16_t* gl = reinterpret_cast<uint16_t*>(smem_raw + lay.gl);
+  const int tid = threadIdx.x, bs = blockDim.x;
+  // XCD-aware patch order: the dispatcher deals workgroups round-robin over the 8
+  // XCDs (separate L2 caches), so workgroup b runs on XCD b % 8.  Each XCD gets a
+  // contiguous run of patches: neighbouring patches, which exchange shared-DOF
+  // partials and read each other's levels, then mostly share one L2.
+  int p;
+  {
+    const int b = blockIdx.x, np = gridDim.x, x = b & 7, k = b >> 3;
+    const int base = np >> 3, rem = np & 7;
+    p = x * base + min(x, rem) + k;
+  }
+  const int c0 = A.cell_start[p], nc = A.cell_start[p + 1] - c0;
+  const int own0 = A.own_start[p], bo0 = own0 + NI * nc, nbo = A.own_start[p + 1] - bo0;
   const int sh0 = A.sh_start[p], nsh = A.sh_start[p + 1] - sh0;
-  const int nloc = nown + nsh;
+  const int nbl = nbo + nsh;
   const bool step = A.mode == 0;
 
-  // ---- every global load first
-  const int c0 = A.cell_start[p], c1 = A.cell_start[p + 1];
-  const int e = c0 + tid;
-  const bool active = e < c1;
-  constexpr int NG = DIM == 2 ? 3 : 6;
-  int m[ND];
-  T G[NG];
-  if (active) {
+  // ---- every global load first, as one straight run: indices of idle lanes are
+  // clamped into range instead of branched on (their values are never used), so
+  // nothing forces a wait until the loads are all in flight.  Loads complete in
+  // issue order; the index loads of the first shared refs go out first.
+  constexpr int KH = Batch<T>::kShared;
+  int gg[KH];
+  int2 sl[KH];
 #pragma unroll
-    for (int a = 0; a < ND; ++a) m[a] = A.lmap[(int64_t)a * A.n_cells + e];
-#pragma unroll
-    for (int k = 0; k < NG; ++k) G[k] = A.geom[(int64_t)k * A.n_cells + e];
+  for (int t = 0; t < KH; ++t) {
+    const int jc = sh0 + min(tid + t * bs, max(nsh - 1, 0));  // padded: always in range
+    gg[t] = A.sh_idx[jc];
+    sl[t] = reinterpret_cast<const int2*>(A.ref_slots)[jc];
   }
-  constexpr int KO = Batch<T>::kOwned;
-  T vu[KO], vc[KO];
-#pragma unroll
-  for (int k = 0; k < KO; ++k) {
-    const int i = tid + k * bs;
-    if (i < nown) {
-      vu[k] = A.u_in[own0 + i];
-      vc[k] = A.c2[own0 + i];
-    }
-  }
-  // update operands of the first owned items: in flight during the element work
   const bool damped = A.beta != nullptr && A.damp_patch[p] != 0;
-  constexpr int KU = Batch<T>::kUpdate;
-  T pdu[KU], pg[KU], pb[KU];
-  if (step) {
+  const T* bsrc = damped ? A.beta : A.gamma;  // any valid array when undamped
+  // their dependent loads (all pointers valid: without a previous level u_prev is
+  // u_in and the partial and increment buffers are allocated)
+  const T* usrc = A.prev ? A.u_prev : A.u_in;
+  T y0[KH], y1[KH], up[KH], dp[KH], gm[KH], bt[KH], cc[KH], ff[KH];
 #pragma unroll
-    for (int k = 0; k < KU; ++k) {
-      const int i = tid + k * bs;
-      if (i < nown) {
-        pdu[k] = A.du[own0 + i];
-        pg[k] = A.gamma[own0 + i];
-        pb[k] = damped ? A.beta[own0 + i] : T(1);
-      }
-    }
+  for (int t = 0; t < KH; ++t) {
+    const int g = gg[t];
+    const int64_t s = max(g - A.n_own, (int64_t)0);
+    y0[t] = A.part_prev[sl[t].x];
+    y1[t] = A.part_prev[sl[t].y >= 0 ? sl[t].y : sl[t].x];
+    cc[t] = A.c2[g];
+    if (ADJ) ff[t] = A.uf[g];
+    up[t] = usrc[g];
+    dp[t] = A.dsh_prev[s];
+    gm[t] = A.gamma[g];
+    bt[t] = bsrc[g];
   }
-  const int gpo = A.gl_ptr_off[p], gpn = (A.gl_ptr_off[p + 1] - gpo) / 8;
-  const int geo = A.gl_ent_off[p], gen = (A.gl_ent_off[p + 1] - geo) / 8;
-  const uint4* gsrc_p = reinterpret_cast<const uint4*>(A.gl_ptr + gpo);
-  const uint4* gsrc_e = reinterpret_cast<const uint4*>(A.gl_ent + geo);
+  // gather lists of the DOFs with more than two contributions
   constexpr int KL = Batch<T>::kList;
+  const int glo = A.glist_off[p], gln = (A.glist_off[p + 1] - glo) / 8;
+  const uint4* glsrc = reinterpret_cast<const uint4*>(A.glist + glo);
   uint4 lw[KL];
 #pragma unroll
-  for (int k = 0; k < KL; ++k) {
-    const int v = tid + k * bs;
-    const uint4* src = v < gpn ? gsrc_p + v : gsrc_e + (v - gpn);
-    lw[k] = v < gpn + gen ? *src : make_uint4(0, 0, 0, 0);
+  for (int k = 0; k < KL; ++k) lw[k] = glsrc[min(tid + k * bs, max(gln - 1, 0))];
+  // cell data and the cell's interior DOFs
+  const int tc = min(tid, nc - 1);
+  const int e = c0 + tc;
+  const bool active = tid < nc;
+  constexpr int NG = DIM == 2 ? 3 : 6;
+  constexpr int NB2 = (NB + 1) / 2;
+  uint32_t mp[NB2 > 0 ? NB2 : 1];
+  T G[NG];
+#pragma unroll
+  for (int q = 0; q < NB2; ++q) mp[q] = A.lmap[(int64_t)q * A.n_cells + e];
+#pragma unroll
+  for (int k = 0; k < NG; ++k) G[k] = A.geom[(int64_t)k * A.n_cells + e];
+  T ui[NIa], ci[NIa], di[NIa], gi[NIa], bi[NIa], fi[ADJ ? NIa : 1];
+  double ga[ADJ ? NIa : 1];  // gradient accumulator of the interior DOFs (read early)
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    const int gx = own0 + j * nc + tc;
+    ui[j] = A.u_in[gx];
+    ci[j] = A.c2[gx];
+    di[j] = A.du[gx];
+    gi[j] = A.gamma[gx];
+    bi[j] = bsrc[gx];
+    if (ADJ) {
+      fi[ADJ ? j : 0] = A.uf[gx];
+      ga[ADJ ? j : 0] = A.gacc[gx];
+    }
   }
-  // shared refs: level-1 loads (global id, inline partial slots) then level 2
-  constexpr int KH = Batch<T>::kShared;
-  for (int j0 = tid; j0 < nsh; j0 += KH * bs) {
-    int gg[KH];
-    int2 sl[KH];
+  // gather words of the first local DOFs of this thread
+  constexpr int KW = Batch<T>::kWords;
+  const uint32_t* gwp = A.gword + A.gword_off[p];
+  uint32_t gw[KW];
 #pragma unroll
-    for (int t = 0; t < KH; ++t) {
-      const int j = j0 + t * bs;
-      if (j < nsh) {
-        gg[t] = A.sh_idx[sh0 + j];
-        if (A.prev) sl[t] = reinterpret_cast<const int2*>(A.ref_slots)[sh0 + j];
-      }
+  for (int k = 0; k < KW; ++k) gw[k] = gwp[min(tid + k * bs, nbl - 1)];
+  // owned non-interior DOFs: level, c^2 [, u^m] and the update operands
+  constexpr int KO = Batch<T>::kOwned;
+  T vu[KO], vc[KO], vf[ADJ ? KO : 1], pdu[KO], pg[KO], pb[KO];
+#pragma unroll
+  for (int k = 0; k < KO; ++k) {
+    const int gx = max(bo0 + min(tid + k * bs, nbo - 1), 0);
+    vu[k] = A.u_in[gx];
+    vc[k] = A.c2[gx];
+    if (ADJ) vf[ADJ ? k : 0] = A.uf[gx];
+    pdu[k] = A.du[gx];
+    pg[k] = A.gamma[gx];
+    pb[k] = bsrc[gx];
+  }
+  if (!damped) {
+#pragma unroll
+    for (int j = 0; j < NI; ++j) bi[j] = T(1);
+#pragma unroll
+    for (int k = 0; k < KO; ++k) pb[k] = T(1);
+  }
+  int m[NBa];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) m[b] = (int)((mp[b / 2] >> (16 * (b & 1))) & 0xFFFFu);
+
+  // shared refs: finish the level from the previous step's partials
+  T uu[KH];
+#pragma unroll
+  for (int t = 0; t < KH; ++t) {
+    uu[t] = up[t];
+    if (!A.prev) continue;
+    const int j = tid + t * bs;
+    const int g = gg[t];
+    const int64_t s = max(g - A.n_own, (int64_t)0);
+    const bool pair = sl[t].y >= 0;  // else: three or more patches, CSR list
+    T y = y0[t] + y1[t];
+    if (!pair && j < nsh) {
+      y = T(0);
+      for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) y += A.part_prev[A.shp_slot[k]];
     }
-    T uu[KH], cc[KH], ff[KH];
-#pragma unroll
-    for (int t = 0; t < KH; ++t) {
-      const int j = j0 + t * bs;
-      if (j >= nsh) continue;
-      const int g = gg[t];
-      cc[t] = A.c2[g];
-      if (ADJ) ff[t] = A.uf[g];
-      if (A.prev) {
-        const int64_t s = g - A.n_own;
-        const bool pair = sl[t].y >= 0;  // else: three or more patches, CSR list
-        T y;
+    const T dn = (damped ? bt[t] : T(1)) * dp[t] - gm[t] * y;
+    uu[t] = up[t] + dn;
+    if (j < nsh && sl[t].x == sh0 + j) {  // the first touching patch stores the level
+      A.u_in_sh[g] = uu[t];
+      A.dsh_cur[s] = dn;
+      if (ADJ) {
+        T r;
         if (pair) {
-          y = A.part_prev[sl[t].x] + A.part_prev[sl[t].y];
+          r = A.partr_prev[sl[t].x] + A.partr_prev[sl[t].y];
         } else {
-          y = T(0);
-          for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) y += A.part_prev[A.shp_slot[k]];
+          r = T(0);
+          for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) r += A.partr_prev[A.shp_slot[k]];
         }
-        const T b = damped ? A.beta[g] : T(1);
-        const T dn = b * A.dsh_prev[s] - A.gamma[g] * y;
-        uu[t] = A.u_prev[g] + dn;
-        if (sl[t].x == sh0 + j) {  // the first touching patch stores the level
-          A.u_in_sh[g] = uu[t];
-          A.dsh_cur[s] = dn;
-          if (ADJ) {
-            T r;
-            if (pair) {
-              r = A.partr_prev[sl[t].x] + A.partr_prev[sl[t].y];
-            } else {
-              r = T(0);
-              for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) r += A.partr_prev[A.shp_slot[k]];
-            }
-            A.gacc[g] += (double)r;
-          }
-        }
-      } else {
-        uu[t] = A.u_in[g];
+        A.gacc[g] += (double)r;
       }
     }
+  }
 #pragma unroll
-    for (int t = 0; t < KH; ++t) {
-      const int j = j0 + t * bs;
-      if (j >= nsh) continue;
-      su[nown + j] = uu[t];
-      sc[nown + j] = cc[t];
-      if (ADJ) sx[j] = ff[t];
+  for (int t = 0; t < KH; ++t) {
+    const int j = tid + t * bs;
+    if (j >= nsh) continue;
+    su[nbo + j] = uu[t];
+    sc[nbo + j] = cc[t];
+    if (ADJ) sf[nbo + j] = ff[t];
+  }
+  // remaining shared refs (patches with more than KH * bs of them)
+  for (int j = tid + KH * bs; j < nsh; j += bs) {
+    const int g = A.sh_idx[sh0 + j];
+    const int64_t s = g - A.n_own;
+    T u, c, f = T(0);
+    c = A.c2[g];
+    if (ADJ) f = A.uf[g];
+    if (A.prev) {
+      const int2 sj = reinterpret_cast<const int2*>(A.ref_slots)[sh0 + j];
+      T y;
+      if (sj.y >= 0) {
+        y = A.part_prev[sj.x] + A.part_prev[sj.y];
+      } else {
+        y = T(0);
+        for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) y += A.part_prev[A.shp_slot[k]];
+      }
+      const T dn = (damped ? A.beta[g] : T(1)) * A.dsh_prev[s] - A.gamma[g] * y;
+      u = A.u_prev[g] + dn;
+      if (sj.x == sh0 + j) {
+        A.u_in_sh[g] = u;
+        A.dsh_cur[s] = dn;
+        if (ADJ) {
+          T r;
+          if (sj.y >= 0) {
+            r = A.partr_prev[sj.x] + A.partr_prev[sj.y];
+          } else {
+            r = T(0);
+            for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) r += A.partr_prev[A.shp_slot[k]];
+          }
+          A.gacc[g] += (double)r;
+        }
+      }
+    } else {
+      u = A.u_in[g];
     }
+    su[nbo + j] = u;
+    sc[nbo + j] = c;
+    if (ADJ) sf[nbo + j] = f;
+  }
+  {
+    uint4* gldst = reinterpret_cast<uint4*>(gl);
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+      const int v = tid + k * bs;
+      if (v < gln) gldst[v] = lw[k];
+    }
+    for (int v = tid + KL * bs; v < gln; v += bs) gldst[v] = glsrc[v];
   }
   // ---- the staged stores
 #pragma unroll
   for (int k = 0; k < KO; ++k) {
     const int i = tid + k * bs;
-    if (i < nown) {
+    if (i < nbo) {
       su[i] = vu[k];
       sc[i] = vc[k];
+      if (ADJ) sf[i] = vf[ADJ ? k : 0];
     }
   }
-  for (int i = tid + KO * bs; i < nown; i += bs) {
-    su[i] = A.u_in[own0 + i];
-    sc[i] = A.c2[own0 + i];
+  for (int i = tid + KO * bs; i < nbo; i += bs) {
+    su[i] = A.u_in[bo0 + i];
+    sc[i] = A.c2[bo0 + i];
+    if (ADJ) sf[i] = A.uf[bo0 + i];
   }
-  uint4* gdst_p = reinterpret_cast<uint4*>(gp);
-  uint4* gdst_e = reinterpret_cast<uint4*>(ge);
-#pragma unroll
-  for (int k = 0; k < KL; ++k) {
-    const int v = tid + k * bs;
-    uint4* dst = v < gpn ? gdst_p + v : gdst_e + (v - gpn);
-    if (v < gpn + gen) *dst = lw[k];
-  }
-  for (int v = tid + KL * bs; v < gpn + gen; v += bs) {
-    if (v < gpn) gdst_p[v] = gsrc_p[v];
-    else gdst_e[v - gpn] = gsrc_e[v - gpn];
+  if (tid == 0) {
+    sx[NB * CS] = T(0);
+    if (ADJ) sr[NB * CS] = T(0);
   }
   __syncthreads();
 
-  // receivers whose cell lies in this patch: d^n from the staged level
-  if (A.trace_row != nullptr) {
-    for (int r = A.rp_ptr[p] + tid; r < A.rp_ptr[p + 1]; r += bs) {
-      T s = T(0);
-      for (int a = 0; a < ND; ++a) s += A.rp_w[r * ND + a] * su[A.rp_loc[r * ND + a]];
-      A.trace_row[A.rp_rec[r]] = s;
-    }
-  }
-
-  // ---- element stiffness (and the gradient pairing) per cell
-  T ye[ND];
-  T re[ADJ ? ND : 1];
+  // ---- per cell: receivers, element stiffness (and pairing), sources, interior DOFs
   if (active) {
-    T ue[ND];
-    T fe[ADJ ? ND : 1];
+    T ue[ND], ce[ND], fe[ADJ ? ND : 1], ye[ND], re[ADJ ? ND : 1];
 #pragma unroll
     for (int a = 0; a < ND; ++a) {
-      ue[a] = su[m[a]];
+      const int x = Tab::IDX[a];
+      if (Tab::INT[a]) {
+        ue[a] = ui[x < NI ? x : 0];
+        ce[a] = ci[x < NI ? x : 0];
+        if (ADJ) fe[ADJ ? a : 0] = fi[ADJ && x < NI ? x : 0];
+      } else {
+        const int l = m[x < NB ? x : 0];
+        ue[a] = su[l];
+        ce[a] = sc[l];
+        if (ADJ) fe[ADJ ? a : 0] = sf[l];
+      }
       ye[a] = T(0);
     }
-    if (ADJ) {
-      // forward state u^m: owned nodes from global memory, shared ones staged
+    if (A.trace_row != nullptr) {
+      for (int r = A.rec_ptr[p]; r < A.rec_ptr[p + 1]; ++r)
+        if (A.rec_cell[r] == tid) {
+          T s = T(0);
 #pragma unroll
-      for (int a = 0; a < ND; ++a) fe[ADJ ? a : 0] = m[a] < nown ? A.uf[own0 + m[a]] : sx[m[a] - nown];
+          for (int a = 0; a < ND; ++a) s += A.rec_w[(int64_t)r * ND + a] * ue[a];
+          A.trace_row[A.rec_pt[r]] = s;
+        }
     }
 #pragma unroll
     for (int q = 0; q < ND; ++q) {
@@ -248,7 +349,7 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
         v[2] = G[2] * g[0] + G[4] * g[1] + G[5] * g[2];
       }
       const T wq = Tab::W[q];
-      const T cw = wq * sc[m[q]];
+      const T cw = wq * ce[q];
       T z[DIM];
 #pragma unroll
       for (int r = 0; r < DIM; ++r) z[r] = cw * v[r];
@@ -276,79 +377,88 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
         re[ADJ ? q : 0] = wq * s;
       }
     }
-  }
-  if (ADJ) __syncthreads();  // staged shared u^m is read; sx is free
-
-  // ---- deterministic assembly: own slots, then a fixed-order sum per DOF
-  if (active) {
+    // point sources in this cell: b enters the element vector as K u - b
+    if (A.inj_ptr != nullptr) {
+      for (int r = A.inj_ptr[p]; r < A.inj_ptr[p + 1]; ++r)
+        if (A.inj_cell[r] == tid) {
+          const T f = A.amp[(int64_t)A.inj_pt[r] * A.amp_stride] * A.amp_scale;
 #pragma unroll
-    for (int a = 0; a < ND; ++a) sx[(e - c0) * ND + a] = ye[a];
-  }
-  __syncthreads();
-#pragma unroll 4
-  for (int i = tid; i < nloc; i += bs) {
-    T y = T(0);
-    for (int k = gp[i]; k < gp[i + 1]; ++k) y += sx[ge[k]];
-    su[i] = y;
-  }
-  if (ADJ) {
-    __syncthreads();
-    if (active) {
-#pragma unroll
-      for (int a = 0; a < ND; ++a) sx[(e - c0) * ND + a] = re[ADJ ? a : 0];
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int i = tid; i < nloc; i += bs) {
-      T r = T(0);
-      for (int k = gp[i]; k < gp[i + 1]; ++k) r += sx[ge[k]];
-      sc[i] = r;
-    }
-  }
-  __syncthreads();
-
-  // point injection: one thread per target DOF, entries in a fixed order
-  if (A.grp_ptr != nullptr && A.grp_ptr[p] < A.grp_ptr[p + 1]) {
-    for (int gi = A.grp_ptr[p] + tid; gi < A.grp_ptr[p + 1]; gi += bs) {
-      T acc = T(0);
-      for (int k = A.grp_eptr[gi]; k < A.grp_eptr[gi + 1]; ++k) acc += A.ent_w[k] * A.amp[A.ent_pt[k]];
-      su[A.grp_local[gi]] -= acc * A.amp_scale;
-    }
-    __syncthreads();
-  }
-
-  if (!step) {
-    for (int i = tid; i < nown; i += bs) A.y_out[own0 + i] = su[i];
-  } else {
-#pragma unroll
-    for (int k = 0; k < KO; ++k) {
-      const int i = tid + k * bs;
-      if (i < nown) {
-        const int gi = own0 + i;
-        T dn;
-        if (k < KU) {
-          dn = pb[k < KU ? k : 0] * pdu[k < KU ? k : 0] - pg[k < KU ? k : 0] * su[i];
-        } else {
-          const T b = damped ? A.beta[gi] : T(1);
-          dn = b * A.du[gi] - A.gamma[gi] * su[i];
+          for (int a = 0; a < ND; ++a) ye[a] -= f * A.inj_w[(int64_t)r * ND + a];
         }
-        A.du[gi] = dn;
-        A.u_out[gi] = vu[k] + dn;
-        if (ADJ) A.gacc[gi] += (double)sc[i];
+    }
+    // interior DOFs are complete: finish them here
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
+      if (!Tab::INT[a]) continue;
+      const int j = Tab::IDX[a] < NI ? Tab::IDX[a] : 0;
+      const int gx = own0 + j * nc + tid;
+      if (step) {
+        const T dn = bi[j] * di[j] - gi[j] * ye[a];
+        A.du[gx] = dn;
+        A.u_out[gx] = ui[j] + dn;
+        if (ADJ) A.gacc[gx] = ga[ADJ ? j : 0] + (double)re[ADJ ? a : 0];
+      } else {
+        A.y_out[gx] = ye[a];
       }
     }
-    for (int i = tid + KO * bs; i < nown; i += bs) {
-      const int gi = own0 + i;
-      const T b = damped ? A.beta[gi] : T(1);
-      const T dn = b * A.du[gi] - A.gamma[gi] * su[i];
-      A.du[gi] = dn;
-      A.u_out[gi] = A.u_in[gi] + dn;
-      if (ADJ) A.gacc[gi] += (double)sc[i];
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
+      if (Tab::INT[a]) continue;
+      const int b = Tab::IDX[a];
+      sx[b * CS + tid] = ye[a];
+      if (ADJ) sr[b * CS + tid] = re[ADJ ? a : 0];
     }
   }
-  for (int j = tid; j < nsh; j += bs) {
-    A.part_cur[sh0 + j] = su[nown + j];
-    if (ADJ) A.partr_cur[sh0 + j] = sc[nown + j];
+  __syncthreads();
+
+  // ---- non-interior DOFs: fixed-order sums of their slots
+#pragma unroll
+  for (int k = 0; k < KW; ++k) {
+    const int l = tid + k * bs;
+    if (l >= nbl) continue;
+    const T y = gather_sum(gw[k], sx, gl);
+    const T r = ADJ ? gather_sum(gw[k], sr, gl) : T(0);
+    if (l < nbo) {
+      const int gx = bo0 + l;
+      if (!step) {
+        A.y_out[gx] = y;
+      } else {
+        T dn, un;
+        if (k < KO) {
+          const int kk = k < KO ? k : 0;
+          dn = pb[kk] * pdu[kk] - pg[kk] * y;
+          un = vu[kk];
+        } else {
+          dn = (damped ? A.beta[gx] : T(1)) * A.du[gx] - A.gamma[gx] * y;
+          un = su[l];
+        }
+        A.du[gx] = dn;
+        A.u_out[gx] = un + dn;
+        if (ADJ) A.gacc[gx] += (double)r;
+      }
+    } else {
+      A.part_cur[sh0 + l - nbo] = y;
+      if (ADJ) A.partr_cur[sh0 + l - nbo] = r;
+    }
+  }
+  for (int l = tid + KW * bs; l < nbl; l += bs) {
+    const uint32_t w = gwp[l];
+    const T y = gather_sum(w, sx, gl);
+    const T r = ADJ ? gather_sum(w, sr, gl) : T(0);
+    if (l < nbo) {
+      const int gx = bo0 + l;
+      if (!step) {
+        A.y_out[gx] = y;
+      } else {
+        const T dn = (damped ? A.beta[gx] : T(1)) * A.du[gx] - A.gamma[gx] * y;
+        A.du[gx] = dn;
+        A.u_out[gx] = su[l] + dn;
+        if (ADJ) A.gacc[gx] += (double)r;
+      }
+    } else {
+      A.part_cur[sh0 + l - nbo] = y;
+      if (ADJ) A.partr_cur[sh0 + l - nbo] = r;
+    }
   }
 }
 
@@ -495,7 +605,7 @@ void launch_ev(K kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, hip
 template <typename T, int DIM, int ND, bool ADJ>
 hipError_t launch_step_t(const StepArgs<T>& a, int np, int block, hipStream_t s, hipEvent_t e0,
                          hipEvent_t e1) {
-  const size_t lds = StepLds(a.nloc_max, a.cells_max, ND, sizeof(T)).total;
+  const size_t lds = StepLds(a.nbl_max, a.slot_stride, KmvTab<T, DIM, ND>::NB, a.glist_max, ADJ, sizeof(T)).total;
   launch_ev(k_step<T, DIM, ND, ADJ>, dim3(np), dim3(block), (uint32_t)lds, s, e0, e1, a);
   return hipGetLastError();
 }
@@ -520,8 +630,8 @@ hipError_t set_lds_t(int bytes) {
   }
 }  // namespace
 
-size_t step_lds_bytes(int nloc_max, int cells_max, int nd, size_t elem_size) {
-  return StepLds(nloc_max, cells_max, nd, elem_size).total;
+size_t step_lds_bytes(int nbl_max, int slot_stride, int nb, int glist_max, bool adjoint, size_t elem_size) {
+  return StepLds(nbl_max, slot_stride, nb, glist_max, adjoint, elem_size).total;
 }
 
 template <typename T>

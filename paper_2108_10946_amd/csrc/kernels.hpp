@@ -6,42 +6,44 @@
 
 namespace kmv {
 
-constexpr int kColStride = 65;  // colour_start row stride (max colours + 1)
-constexpr int kRefStride = 2;   // inline partial slots per shared ref
+constexpr int kRefStride = 2;          // inline partial slots per shared ref
+constexpr uint32_t kGatherList = 0xFFFFu;  // high half of a gather word that points into a list
 
 // Arguments of the fused step kernel.  One workgroup processes one patch of cells
-// per time step:
+// per time step, one thread per cell:
 //   1. it finishes the DOFs it shares with other patches for the current level:
 //      their K u of the previous step is the fixed-order sum of the patches'
 //      partials, and every touching patch repeats the same arithmetic, so all
 //      copies agree bit for bit; the first touching patch stores the result;
-//   2. it stages the patch's values in LDS (owned DOFs are a contiguous range);
-//   3. it samples the receivers whose cell lies in the patch;
-//   4. it applies the element stiffness of its cells; each cell writes its own
-//      LDS slots and each DOF sums its slots in a fixed order (deterministic);
-//   5. it adds the point sources of the DOFs it is designated for;
-//   6. it finishes the leapfrog update (or writes y = K u) of the DOFs only it
-//      touches and writes its partial sums of the shared ones.
-// The adjoint variant also gathers the forward state u^m and accumulates the
+//   2. it stages the level of the patch's non-interior DOFs in LDS (the owned
+//      ones are a contiguous range); each thread loads its cell's interior DOFs
+//      straight into registers;
+//   3. each thread samples the receivers in its cell, applies its element
+//      stiffness, subtracts the point sources in its cell and finishes its
+//      interior DOFs (leapfrog update, or y = K u);
+//   4. the non-interior contributions go to per-cell LDS slots and each DOF sums
+//      its slots in a fixed order (deterministic); owned DOFs are updated, shared
+//      ones write this patch's partial sum.
+// The adjoint variant also stages the forward state u^m and accumulates the
 // gradient pairing in float64.
 template <typename T>
 struct StepArgs {
   // mesh
-  const uint16_t* lmap;        // [nd * n_cells] patch-local DOF of node a of cell e
+  const uint32_t* lmap;        // [ceil(nb/2) * n_cells] local non-interior DOFs of nodes 2q, 2q+1 of cell e
   const T* geom;               // [ng * n_cells] |det J| J^-1 J^-T (upper triangle)
   const int32_t* cell_start;   // [np+1]
-  const int32_t* own_start;    // [np+1]
+  const int32_t* own_start;    // [np+1] interior DOFs, then the other owned DOFs
   const int32_t* sh_start;     // [np+1]
-  const int32_t* sh_idx;       // [n_shared_refs] global id of each shared ref
-  const uint16_t* gl_ptr;      // gather pointers per patch (16-byte aligned regions)
-  const uint16_t* gl_ent;      // gather entries per patch (16-byte aligned regions)
-  const int32_t* gl_ptr_off;   // [np+1]
-  const int32_t* gl_ent_off;   // [np+1]
+  const int32_t* sh_idx;       // [n_shared_refs + 1] global id of each shared ref (+ padding)
+  const uint32_t* gword;       // gather word per local non-interior DOF, per patch
+  const int32_t* gword_off;    // [np+1]
+  const uint16_t* glist;       // gather lists of DOFs with more than two slots (8-aligned regions, + 8 padding)
+  const int32_t* glist_off;    // [np+1]
   const int32_t* shp_ptr;      // [n_shared+1] partial slots of each shared DOF
   const int32_t* shp_slot;     // [n_shared_refs], in patch order
-  const int32_t* ref_slots;    // [n_shared_refs*kRefStride] the same lists per ref, -1 padded
-  int64_t n_cells, n_own;
-  int nloc_max, cells_max;     // LDS sizing
+  const int32_t* ref_slots;    // [(n_shared_refs+1)*kRefStride] {first, second} or {first, -count}
+  int64_t n_cells, n_own, n_dofs;
+  int nbl_max, slot_stride, glist_max;  // LDS sizing; cell-node slot = b*slot_stride + t
   int mode;                    // 0: leapfrog step, 1: y = K u
   int prev;                    // 1: shared DOFs of this level are finished here
   // state (level n -> n+1; the adjoint runs the same recursion backwards)
@@ -59,19 +61,19 @@ struct StepArgs {
   const T* beta;               // (1-a)/(1+a), or nullptr (no damping)
   const int32_t* damp_patch;   // [np] 1 if a DOF of the patch is damped (beta read only there)
   T* y_out;                    // mode 1
-  // point injection: groups of entries per patch, one group per local DOF
-  const int32_t* grp_ptr;      // [np+1] or nullptr
-  const int32_t* grp_local;
-  const int32_t* grp_eptr;
-  const int32_t* ent_pt;       // amplitude index of each entry
-  const T* ent_w;              // phi_a(x_point)
-  const T* amp;                // amplitudes (wavelet sample or adjoint data row)
+  // point sources: entries (cell, point, phi_a(x_point) per node) per patch
+  const int32_t* inj_ptr;      // [np+1] or nullptr
+  const int32_t* inj_cell;     // patch-local cell of the entry
+  const int32_t* inj_pt;       // point index
+  const T* inj_w;              // [n*nd]
+  const T* amp;                // amplitude of point j: amp[j * amp_stride]
+  int amp_stride;
   T amp_scale;
-  // receivers sampled from LDS (level n), per patch
-  const int32_t* rp_ptr;       // [np+1]
-  const int32_t* rp_rec;       // receiver index
-  const uint16_t* rp_loc;      // [n*nd] patch-local DOFs
-  const T* rp_w;               // [n*nd] phi_a(x_r)
+  // receivers sampled from level n, entries as for the sources
+  const int32_t* rec_ptr;
+  const int32_t* rec_cell;
+  const int32_t* rec_pt;
+  const T* rec_w;
   T* trace_row;                // d^n row, or nullptr
   // adjoint + gradient
   const T* uf;                 // forward state u^m
@@ -105,7 +107,7 @@ template <typename T>
 hipError_t launch_step(int dim, int nd, bool adjoint, const StepArgs<T>& a, int n_patches, int block,
                        hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Dynamic LDS bytes of one k_step workgroup.
-size_t step_lds_bytes(int nloc_max, int cells_max, int nd, size_t elem_size);
+size_t step_lds_bytes(int nbl_max, int slot_stride, int nb, int glist_max, bool adjoint, size_t elem_size);
 template <typename T>
 hipError_t launch_finish(bool adjoint, const FinishArgs<T>& a, hipStream_t s, hipEvent_t e0 = nullptr,
                          hipEvent_t e1 = nullptr);

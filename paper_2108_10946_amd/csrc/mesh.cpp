@@ -1,6 +1,6 @@
 // Mesh preprocessing (host): topological DOF numbering, geometry, lumped mass,
-// recursive-coordinate-bisection patches, in-patch colouring, owned/shared DOF
-// split and patch-local maps for the GPU kernels.
+// recursive-coordinate-bisection patches, the owned/shared DOF split, the
+// interior-DOF layout and the patch-local gather words of the GPU kernels.
 #include "mesh.hpp"
 
 #include <algorithm>
@@ -220,11 +220,13 @@ Mesh* build_mesh(int dim, int degree, const double* coords, int64_t nv, const in
 
   // ---- patches by recursive coordinate bisection
   if (patch_cells <= 0) {
-    double dofs_per_cell = dim == 2 ? 0.5 + 1.5 * el.n_edge + el.n_cell
-                                    : 1.0 / 6.0 + 7.0 / 6.0 * el.n_edge + 2.0 * el.n_face + el.n_cell;
-    int P = (int)(2048.0 / (dofs_per_cell * 1.25));
+    // LDS holds the patch's non-interior DOFs and its cells' non-interior slots:
+    // aim at about 4096 such DOFs, at most 256 cells (4 waves) per patch
+    const double nonint_per_cell = dim == 2 ? 0.5 + 1.5 * el.n_edge
+                                            : 1.0 / 6.0 + 7.0 / 6.0 * el.n_edge + 2.0 * el.n_face;
+    int P = (int)(4096.0 / (std::max(nonint_per_cell, 1.0) * 1.25));
     P = (P / 64) * 64;
-    patch_cells = std::max(64, std::min(512, P));
+    patch_cells = std::max(64, std::min(256, P));
   }
   m->patch_cells = patch_cells;
   std::vector<int64_t> order(ne);
@@ -235,45 +237,23 @@ Mesh* build_mesh(int dim, int degree, const double* coords, int64_t nv, const in
   const int64_t np = (int64_t)leaf_start.size() - 1;
   m->n_patches = np;
 
-  // ---- colour cells inside each patch (no two same-colour cells share a DOF)
-  std::vector<uint64_t> dof_mask(ndof, 0);
-  std::vector<int> colour(ne, -1);
-  m->patch_ncol.assign(np, 0);
-  for (int64_t p = 0; p < np; ++p) {
-    int ncol = 0;
-    for (int64_t i = leaf_start[p]; i < leaf_start[p + 1]; ++i) {
-      const int64_t c = order[i];
-      uint64_t forbid = 0;
-      for (int q = 0; q < nd; ++q) forbid |= dof_mask[cdof0[c * nd + q]];
-      if (forbid == ~0ull) {
-          throw MeshError{"more than 64 colours needed inside a patch"};
-      }
-      int col = __builtin_ctzll(~forbid);
-      colour[c] = col;
-      ncol = std::max(ncol, col + 1);
-      for (int q = 0; q < nd; ++q) dof_mask[cdof0[c * nd + q]] |= 1ull << col;
-    }
-    for (int64_t i = leaf_start[p]; i < leaf_start[p + 1]; ++i) {
-      const int64_t c = order[i];
-      for (int q = 0; q < nd; ++q) dof_mask[cdof0[c * nd + q]] = 0;
-    }
-    std::stable_sort(order.begin() + leaf_start[p], order.begin() + leaf_start[p + 1],
-                     [&](int64_t x, int64_t y) { return colour[x] < colour[y]; });
-    m->patch_ncol[p] = ncol;
-    m->max_colours = std::max(m->max_colours, ncol);
-  }
   m->cell_input = order;
+  for (int q = 0; q < nd; ++q) (el.entity[q] == ENT_CELL ? m->int_nodes : m->bnd_nodes).push_back(q);
+  const int ni = (int)m->int_nodes.size(), nb = (int)m->bnd_nodes.size();
+  m->ni = ni;
+  m->nb = nb;
 
   // ---- owned / shared classification
-  std::vector<int32_t> last(ndof, -1), npat(ndof, 0), first_patch(ndof, -1);
+  std::vector<int32_t> last(ndof, -1), npat(ndof, 0), ncell_of(ndof, 0);
   for (int64_t p = 0; p < np; ++p)
     for (int64_t i = leaf_start[p]; i < leaf_start[p + 1]; ++i) {
       const int64_t c = order[i];
       for (int q = 0; q < nd; ++q) {
         const int64_t g = cdof0[c * nd + q];
+        ncell_of[g]++;
         if (last[g] != p) {
           last[g] = (int32_t)p;
-          if (npat[g]++ == 0) first_patch[g] = (int32_t)p;
+          npat[g]++;
         }
       }
     }
@@ -282,13 +262,19 @@ Mesh* build_mesh(int dim, int degree, const double* coords, int64_t nv, const in
   m->patch_own_start.assign(np + 1, 0);
   for (int64_t p = 0; p < np; ++p) {
     m->patch_own_start[p] = (int32_t)next;
-    for (int64_t i = leaf_start[p]; i < leaf_start[p + 1]; ++i) {
-      const int64_t c = order[i];
-      for (int q = 0; q < nd; ++q) {
-        const int64_t g = cdof0[c * nd + q];
-        if (npat[g] == 1 && newid[g] < 0) newid[g] = next++;
-      }
-    }
+    const int64_t c0 = leaf_start[p], nc = leaf_start[p + 1] - c0;
+    // interior DOFs: node j of the patch's t-th cell at next + j*nc + t
+    for (int64_t t = 0; t < nc; ++t)
+      for (int j = 0; j < ni; ++j) newid[cdof0[order[c0 + t] * nd + m->int_nodes[j]]] = next + j * nc + t;
+    next += (int64_t)ni * nc;
+    // the other owned DOFs: those with one or two cells first, then the rest,
+    // each group in first-touch order
+    for (int pass = 0; pass < 2; ++pass)
+      for (int64_t t = 0; t < nc; ++t)
+        for (int b = 0; b < nb; ++b) {
+          const int64_t g = cdof0[order[c0 + t] * nd + m->bnd_nodes[b]];
+          if (npat[g] == 1 && newid[g] < 0 && (ncell_of[g] > 2) == (pass == 1)) newid[g] = next++;
+        }
   }
   m->patch_own_start[np] = (int32_t)next;
   m->n_own_total = next;
@@ -305,11 +291,6 @@ Mesh* build_mesh(int dim, int degree, const double* coords, int64_t nv, const in
   }
   m->n_dofs = ndof;
   m->n_shared = ndof - m->n_own_total;
-  {
-    std::vector<int32_t> fp(ndof);
-    for (int64_t g = 0; g < ndof; ++g) fp[newid[g]] = first_patch[g];
-    first_patch.swap(fp);
-  }
   if (ndof >= (int64_t)1 << 31) {
     throw std::invalid_argument("more than 2^31 DOFs");
   }
@@ -356,91 +337,91 @@ Mesh* build_mesh(int dim, int degree, const double* coords, int64_t nv, const in
       }
     }
 
-  // ---- patch-local maps
+  // ---- patch-local maps of the non-interior DOFs and their gather words
   m->patch_cell_start.assign(leaf_start.begin(), leaf_start.end());
   m->patch_sh_start.assign(np + 1, 0);
-  m->colour_start.assign(np * (kMaxColours + 1), 0);
-  m->lmap.assign((size_t)nd * ne, 0);
-  m->dof_patch.assign(ndof, -1);
-  m->dof_local.assign(ndof, -1);
-  std::vector<int32_t> loc(ndof, -1);
+  m->lmap.assign((size_t)nb * ne, 0);
+  for (int64_t p = 0; p < np; ++p)
+    m->max_patch_cells = std::max(m->max_patch_cells, (int)(leaf_start[p + 1] - leaf_start[p]));
+  m->slot_stride = m->max_patch_cells;
+  if ((int64_t)nb * m->slot_stride + 1 >= (int64_t)kListMark) {
+    throw std::invalid_argument("patch too large for 16-bit cell-node slots");
+  }
+  const uint32_t zslot = (uint32_t)(nb * m->slot_stride);
+  m->gword_off.assign(np + 1, 0);
+  m->glist_off.assign(np + 1, 0);
+  std::vector<int32_t> loc(ndof, -1), pc(ndof, 0);
   std::vector<int32_t> sh_list;
   for (int64_t p = 0; p < np; ++p) {
     m->patch_sh_start[p] = (int32_t)sh_list.size();
-    const int32_t own0 = m->patch_own_start[p];
-    const int32_t nown = m->patch_own_start[p + 1] - own0;
-    int32_t nsh = 0;
-    std::vector<int32_t> touched;
-    // colour boundaries
-    int32_t* cs = &m->colour_start[p * (kMaxColours + 1)];
-    for (int col = 0; col <= kMaxColours; ++col) cs[col] = (int32_t)leaf_start[p + 1];
-    for (int64_t i = leaf_start[p + 1] - 1; i >= leaf_start[p]; --i) cs[colour[order[i]]] = (int32_t)i;
-    for (int col = m->patch_ncol[p] - 1; col >= 0; --col)
-      if (cs[col] > cs[col + 1]) cs[col] = cs[col + 1];
-    for (int64_t i = leaf_start[p]; i < leaf_start[p + 1]; ++i)
-      for (int q = 0; q < nd; ++q) {
-        const int64_t g = m->cell_dofs[i * nd + q];
-        if (loc[g] < 0) {
-          if (g < m->n_own_total) {
-            loc[g] = (int32_t)(g - own0);
-          } else {
-            loc[g] = nown + nsh++;
-            sh_list.push_back((int32_t)g);
-          }
+    const int32_t c0 = (int32_t)leaf_start[p], nc = (int32_t)(leaf_start[p + 1] - c0);
+    const int32_t bo0 = m->patch_own_start[p] + ni * nc;
+    const int32_t nbo = m->patch_own_start[p + 1] - bo0;
+    // shared refs in first-touch order, those with one or two cells here first
+    std::vector<int32_t> refs, touched;
+    for (int32_t t = 0; t < nc; ++t)
+      for (int b = 0; b < nb; ++b) {
+        const int64_t g = m->cell_dofs[(int64_t)(c0 + t) * nd + m->bnd_nodes[b]];
+        if (pc[g]++ == 0) {
           touched.push_back((int32_t)g);
+          if (g >= m->n_own_total) refs.push_back((int32_t)g);
         }
-        m->lmap[(size_t)q * ne + i] = (uint16_t)loc[g];
       }
-    const int nloc = nown + nsh;
-    if (nloc > 65535) {
+    std::stable_sort(refs.begin(), refs.end(), [&](int32_t x, int32_t y) { return (pc[x] > 2) < (pc[y] > 2); });
+    for (int32_t g : touched) loc[g] = g < m->n_own_total ? g - bo0 : -1;
+    for (size_t j = 0; j < refs.size(); ++j) {
+      loc[refs[j]] = nbo + (int32_t)j;
+      sh_list.push_back(refs[j]);
+    }
+    const int32_t nbl = nbo + (int32_t)refs.size();
+    if (nbl > 65535) {
       throw std::invalid_argument("patch too large for 16-bit local indices");
     }
-    m->max_nloc = std::max(m->max_nloc, nloc);
-    m->max_patch_cells = std::max(m->max_patch_cells, (int)(leaf_start[p + 1] - leaf_start[p]));
-    for (int32_t g : touched) {
-      if (first_patch[g] == p) {  // owner patch of an owned DOF, or first of a shared one
-        m->dof_patch[g] = (int32_t)p;
-        m->dof_local[g] = loc[g];
+    m->max_nbl = std::max(m->max_nbl, (int)nbl);
+    // slots of every local DOF in (cell, node) order
+    std::vector<int32_t> cnt(nbl + 1, 0);
+    for (int32_t t = 0; t < nc; ++t)
+      for (int b = 0; b < nb; ++b) {
+        const int64_t g = m->cell_dofs[(int64_t)(c0 + t) * nd + m->bnd_nodes[b]];
+        const int32_t l = loc[g];
+        if (l < 0 || l >= nbl) throw std::logic_error("local DOF index out of range");
+        m->lmap[(size_t)b * ne + c0 + t] = (uint16_t)l;
+        cnt[l + 1]++;
       }
+    for (int32_t l = 0; l < nbl; ++l) cnt[l + 1] += cnt[l];
+    std::vector<uint16_t> slots(cnt[nbl]);
+    {
+      std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+      for (int32_t t = 0; t < nc; ++t)
+        for (int b = 0; b < nb; ++b) {
+          const int32_t l = m->lmap[(size_t)b * ne + c0 + t];
+          slots[fill[l]++] = (uint16_t)(b * m->slot_stride + t);
+        }
+    }
+    const size_t list0 = m->glist.size();
+    for (int32_t l = 0; l < nbl; ++l) {
+      const int32_t k = cnt[l + 1] - cnt[l];
+      if (k <= 0) throw std::logic_error("local DOF without a contributing cell");
+      if (k <= 2) {
+        const uint32_t s1 = k == 2 ? slots[cnt[l] + 1] : zslot;
+        m->gword.push_back((uint32_t)slots[cnt[l]] | (s1 << 16));
+      } else {
+        const size_t off = m->glist.size() - list0;
+        if (off > 0xFFFE || k > 0xFFFF) throw std::invalid_argument("patch gather list too long");
+        m->gword.push_back((uint32_t)off | (kListMark << 16));
+        m->glist.push_back((uint16_t)k);
+        for (int32_t q = cnt[l]; q < cnt[l + 1]; ++q) m->glist.push_back(slots[q]);
+      }
+    }
+    while (m->glist.size() % 8) m->glist.push_back(0);
+    m->gword_off[p + 1] = (int32_t)m->gword.size();
+    m->glist_off[p + 1] = (int32_t)m->glist.size();
+    m->max_glist = std::max(m->max_glist, m->glist_off[p + 1] - m->glist_off[p]);
+    for (int32_t g : touched) {
+      pc[g] = 0;
       loc[g] = -1;
     }
   }
-  // gather lists (inverse of lmap per patch), entries in (cell, node) order
-  if ((int64_t)m->max_patch_cells * nd > 65535) throw std::invalid_argument("patch too large for 16-bit slots");
-  m->gl_ptr_off.assign(np + 1, 0);
-  m->gl_ent_off.assign(np + 1, 0);
-  auto pad8 = [](int64_t x) { return (x + 7) / 8 * 8; };
-  for (int64_t p = 0; p < np; ++p) {
-    const int32_t nloc = (m->patch_own_start[p + 1] - m->patch_own_start[p]) +
-                         ((p + 1 < np ? m->patch_sh_start[p + 1] : (int32_t)sh_list.size()) - m->patch_sh_start[p]);
-    m->gl_ptr_off[p + 1] = (int32_t)(m->gl_ptr_off[p] + pad8(nloc + 1));
-    m->gl_ent_off[p + 1] = (int32_t)(m->gl_ent_off[p] + pad8((leaf_start[p + 1] - leaf_start[p]) * nd));
-  }
-  m->gl_ptr.assign(m->gl_ptr_off[np], 0);
-  m->gl_ent.assign(m->gl_ent_off[np], 0);
-  for (int64_t p = 0; p < np; ++p) {
-    const int32_t c0 = (int32_t)leaf_start[p], c1 = (int32_t)leaf_start[p + 1];
-    const int32_t nloc = (m->patch_own_start[p + 1] - m->patch_own_start[p]) +
-                         ((p + 1 < np ? m->patch_sh_start[p + 1] : (int32_t)sh_list.size()) - m->patch_sh_start[p]);
-    uint16_t* gp = &m->gl_ptr[m->gl_ptr_off[p]];
-    uint16_t* ge = &m->gl_ent[m->gl_ent_off[p]];
-    std::vector<int32_t> cnt(nloc + 1, 0);
-    for (int32_t e = c0; e < c1; ++e)
-      for (int a = 0; a < nd; ++a) cnt[m->lmap[(size_t)a * ne + e] + 1]++;
-    for (int32_t i = 0; i < nloc; ++i) cnt[i + 1] += cnt[i];
-    for (int32_t i = 0; i <= nloc; ++i) gp[i] = (uint16_t)cnt[i];
-    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
-    for (int32_t e = c0; e < c1; ++e)
-      for (int a = 0; a < nd; ++a) {
-        const int li = m->lmap[(size_t)a * ne + e];
-        ge[fill[li]++] = (uint16_t)((e - c0) * nd + a);
-      }
-  }
-  // designated patch of a shared DOF: the first patch touching it
-  for (int64_t g = 0; g < ndof; ++g)
-    if (m->dof_patch[g] < 0) {
-      throw std::logic_error("DOF without a designated patch");
-    }
   m->patch_sh_start[np] = (int32_t)sh_list.size();
   m->sh_idx = sh_list;
   m->n_shared_refs = (int64_t)sh_list.size();
@@ -625,60 +606,94 @@ double gershgorin_rho(const Mesh& m, const double* c) {
 }
 
 bool validate_mesh(const Mesh& m, std::string& why) {
-  const int nd = m.nd;
+  const int nd = m.nd, ni = m.ni, nb = m.nb;
   const int64_t ne = m.n_cells, N = m.n_dofs;
   for (int64_t g = 0; g < N; ++g)
     if (!(m.mass[g] > 0)) {
       why = "non-positive lumped mass at DOF " + std::to_string(g);
       return false;
     }
-  std::vector<int64_t> stamp(N, -1), lastp(N, -1), npatch(N, 0);
-  int64_t st = 0;
+  if ((int)m.int_nodes.size() != ni || (int)m.bnd_nodes.size() != nb || ni + nb != nd) {
+    why = "node classes do not cover the element";
+    return false;
+  }
+  const int64_t cs = m.slot_stride, zslot = (int64_t)nb * cs;
+  std::vector<int64_t> lastp(N, -1), npatch(N, 0);
   for (int64_t p = 0; p < m.n_patches; ++p) {
-    const int32_t c0 = m.patch_cell_start[p], c1 = m.patch_cell_start[p + 1];
-    const int32_t own0 = m.patch_own_start[p], nown = m.patch_own_start[p + 1] - own0;
+    const int32_t c0 = m.patch_cell_start[p], nc = m.patch_cell_start[p + 1] - c0;
+    const int32_t own0 = m.patch_own_start[p], bo0 = own0 + ni * nc;
+    const int32_t nbo = m.patch_own_start[p + 1] - bo0;
     const int32_t sh0 = m.patch_sh_start[p], nsh = m.patch_sh_start[p + 1] - sh0;
-    const int32_t* cs = &m.colour_start[p * (kMaxColours + 1)];
-    const int ncol = m.patch_ncol[p];
-    if (cs[0] != c0 || cs[ncol] != c1) {
-      why = "colour ranges do not cover patch " + std::to_string(p);
+    const int32_t nbl = nbo + nsh;
+    if (nc <= 0 || nc > cs || nbo < 0 || nbl > m.max_nbl || m.gword_off[p + 1] - m.gword_off[p] != nbl) {
+      why = "patch " + std::to_string(p) + " has inconsistent ranges";
       return false;
     }
-    for (int c = 0; c < ncol; ++c) {
-      if (cs[c] > cs[c + 1]) {
-        why = "colour ranges out of order";
-        return false;
-      }
-      ++st;
-      for (int32_t e = cs[c]; e < cs[c + 1]; ++e)
-        for (int a = 0; a < nd; ++a) {
-          const int64_t g = m.cell_dofs[e * nd + a];
-          if (stamp[g] == st) {
-            why = "two cells of colour " + std::to_string(c) + " in patch " + std::to_string(p) +
-                  " share DOF " + std::to_string(g);
-            return false;
-          }
-          stamp[g] = st;
+    for (int32_t t = 0; t < nc; ++t) {
+      const int64_t e = c0 + t;
+      for (int j = 0; j < ni; ++j)
+        if (m.cell_dofs[e * nd + m.int_nodes[j]] != own0 + (int64_t)j * nc + t) {
+          why = "interior DOF of cell " + std::to_string(e) + " is not at its implicit position";
+          return false;
         }
-    }
-    for (int32_t e = c0; e < c1; ++e)
-      for (int a = 0; a < nd; ++a) {
-        const int64_t g = m.cell_dofs[e * nd + a];
-        const int loc = m.lmap[(size_t)a * ne + e];
-        if (loc < nown) {
-          if (g != own0 + loc) {
+      for (int b = 0; b < nb; ++b) {
+        const int64_t g = m.cell_dofs[e * nd + m.bnd_nodes[b]];
+        const int l = m.lmap[(size_t)b * ne + e];
+        if (l < nbo) {
+          if (g != bo0 + l) {
             why = "owned local index does not match the DOF map";
             return false;
           }
-        } else if (loc - nown >= nsh || m.sh_idx[sh0 + loc - nown] != g) {
+        } else if (l >= nbl || m.sh_idx[sh0 + l - nbo] != g) {
           why = "shared local index does not match the DOF map";
           return false;
         }
+      }
+      for (int a = 0; a < nd; ++a) {
+        const int64_t g = m.cell_dofs[e * nd + a];
         if (lastp[g] != p) {
           lastp[g] = p;
           npatch[g]++;
         }
       }
+    }
+    // gather words: every cell-node slot of the patch exactly once, under its DOF
+    std::vector<char> seen((size_t)zslot, 0);
+    const uint32_t* gw = &m.gword[m.gword_off[p]];
+    const uint16_t* gl = &m.glist[m.glist_off[p]];
+    const int32_t gln = m.glist_off[p + 1] - m.glist_off[p];
+    if (m.glist_off[p] % 8) {
+      why = "gather list of patch " + std::to_string(p) + " is not 16-byte aligned";
+      return false;
+    }
+    for (int32_t l = 0; l < nbl; ++l) {
+      std::vector<int64_t> sl;
+      const uint32_t lo = gw[l] & 0xFFFFu, hi = gw[l] >> 16;
+      if (hi == kListMark) {
+        if ((int32_t)lo >= gln || (int32_t)(lo + 1 + gl[lo]) > gln || gl[lo] < 3) {
+          why = "gather list entry out of range";
+          return false;
+        }
+        for (int k = 0; k < gl[lo]; ++k) sl.push_back(gl[lo + 1 + k]);
+      } else {
+        sl.push_back(lo);
+        if (hi != zslot) sl.push_back(hi);
+      }
+      for (int64_t sv : sl) {
+        const int64_t b = sv / cs, t = sv % cs;
+        if (sv >= zslot || t >= nc || seen[sv] || m.lmap[(size_t)b * ne + c0 + t] != l) {
+          why = "gather words of patch " + std::to_string(p) + " are not the inverse of the local map";
+          return false;
+        }
+        seen[sv] = 1;
+      }
+    }
+    for (int32_t t = 0; t < nc; ++t)
+      for (int b = 0; b < nb; ++b)
+        if (!seen[(size_t)b * cs + t]) {
+          why = "a cell-node slot of patch " + std::to_string(p) + " is never gathered";
+          return false;
+        }
   }
   for (int64_t g = 0; g < m.n_own_total; ++g)
     if (npatch[g] != 1) {
@@ -698,31 +713,6 @@ bool validate_mesh(const Mesh& m, std::string& why) {
         return false;
       }
     }
-  }
-  // gather lists: per patch a permutation of the cell-node slots, grouped by DOF
-  for (int64_t p = 0; p < m.n_patches; ++p) {
-    const int32_t c0 = m.patch_cell_start[p], c1 = m.patch_cell_start[p + 1];
-    const int32_t nloc = (m.patch_own_start[p + 1] - m.patch_own_start[p]) +
-                         (m.patch_sh_start[p + 1] - m.patch_sh_start[p]);
-    const uint16_t* gp = &m.gl_ptr[m.gl_ptr_off[p]];
-    const uint16_t* ge = &m.gl_ent[m.gl_ent_off[p]];
-    const int nslot = (c1 - c0) * nd;
-    if (m.gl_ptr_off[p] % 8 || m.gl_ent_off[p] % 8 || m.gl_ptr_off[p + 1] - m.gl_ptr_off[p] < nloc + 1 ||
-        m.gl_ent_off[p + 1] - m.gl_ent_off[p] < nslot || gp[0] != 0 || gp[nloc] != nslot) {
-      why = "gather list of patch " + std::to_string(p) + " does not cover its cells";
-      return false;
-    }
-    std::vector<char> seen(nslot, 0);
-    for (int32_t i = 0; i < nloc; ++i)
-      for (int k = gp[i]; k < gp[i + 1]; ++k) {
-        const int slot = ge[k];
-        const int e = c0 + slot / nd, a = slot % nd;
-        if (slot >= nslot || seen[slot] || m.lmap[(size_t)a * ne + e] != i || (k > gp[i] && slot <= ge[k - 1])) {
-          why = "gather list of patch " + std::to_string(p) + " is not the inverse of the local map";
-          return false;
-        }
-        seen[slot] = 1;
-      }
   }
   // inline slot lists of every shared ref agree with the CSR lists
   for (int64_t r = 0; r < m.n_shared_refs; ++r) {

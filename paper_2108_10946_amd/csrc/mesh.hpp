@@ -8,8 +8,8 @@
 
 namespace kmv {
 
-constexpr int kMaxColours = 64;
 constexpr int kMaxShare = 2;  // inline partial slots per shared ref (DOFs on one patch interface)
+constexpr uint32_t kListMark = 0xFFFFu;  // high half of a gather word that points into a list
 
 // A point inside the mesh: containing (internal) cell and basis weights.
 struct PointLoc {
@@ -33,15 +33,20 @@ struct Mesh {
   std::vector<double> geom;          // [n_cells*ng] |det J| J^-1 J^-T, upper triangle
   std::vector<double> dof_coords;    // [n_dofs*dim]
   std::vector<double> mass;          // [n_dofs]
-  // patches
+  // node classes: interior nodes (the DOF belongs to that cell alone) and the
+  // rest, each in ascending local-node order
+  int ni = 0, nb = 0;
+  std::vector<int> int_nodes, bnd_nodes;
+  // patches.  The DOFs touched by one patch only ("owned") come first, patch by
+  // patch: the patch's interior DOFs, interior node j of its t-th cell at
+  // own_start + j*nc + t (nc cells in the patch), then its other owned DOFs.
+  // DOFs touched by several patches ("shared") follow all owned ones.
   int patch_cells = 0;
   int64_t n_patches = 0, n_own_total = 0, n_shared = 0, n_shared_refs = 0;
-  int max_nloc = 0, max_patch_cells = 0, max_colours = 0;
+  int max_nbl = 0, max_patch_cells = 0;
   std::vector<int32_t> patch_cell_start;  // [n_patches+1]
   std::vector<int32_t> patch_own_start;   // [n_patches+1]
   std::vector<int32_t> patch_sh_start;    // [n_patches+1] into sh_idx / partial slots
-  std::vector<int32_t> patch_ncol;        // [n_patches]
-  std::vector<int32_t> colour_start;      // [n_patches*(kMaxColours+1)] internal cell ids
   std::vector<int32_t> sh_idx;            // [n_shared_refs] global DOF id
   std::vector<int32_t> shp_ptr;           // [n_shared+1]
   std::vector<int32_t> shp_slot;          // [n_shared_refs]
@@ -49,16 +54,19 @@ struct Mesh {
   // patches touch the DOF, else {first slot, -count} (walk the CSR list)
   std::vector<int32_t> ref_slots;         // [n_shared_refs*kMaxShare]
   int max_share = 0;                      // most patches touching one DOF
-  std::vector<uint16_t> lmap;             // [nd*n_cells] SoA patch-local index
-  // per-patch gather lists, the inverse of lmap: local DOF i of patch p collects
-  // the cell-node slots (e - c0)*nd + a listed in
-  //   gl_ent[gl_ent_off[p] + gl_ptr[gl_ptr_off[p] + i] .. + gl_ptr[gl_ptr_off[p] + i + 1])
-  // in (e, a) order.  Each patch's regions start on a 16-byte boundary.
-  std::vector<uint16_t> gl_ptr;           // [per patch nloc_p + 1, padded to 8]
-  std::vector<uint16_t> gl_ent;           // [per patch ncells_p*nd, padded to 8]
-  std::vector<int32_t> gl_ptr_off, gl_ent_off;  // [n_patches+1]
-  std::vector<int32_t> dof_patch;         // designated patch of each DOF
-  std::vector<int32_t> dof_local;         // local index inside the designated patch
+  // Patch-local numbering of the non-interior DOFs: the owned ones in global
+  // order (0..nbo-1), then the patch's shared refs (nbo + j).
+  std::vector<uint16_t> lmap;             // [nb*n_cells] SoA: local DOF of non-interior node b of cell e
+  // Cell-node slots: non-interior node b of the patch's t-th cell writes slot
+  // b*slot_stride + t; slot nb*slot_stride holds zero.  Gather word of a local
+  // DOF: s0 | s1 << 16 for one or two contributions (s1 = the zero slot for one),
+  // or off | kListMark << 16 for more: glist[off] = count, then the slots.
+  int slot_stride = 0;
+  std::vector<uint32_t> gword;            // per patch, per local non-interior DOF
+  std::vector<int32_t> gword_off;         // [n_patches+1]
+  std::vector<uint16_t> glist;            // per patch, 8-entry aligned regions
+  std::vector<int32_t> glist_off;         // [n_patches+1]
+  int max_glist = 0;                      // longest per-patch glist region
   // point location grid
   double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   int grid_n[3] = {1, 1, 1};

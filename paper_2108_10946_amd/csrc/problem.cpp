@@ -16,7 +16,6 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
-#include <random>
 
 #include "../../include/kmvwave.h"
 #include "kernels.hpp"
@@ -125,18 +124,12 @@ Status upload_coefficients(Problem* p) {
   return OK;
 }
 
-// Injection groups: every entry (point j, DOF g, weight phi) is assigned to the
-// designated patch of g and grouped by its patch-local index, entries in point
-// order.  Sampling rows: global DOF ids, and patch-local ids in the patch that
-// holds the point's cell.
-Status build_points(Problem* p, const double* xyz, int npts, bool same_amp, PointTables& T) {
+// Point tables: each point is located in one cell (lowest input id on ties); its
+// entry (patch-local cell, point index, phi_a(x) per node) goes to the patch of
+// that cell, entries in point order.  Global rows: DOF ids and weights.
+Status build_points(Problem* p, const double* xyz, int npts, PointTables& T) {
   const Mesh& m = *p->mesh;
   const int nd = m.nd, dim = m.dim;
-  struct Ent {
-    int32_t patch, local, pt;
-    double w;
-  };
-  std::vector<Ent> ents;
   std::vector<int32_t> sdof((size_t)npts * nd);
   std::vector<double> sw((size_t)npts * nd);
   std::vector<int64_t> cell_of(npts);
@@ -146,81 +139,39 @@ Status build_points(Problem* p, const double* xyz, int npts, bool same_amp, Poin
       return Status{KMV_EOUTSIDE, "point " + std::to_string(j) + " lies outside the mesh"};
     cell_of[j] = loc.cell;
     for (int a = 0; a < nd; ++a) {
-      const int64_t g = m.cell_dofs[loc.cell * nd + a];
-      sdof[(size_t)j * nd + a] = (int32_t)g;
+      sdof[(size_t)j * nd + a] = (int32_t)m.cell_dofs[loc.cell * nd + a];
       sw[(size_t)j * nd + a] = loc.phi[a];
-      ents.push_back({m.dof_patch[g], m.dof_local[g], same_amp ? 0 : j, loc.phi[a]});
     }
   }
-  std::stable_sort(ents.begin(), ents.end(), [](const Ent& x, const Ent& y) {
-    return x.patch < y.patch || (x.patch == y.patch && (x.local < y.local || (x.local == y.local && x.pt < y.pt)));
-  });
-  std::vector<int32_t> gptr(m.n_patches + 1, 0), glocal, geptr{0}, ept;
-  std::vector<double> ew;
-  for (size_t k = 0; k < ents.size(); ++k) {
-    if (k == 0 || ents[k].patch != ents[k - 1].patch || ents[k].local != ents[k - 1].local) {
-      if (k > 0) geptr.push_back((int32_t)ept.size());
-      glocal.push_back(ents[k].local);
-      gptr[ents[k].patch + 1]++;
-    }
-    ept.push_back(ents[k].pt);
-    ew.push_back(ents[k].w);
-  }
-  if (!ents.empty()) geptr.push_back((int32_t)ept.size());
-  for (int64_t q = 0; q < m.n_patches; ++q) gptr[q + 1] += gptr[q];
-  // per-patch sampling rows
-  std::vector<int32_t> order(npts);
-  std::vector<int32_t> patch_of(npts);
+  std::vector<int32_t> order(npts), patch_of(npts);
   for (int j = 0; j < npts; ++j) {
     order[j] = j;
     patch_of[j] = (int32_t)(std::upper_bound(m.patch_cell_start.begin(), m.patch_cell_start.end(),
                                              (int32_t)cell_of[j]) - m.patch_cell_start.begin() - 1);
   }
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return patch_of[a] < patch_of[b]; });
-  std::vector<int32_t> rptr(m.n_patches + 1, 0), rrec(npts);
-  std::vector<uint16_t> rloc((size_t)npts * nd);
-  std::vector<double> rw((size_t)npts * nd);
+  std::vector<int32_t> ptr(m.n_patches + 1, 0), pcell(npts), ppt(npts);
+  std::vector<double> pw((size_t)npts * nd);
   for (int k = 0; k < npts; ++k) {
     const int j = order[k];
-    const int32_t q = patch_of[j];
-    rptr[q + 1]++;
-    rrec[k] = j;
-    const int32_t own0 = m.patch_own_start[q], own1 = m.patch_own_start[q + 1];
-    const int32_t sh0 = m.patch_sh_start[q], sh1 = m.patch_sh_start[q + 1];
-    for (int a = 0; a < nd; ++a) {
-      const int32_t g = sdof[(size_t)j * nd + a];
-      int32_t loc = -1;
-      if (g >= own0 && g < own1) {
-        loc = g - own0;
-      } else {
-        for (int32_t t = sh0; t < sh1; ++t)
-          if (m.sh_idx[t] == g) loc = (own1 - own0) + (t - sh0);
-      }
-      if (loc < 0) return Status{KMV_EINVAL, "point DOF not found in its patch"};
-      rloc[(size_t)k * nd + a] = (uint16_t)loc;
-      rw[(size_t)k * nd + a] = sw[(size_t)j * nd + a];
-    }
+    ptr[patch_of[j] + 1]++;
+    pcell[k] = (int32_t)(cell_of[j] - m.patch_cell_start[patch_of[j]]);
+    ppt[k] = j;
+    for (int a = 0; a < nd; ++a) pw[(size_t)k * nd + a] = sw[(size_t)j * nd + a];
   }
-  for (int64_t q = 0; q < m.n_patches; ++q) rptr[q + 1] += rptr[q];
+  for (int64_t q = 0; q < m.n_patches; ++q) ptr[q + 1] += ptr[q];
   T.npts = npts;
-  STTRY(upload_i(&T.grp_ptr, gptr));
-  STTRY(upload_i(&T.grp_local, glocal));
-  STTRY(upload_i(&T.grp_eptr, geptr));
-  STTRY(upload_i(&T.ent_pt, ept));
-  STTRY(upload_real(&T.ent_w, ew, p->prec));
+  STTRY(upload_i(&T.pp_ptr, ptr));
+  STTRY(upload_i(&T.pp_cell, pcell));
+  STTRY(upload_i(&T.pp_pt, ppt));
+  STTRY(upload_real(&T.pp_w, pw, p->prec));
   STTRY(upload_i(&T.s_dof, sdof));
   STTRY(upload_real(&T.s_w, sw, p->prec));
-  STTRY(upload_i(&T.rp_ptr, rptr));
-  STTRY(upload_i(&T.rp_rec, rrec));
-  STTRY(upload_i(&T.rp_loc, rloc));
-  STTRY(upload_real(&T.rp_w, rw, p->prec));
   return OK;
 }
 
 void free_points(PointTables& T) {
-  for (void* q : {(void*)T.grp_ptr, (void*)T.grp_local, (void*)T.grp_eptr, (void*)T.ent_pt, T.ent_w,
-                  (void*)T.s_dof, T.s_w, (void*)T.rp_ptr, (void*)T.rp_rec, (void*)T.rp_loc, T.rp_w})
-    dfree(q);
+  for (void* q : {(void*)T.pp_ptr, (void*)T.pp_cell, (void*)T.pp_pt, T.pp_w, (void*)T.s_dof, T.s_w}) dfree(q);
   T = PointTables();
 }
 
@@ -273,17 +224,19 @@ StepArgs<T> base_args(const Problem* p) {
   a.own_start = p->d_own_start;
   a.sh_start = p->d_sh_start;
   a.sh_idx = p->d_sh_idx;
-  a.gl_ptr = p->d_gl_ptr;
-  a.gl_ent = p->d_gl_ent;
-  a.gl_ptr_off = p->d_gl_ptr_off;
-  a.gl_ent_off = p->d_gl_ent_off;
+  a.gword = p->d_gword;
+  a.gword_off = p->d_gword_off;
+  a.glist = p->d_glist;
+  a.glist_off = p->d_glist_off;
   a.shp_ptr = p->d_shp_ptr;
   a.shp_slot = p->d_shp_slot;
   a.ref_slots = p->d_ref_slots;
   a.n_cells = m.n_cells;
   a.n_own = m.n_own_total;
-  a.nloc_max = p->nloc;
-  a.cells_max = m.max_patch_cells;
+  a.n_dofs = m.n_dofs;
+  a.nbl_max = m.max_nbl;
+  a.slot_stride = m.slot_stride;
+  a.glist_max = m.max_glist;
   a.c2 = (const T*)p->d_c2;
   a.gamma = (const T*)p->d_gamma;
   a.beta = (const T*)p->d_beta;
@@ -300,34 +253,35 @@ struct Par {
 
 template <typename T>
 Status step(Problem* p, Sweep& S, bool grad, bool prev, const T* u_in, const T* u_prev, T* u_out, Par q,
-            const PointTables* inj, const T* amp, T scale, const T* uf, T* trace_row, hipStream_t s) {
+            const PointTables* inj, const T* amp, int amp_stride, T scale, const T* uf, T* trace_row,
+            hipStream_t s) {
   const Mesh& m = *p->mesh;
   StepArgs<T> a = base_args<T>(p);
   a.mode = 0;
   a.prev = prev ? 1 : 0;
   a.u_in = u_in;
   a.u_in_sh = const_cast<T*>(u_in);
-  a.u_prev = u_prev;
+  a.u_prev = u_prev ? u_prev : u_in;  // never dereferenced as a previous level when !prev
   a.u_out = u_out;
   a.du = (T*)S.d;
   a.dsh_prev = (const T*)S.dsh[q.lvl_prev];
   a.dsh_cur = (T*)S.dsh[q.lvl_cur];
   a.part_prev = (const T*)S.part[q.step_prev];
   a.part_cur = (T*)S.part[q.step_cur];
-  if (inj && inj->grp_ptr) {
-    a.grp_ptr = inj->grp_ptr;
-    a.grp_local = inj->grp_local;
-    a.grp_eptr = inj->grp_eptr;
-    a.ent_pt = inj->ent_pt;
-    a.ent_w = (const T*)inj->ent_w;
+  if (inj && inj->pp_ptr) {
+    a.inj_ptr = inj->pp_ptr;
+    a.inj_cell = inj->pp_cell;
+    a.inj_pt = inj->pp_pt;
+    a.inj_w = (const T*)inj->pp_w;
     a.amp = amp;
+    a.amp_stride = amp_stride;
     a.amp_scale = scale;
   }
   if (trace_row) {
-    a.rp_ptr = p->rec.rp_ptr;
-    a.rp_rec = p->rec.rp_rec;
-    a.rp_loc = p->rec.rp_loc;
-    a.rp_w = (const T*)p->rec.rp_w;
+    a.rec_ptr = p->rec.pp_ptr;
+    a.rec_cell = p->rec.pp_cell;
+    a.rec_pt = p->rec.pp_pt;
+    a.rec_w = (const T*)p->rec.pp_w;
     a.trace_row = trace_row;
   }
   if (grad) {
@@ -415,7 +369,7 @@ Status run_forward(Problem* p, int64_t n0, int64_t n1, F slot_of, T* traces, boo
     }
     T* row = (traces && n >= 1) ? traces + (n - 1) * p->rec.npts : nullptr;
     STTRY(step<T>(p, S, false, !fresh, slot_of(n), n > n0 ? slot_of(n - 1) : nullptr, slot_of(n + 1),
-                  fwd_par(n), &p->src, (const T*)p->d_wavelet + n, T(1), nullptr, row, s));
+                  fwd_par(n), &p->src, (const T*)p->d_wavelet + n, 0, T(1), nullptr, row, s));
     fresh = false;
   }
   if (n1 > n0) STTRY(finish<T>(p, S, false, slot_of(n1 - 1), slot_of(n1), fwd_par(n1), s));
@@ -472,7 +426,7 @@ Status adjoint_launch(Problem* p, int64_t m, bool grad, const T* adj_rows, const
   T* lam_in = (T*)p->d_lam[(m + 1) & 1];
   T* lam_out = (T*)p->d_lam[m & 1];
   return step<T>(p, p->adj, grad, m != p->nt, lam_in, lam_out, lam_out, adj_par(m), &p->rec,
-                 adj_rows + (m - 1) * p->rec.npts, (T)inv_dt2, uf, nullptr, s);
+                 adj_rows + (m - 1) * p->rec.npts, 1, (T)inv_dt2, uf, nullptr, s);
 }
 
 template <typename T>
@@ -570,6 +524,11 @@ Status apply_t(Problem* p, const double* c, const T* u, T* y, hipStream_t s) {
   a.prev = 0;
   a.u_in = u;
   a.y_out = y;
+  // loaded (not used) by the branch-free prologue: any valid buffers
+  a.du = y;
+  a.u_prev = u;
+  a.dsh_prev = (const T*)p->fwd.dsh[0];
+  a.part_prev = (const T*)p->fwd.part[1];
   a.part_cur = (T*)p->fwd.part[0];
   STTRY(probed(p, 0, s, [&](hipEvent_t e0, hipEvent_t e1) {
     return launch_step<T>(m.dim, m.nd, false, a, (int)m.n_patches, p->block, s, e0, e1);
@@ -586,17 +545,31 @@ Status apply_t(Problem* p, const double* c, const T* u, T* y, hipStream_t s) {
                 [&](hipEvent_t e0, hipEvent_t e1) { return launch_finish<T>(false, f, s, e0, e1); });
 }
 
+// SplitMix64 (Steele, Lea and Flood, 2014): one step of the generator's output map.
+uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
 template <typename T>
 Status spectral_t(Problem* p, const double* c, int iters, uint64_t seed, double* rho, hipStream_t s) {
   const Mesh& m = *p->mesh;
   const int64_t N = m.n_dofs;
+  // Start vector: a standard normal per DOF drawn from a counter-based hash of the
+  // seed and the DOF's coordinates, so the iteration does not depend on the
+  // library's internal DOF numbering.
   std::vector<T> v0(N);
-  std::mt19937_64 gen(seed);
-  std::normal_distribution<double> nd(0.0, 1.0);
-  double nrm = 0;
   std::vector<double> tmp(N);
+  double nrm = 0;
   for (int64_t i = 0; i < N; ++i) {
-    tmp[i] = nd(gen);
+    uint64_t h = splitmix64(seed);
+    for (int r = 0; r < m.dim; ++r)
+      h = splitmix64(h ^ (uint64_t)std::llround(m.dof_coords[i * m.dim + r] * 1073741824.0));
+    const uint64_t h2 = splitmix64(h);
+    const double u1 = ((double)(h >> 11) + 0.5) * 0x1.0p-53, u2 = (double)(h2 >> 11) * 0x1.0p-53;
+    tmp[i] = std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
     nrm += tmp[i] * tmp[i];
   }
   for (int64_t i = 0; i < N; ++i) v0[i] = (T)(tmp[i] / std::sqrt(nrm));
@@ -653,8 +626,8 @@ Status alloc_sweep(Sweep& S, const Mesh& m, size_t ts, bool with_r) {
 
 Problem::~Problem() {
   for (void* q : {(void*)d_lmap, d_geom, (void*)d_cell_start, (void*)d_own_start, (void*)d_sh_start,
-                  (void*)d_sh_idx, (void*)d_shp_ptr, (void*)d_shp_slot, (void*)d_ref_slots, (void*)d_gl_ptr,
-                  (void*)d_gl_ent, (void*)d_gl_ptr_off, (void*)d_gl_ent_off, (void*)d_damp_patch, d_gamma, d_beta, d_c2, d_minv_sqrt, d_lam[0], d_lam[1], (void*)d_gacc, (void*)d_red, d_slots,
+                  (void*)d_sh_idx, (void*)d_shp_ptr, (void*)d_shp_slot, (void*)d_ref_slots, (void*)d_gword,
+                  (void*)d_glist, (void*)d_gword_off, (void*)d_glist_off, (void*)d_damp_patch, d_gamma, d_beta, d_c2, d_minv_sqrt, d_lam[0], d_lam[1], (void*)d_gacc, (void*)d_red, d_slots,
                   d_ck_u, d_ck_du, d_resid, d_traces_tmp, d_wavelet})
     dfree(q);
   free_sweep(fwd);
@@ -709,22 +682,28 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
   p->budget = budget ? budget : ((size_t)8 << 30);
   HIPTRY(hipGetDevice(&p->device));
   p->block = std::max(64, ((m->max_patch_cells + 63) / 64) * 64);
-  p->nloc = m->max_nloc;
-  for (int64_t q = 0; q < m->n_patches; ++q)
-    p->nown = std::max(p->nown, m->patch_own_start[q + 1] - m->patch_own_start[q]);
-  {
-    const size_t bytes = step_lds_bytes(p->nloc, m->max_patch_cells, m->nd, p->ts);
+  for (bool adjv : {false, true}) {
+    const size_t bytes = step_lds_bytes(m->max_nbl, m->slot_stride, m->nb, m->max_glist, adjv, p->ts);
     if (bytes > 160 * 1024) return Status{KMV_EINVAL, "patch LDS footprint above 160 KiB; use smaller patches"};
     if (bytes > 64 * 1024) {
-      for (bool adjv : {false, true}) {
-        if (prec == KMV_FP64)
-          HIPTRY(set_step_lds_limit<double>(m->dim, m->nd, adjv, (int)bytes));
-        else
-          HIPTRY(set_step_lds_limit<float>(m->dim, m->nd, adjv, (int)bytes));
-      }
+      if (prec == KMV_FP64)
+        HIPTRY(set_step_lds_limit<double>(m->dim, m->nd, adjv, (int)bytes));
+      else
+        HIPTRY(set_step_lds_limit<float>(m->dim, m->nd, adjv, (int)bytes));
     }
   }
-  STTRY(upload_i(&p->d_lmap, m->lmap));
+  {
+    // local indices of node pairs (2q, 2q+1) of a cell packed in one 32-bit word, SoA
+    const int nb2 = (m->nb + 1) / 2;
+    std::vector<uint32_t> lm2((size_t)std::max(nb2, 1) * m->n_cells, 0);
+    for (int q = 0; q < nb2; ++q)
+      for (int64_t e = 0; e < m->n_cells; ++e) {
+        const uint32_t lo = m->lmap[(size_t)(2 * q) * m->n_cells + e];
+        const uint32_t hi = 2 * q + 1 < m->nb ? m->lmap[(size_t)(2 * q + 1) * m->n_cells + e] : 0u;
+        lm2[(size_t)q * m->n_cells + e] = lo | (hi << 16);
+      }
+    STTRY(upload_i(&p->d_lmap, lm2));
+  }
   {
     std::vector<double> g((size_t)m->ng * m->n_cells);  // SoA
     for (int64_t e = 0; e < m->n_cells; ++e)
@@ -734,14 +713,25 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
   STTRY(upload_i(&p->d_cell_start, m->patch_cell_start));
   STTRY(upload_i(&p->d_own_start, m->patch_own_start));
   STTRY(upload_i(&p->d_sh_start, m->patch_sh_start));
-  STTRY(upload_i(&p->d_sh_idx, m->sh_idx));
-  STTRY(upload_i(&p->d_gl_ptr, m->gl_ptr));
-  STTRY(upload_i(&p->d_gl_ent, m->gl_ent));
-  STTRY(upload_i(&p->d_gl_ptr_off, m->gl_ptr_off));
-  STTRY(upload_i(&p->d_gl_ent_off, m->gl_ent_off));
+  // ref and list arrays carry padding so that clamped indices of idle lanes stay
+  // in bounds (the kernels load them without branching)
+  {
+    std::vector<int32_t> v(m->sh_idx);
+    v.push_back(0);
+    STTRY(upload_i(&p->d_sh_idx, v));
+    std::vector<int32_t> r(m->ref_slots);
+    r.push_back(0);
+    r.push_back(0);
+    STTRY(upload_i(&p->d_ref_slots, r));
+    std::vector<uint16_t> gl(m->glist);
+    gl.resize(gl.size() + 8, 0);
+    STTRY(upload_i(&p->d_glist, gl));
+  }
+  STTRY(upload_i(&p->d_gword, m->gword));
+  STTRY(upload_i(&p->d_gword_off, m->gword_off));
+  STTRY(upload_i(&p->d_glist_off, m->glist_off));
   STTRY(upload_i(&p->d_shp_ptr, m->shp_ptr));
   STTRY(upload_i(&p->d_shp_slot, m->shp_slot));
-  if (!m->ref_slots.empty()) STTRY(upload_i(&p->d_ref_slots, m->ref_slots));
   STTRY(upload_coefficients(p));
   {
     std::vector<double> ms(m->n_dofs);
@@ -782,7 +772,7 @@ Status set_sources(Problem* p, const double* xs, int nsrc, double f0, double t0,
   DeviceGuard dg(p->device);
   if (nsrc <= 0 || !xs) return Status{KMV_EINVAL, "need at least one source"};
   free_points(p->src);
-  STTRY(build_points(p, xs, nsrc, true, p->src));
+  STTRY(build_points(p, xs, nsrc, p->src));
   std::vector<double> w(p->nt);
   const double pi = 3.14159265358979323846;
   for (int64_t n = 0; n < p->nt; ++n) {
@@ -798,7 +788,7 @@ Status set_receivers(Problem* p, const double* xr, int nrec) {
   DeviceGuard dg(p->device);
   if (nrec <= 0 || !xr) return Status{KMV_EINVAL, "need at least one receiver"};
   free_points(p->rec);
-  STTRY(build_points(p, xr, nrec, false, p->rec));
+  STTRY(build_points(p, xr, nrec, p->rec));
   const size_t tb = (size_t)p->nt * nrec * p->ts;
   STTRY(alloc(&p->d_resid, tb));
   STTRY(alloc(&p->d_traces_tmp, tb));

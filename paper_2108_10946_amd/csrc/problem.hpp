@@ -15,21 +15,18 @@ struct Status {
   std::string msg;
 };
 
-// Point tables on the device: injection groups (per designated patch), global
-// sampling rows, and per-patch sampling rows with patch-local DOF indices.
+// Point tables on the device: per patch, the entries (patch-local cell, point
+// index, phi_a(x_point) per node) of the points whose cell lies in the patch, used
+// for injection and for sampling inside k_step; and global sampling rows (DOF
+// ids and weights) for k_sample.
 struct PointTables {
   int npts = 0;
-  int32_t* grp_ptr = nullptr;   // [np+1]
-  int32_t* grp_local = nullptr;
-  int32_t* grp_eptr = nullptr;
-  int32_t* ent_pt = nullptr;
-  void* ent_w = nullptr;
+  int32_t* pp_ptr = nullptr;    // [np+1]
+  int32_t* pp_cell = nullptr;   // patch-local cell
+  int32_t* pp_pt = nullptr;     // point index
+  void* pp_w = nullptr;         // [n*nd]
   int32_t* s_dof = nullptr;     // [npts*nd] global DOFs
   void* s_w = nullptr;          // [npts*nd]
-  int32_t* rp_ptr = nullptr;    // [np+1] points whose cell lies in each patch
-  int32_t* rp_rec = nullptr;    // point index
-  uint16_t* rp_loc = nullptr;   // [npts*nd] patch-local DOFs
-  void* rp_w = nullptr;         // [npts*nd]
 };
 
 // Event-based timing of sampled kernel launches (see kmv_profile_enable).
@@ -67,14 +64,14 @@ struct Problem {
   size_t budget = 0;
   int device = 0;
   int block = 64;
-  int nloc = 0, nown = 0;
   // mesh data
-  uint16_t* d_lmap = nullptr;
+  uint32_t* d_lmap = nullptr;
   void* d_geom = nullptr;
   int32_t *d_cell_start = nullptr, *d_own_start = nullptr, *d_sh_start = nullptr, *d_sh_idx = nullptr,
-          *d_shp_ptr = nullptr, *d_shp_slot = nullptr, *d_ref_slots = nullptr, *d_gl_ptr_off = nullptr,
-          *d_gl_ent_off = nullptr;
-  uint16_t *d_gl_ptr = nullptr, *d_gl_ent = nullptr;
+          *d_shp_ptr = nullptr, *d_shp_slot = nullptr, *d_ref_slots = nullptr, *d_gword_off = nullptr,
+          *d_glist_off = nullptr;
+  uint32_t* d_gword = nullptr;
+  uint16_t* d_glist = nullptr;
   // coefficients
   std::vector<double> eta;      // host damping (empty = none)
   void* d_gamma = nullptr;
