@@ -82,8 +82,8 @@ int kmv_element_tables(int dim, int degree, int* n_nodes, double* nodes, double*
 
 /* Build the discretisation of a simplicial mesh (host only, no GPU needed):
  * global DOF numbering (one per distinct node; the local-to-global map g(j,k) of
- * section "Receivers and sources"), cell patches and colouring, geometry, lumped
- * mass M_i = sum w_q |det J_e|.
+ * section "Receivers and sources"), cell patches (interior DOFs of a cell numbered
+ * together, the rest per patch), geometry, lumped mass M_i = sum w_q |det J_e|.
  *   coords [n_vertices*dim] (copied), cells [n_cells*(dim+1)] 0-based (copied).
  *   patch_cells: cells per patch (0 = chosen from degree and dimension).
  * Errors: KMV_EINVAL, KMV_EDEGREE, KMV_EMESH (index out of range, zero volume). */
@@ -103,10 +103,11 @@ int kmv_mesh_cell_dofs(kmv_mesh m, int64_t* out);
  * (eq. spectral), for nodal wavespeed c_host [n_dofs] (host, DOF order).  Host
  * only.  Errors: KMV_EINVAL. */
 int kmv_cfl_dt(kmv_mesh m, const double* c_host, double* dt_max);
-/* Check the scheduling invariants the kernels rely on: no two cells of one colour
- * in a patch share a DOF, patch-local maps agree with the global DOF map, every
- * shared DOF lists the partial slots of exactly the patches that touch it, in
- * patch order, and every lumped mass is positive.  Host only.
+/* Check the scheduling invariants the kernels rely on: interior DOFs sit at their
+ * implicit positions, patch-local maps agree with the global DOF map, the gather
+ * words of every patch collect each cell-node slot exactly once, every shared DOF
+ * lists the partial slots of exactly the patches that touch it, in patch order,
+ * and every lumped mass is positive.  Host only.
  * Returns KMV_OK or KMV_EMESH with the first violation in kmv_last_error(). */
 int kmv_mesh_validate(kmv_mesh m);
 int kmv_mesh_destroy(kmv_mesh m);
@@ -188,6 +189,66 @@ int kmv_profile_read(kmv_problem p, int variant, int64_t* n_launches, int64_t* n
 int kmv_problem_info(kmv_problem p, int64_t* n_dofs, int64_t* n_steps, int* n_rec,
                      int* precision, int64_t* checkpoint_every);
 int kmv_problem_destroy(kmv_problem p);
+
+/* ------------------------------------------------------------------- serving */
+
+/* A shot server keeps a queue of independent shot solves (the per-shot forward
+ * and misfit-gradient evaluations of section "Parallelism", one shot per request)
+ * and runs them on the current device.  Up to max_slots requests run at once,
+ * each on its own stream and worker thread; a request is admitted, in arrival
+ * order, when its device memory (states or checkpoints, traces, tables) fits in
+ * what the running requests leave of mem_budget.  Requests admitted together
+ * overlap on the GPU.  Every solve is deterministic and shares no buffer with
+ * another, so a request's results are bitwise those it gets alone. */
+typedef struct kmv_server_s* kmv_server;  /* opaque, library-owned */
+
+typedef struct {
+  kmv_mesh mesh;          /* must outlive the request; degree comes with it */
+  int precision;          /* KMV_FP64 or KMV_FP32 */
+  double dt;              /* time step (s) */
+  int64_t n_steps;        /* N_t */
+  const double* c;        /* [n_dofs] P-wave speed (host, DOF order) */
+  const double* eta;      /* [n_dofs] damping in 1/s, or NULL */
+  const double* xs;       /* [n_src*dim] source positions (Ricker, as kmv_set_sources) */
+  int n_src;
+  double f0, t0, amp;
+  const double* xr;       /* [n_rec*dim] receiver positions */
+  int n_rec;
+  int forward_only;       /* 1: traces only; 0: misfit, traces and gradient */
+  const void* observed;   /* [n_steps*n_rec] host, element type of the precision */
+} kmv_request;
+
+typedef struct {
+  int status;             /* KMV_OK or the solve's error code (text: kmv_last_error) */
+  double J;               /* misfit (0 for forward-only requests) */
+  const void* traces;     /* [n_steps*n_rec] host, element type of the precision */
+  const double* grad;     /* [n_dofs] host dJ/dc, or NULL for forward-only requests */
+  int64_t n_steps, n_rec, n_dofs;
+  double t_submit, t_admit, t_done;  /* seconds since the server was created */
+  size_t device_bytes;    /* device memory reserved for the request while it ran */
+} kmv_result;
+
+/* mem_budget: device bytes for requests (0 = 80% of the free memory).  Each
+ * request keeps all its states if they fit in min(mem_budget, 8 GiB), else it
+ * checkpoints (as kmv_options.checkpoint_every = 0).
+ * max_slots: requests that may run at once (1..64).
+ * Errors: KMV_EINVAL, KMV_EDEVICE. */
+int kmv_server_create(size_t mem_budget, int max_slots, kmv_server* out);
+/* Copy the request's host inputs (the caller may free them on return) and queue
+ * it.  Errors: KMV_EINVAL (missing inputs), KMV_ENOMEM (needs more than the whole
+ * budget), KMV_ESTATE (server shutting down). */
+int kmv_server_submit(kmv_server s, const kmv_request* req, uint64_t* ticket);
+/* KMV_EBUSY while the request is pending, else KMV_OK with *out filled; the
+ * result buffers stay valid until kmv_server_release.  Errors: KMV_EINVAL. */
+int kmv_server_poll(kmv_server s, uint64_t ticket, kmv_result* out);
+/* As kmv_server_poll, blocking up to timeout_s seconds (< 0: no limit). */
+int kmv_server_wait(kmv_server s, uint64_t ticket, double timeout_s, kmv_result* out);
+/* Free a finished request's results.  Errors: KMV_EBUSY, KMV_EINVAL. */
+int kmv_server_release(kmv_server s, uint64_t ticket);
+/* Requests running and queued, and device bytes reserved by the running ones. */
+int kmv_server_stats(kmv_server s, int* running, int* queued, size_t* bytes_in_use);
+/* Cancel queued requests, wait for the running ones, free everything. */
+int kmv_server_destroy(kmv_server s);
 
 #ifdef __cplusplus
 }

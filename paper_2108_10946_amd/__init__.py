@@ -11,8 +11,8 @@ behind a C ABI; this package is the Python binding).
     J, grad, traces = prob.misfit_gradient(c, observed)
 """
 from .kmvwave import (KMVError, KMV_FP32, KMV_FP64, kmv_element_tables, lib)
-from .api import Mesh, Problem
+from .api import Mesh, Problem, Server
 from .autograd import FWIMisfit, fwi_misfit
 
-__all__ = ["Mesh", "Problem", "FWIMisfit", "fwi_misfit", "KMVError", "KMV_FP32", "KMV_FP64",
+__all__ = ["Mesh", "Problem", "Server", "FWIMisfit", "fwi_misfit", "KMVError", "KMV_FP32", "KMV_FP64",
            "kmv_element_tables", "lib"]

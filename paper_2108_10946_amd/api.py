@@ -158,3 +158,58 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+class Server:
+    """Shot server on the current device: requests (one shot each) are admitted
+    in arrival order as slots and device memory free up, and run concurrently,
+    each on its own stream (see kmv_server_create).  Inputs are host arrays; the
+    results come back as host arrays."""
+
+    def __init__(self, mem_budget=0, max_slots=4):
+        self.handle = K.kmv_server_create(mem_budget, max_slots)
+        self._prec = {}
+        self._keep = {}  # meshes of pending requests stay alive
+
+    def submit(self, mesh: Mesh, c, xs, xr, dt, n_steps, precision="fp32", eta=None, observed=None,
+               forward_only=False, f0=5.0, t0=None, amp=1.0):
+        prec = K.KMV_FP64 if precision == "fp64" else K.KMV_FP32
+        t = K.kmv_server_submit(self.handle, mesh.handle, prec, dt, n_steps, c, xs, xr, f0,
+                                1.0 / f0 if t0 is None else t0, amp, eta=eta, observed=observed,
+                                forward_only=forward_only)
+        self._prec[t] = prec
+        self._keep[t] = mesh
+        return t
+
+    def poll(self, ticket):
+        """None while pending, else a dict (status, J, traces, grad, timestamps)."""
+        return K.kmv_server_poll(self.handle, ticket, self._prec[ticket])
+
+    def wait(self, ticket, timeout=-1.0):
+        return K.kmv_server_wait(self.handle, ticket, self._prec[ticket], timeout)
+
+    def release(self, ticket):
+        K.kmv_server_release(self.handle, ticket)
+        self._prec.pop(ticket, None)
+        self._keep.pop(ticket, None)
+
+    def result(self, ticket):
+        """Wait for a request, return its results and free them in the library."""
+        r = self.wait(ticket)
+        self.release(ticket)
+        return r
+
+    def stats(self):
+        return K.kmv_server_stats(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            K.kmv_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -19,12 +19,12 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libkmvwave.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["element.cpp", "mesh.cpp", "problem.cpp", "capi.cpp", "kernels.hip"]
+SOURCES = ["element.cpp", "mesh.cpp", "problem.cpp", "server.cpp", "capi.cpp", "kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("KMV_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-I", os.path.join(ROOT, "include"), "-I", BUILD, "-Wall", "-Wno-unused-result"]
+          "-I", os.path.join(ROOT, "include"), "-I", BUILD, "-Wall", "-Wno-unused-result", "-pthread"]
 
 
 def _compile(src):
@@ -63,7 +63,7 @@ def build(jobs: int = 0, verbose: bool = True) -> str:
                 print(f"[{src}]\n{err}", file=sys.stderr)
             objs.append(obj)
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -10,12 +10,16 @@
 #include "element.hpp"
 #include "mesh.hpp"
 #include "problem.hpp"
+#include "server.hpp"
 
 struct kmv_mesh_s {
   kmv::Mesh* m;
 };
 struct kmv_problem_s {
   kmv::Problem* p;
+};
+struct kmv_server_s {
+  kmv::Server* s;
 };
 
 namespace {
@@ -251,6 +255,72 @@ int kmv_profile_read(kmv_problem h, int variant, int64_t* n_launches, int64_t* n
 int kmv_problem_destroy(kmv_problem h) {
   if (!h) return KMV_OK;
   delete h->p;
+  delete h;
+  return KMV_OK;
+}
+
+// ------------------------------------------------------------------- serving
+
+int kmv_server_create(size_t mem_budget, int max_slots, kmv_server* out) {
+  return guarded([&]() -> int {
+    if (!out) return fail(KMV_EINVAL, "out is NULL");
+    kmv::Server* s = nullptr;
+    const int rc = done(kmv::server_create(mem_budget, max_slots, &s));
+    if (rc != KMV_OK) return rc;
+    *out = new kmv_server_s{s};
+    return KMV_OK;
+  });
+}
+
+int kmv_server_submit(kmv_server h, const kmv_request* req, uint64_t* ticket) {
+  return guarded([&]() {
+    if (!h || !req || !req->mesh) return fail(KMV_EINVAL, "server, request or mesh is NULL");
+    return done(kmv::server_submit(h->s, req->mesh->m, req, ticket));
+  });
+}
+
+namespace {
+int result_status(int rc, const kmv_result* out, const std::string& msg) {
+  if (rc == KMV_OK && out && out->status != KMV_OK) g_err = msg;
+  return rc;
+}
+}  // namespace
+
+int kmv_server_poll(kmv_server h, uint64_t ticket, kmv_result* out) {
+  return guarded([&]() {
+    if (!h) return fail(KMV_EINVAL, "server is NULL");
+    std::string msg;
+    const int rc = done(kmv::server_poll(h->s, ticket, out, &msg));
+    return result_status(rc, out, msg);
+  });
+}
+
+int kmv_server_wait(kmv_server h, uint64_t ticket, double timeout_s, kmv_result* out) {
+  return guarded([&]() {
+    if (!h) return fail(KMV_EINVAL, "server is NULL");
+    std::string msg;
+    const int rc = done(kmv::server_wait(h->s, ticket, timeout_s, out, &msg));
+    return result_status(rc, out, msg);
+  });
+}
+
+int kmv_server_release(kmv_server h, uint64_t ticket) {
+  return guarded([&]() {
+    if (!h) return fail(KMV_EINVAL, "server is NULL");
+    return done(kmv::server_release(h->s, ticket));
+  });
+}
+
+int kmv_server_stats(kmv_server h, int* running, int* queued, size_t* bytes_in_use) {
+  return guarded([&]() {
+    if (!h) return fail(KMV_EINVAL, "server is NULL");
+    return done(kmv::server_stats(h->s, running, queued, bytes_in_use));
+  });
+}
+
+int kmv_server_destroy(kmv_server h) {
+  if (!h) return KMV_OK;
+  kmv::server_destroy(h->s);
   delete h;
   return KMV_OK;
 }

@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
     sl[t] = reinterpret_cast<const int2*>(A.ref_slots)[jc];
   }
   const bool damped = A.beta != nullptr && A.damp_patch[p] != 0;
-  const T* bsrc = damped ? A.beta : A.gamma;  // any valid array when undamped
+  const T* bsrc = damped ? A.beta : A.c2;  // undamped: a valid array already being read
   // their dependent loads (all pointers valid: without a previous level u_prev is
   // u_in and the partial and increment buffers are allocated)
   const T* usrc = A.prev ? A.u_prev : A.u_in;
@@ -147,6 +147,7 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
   for (int q = 0; q < NB2; ++q) mp[q] = A.lmap[(int64_t)q * A.n_cells + e];
 #pragma unroll
   for (int k = 0; k < NG; ++k) G[k] = A.geom[(int64_t)k * A.n_cells + e];
+  const T gdet = A.gdet[e];  // dt^2 / |det J_e|: interior DOF i has M_i = w_a |det J_e|
   T ui[NIa], ci[NIa], di[NIa], gi[NIa], bi[NIa], fi[ADJ ? NIa : 1];
   double ga[ADJ ? NIa : 1];  // gradient accumulator of the interior DOFs (read early)
 #pragma unroll
@@ -155,7 +156,6 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
     ui[j] = A.u_in[gx];
     ci[j] = A.c2[gx];
     di[j] = A.du[gx];
-    gi[j] = A.gamma[gx];
     bi[j] = bsrc[gx];
     if (ADJ) {
       fi[ADJ ? j : 0] = A.uf[gx];
@@ -186,6 +186,14 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
     for (int j = 0; j < NI; ++j) bi[j] = T(1);
 #pragma unroll
     for (int k = 0; k < KO; ++k) pb[k] = T(1);
+  }
+  // interior gamma = dt^2 / (w_a |det J_e| (1+a)), with 1/(1+a) = (1+beta)/2
+#pragma unroll
+  for (int a = 0; a < ND; ++a) {
+    if (!Tab::INT[a]) continue;
+    const int j = Tab::IDX[a] < NI ? Tab::IDX[a] : 0;
+    gi[j] = gdet * (T(1) / Tab::W[a]);
+    if (damped) gi[j] = gi[j] * ((T(1) + bi[j]) * T(0.5));
   }
   int m[NBa];
 #pragma unroll

@@ -31,6 +31,7 @@ struct StepArgs {
   // mesh
   const uint32_t* lmap;        // [ceil(nb/2) * n_cells] local non-interior DOFs of nodes 2q, 2q+1 of cell e
   const T* geom;               // [ng * n_cells] |det J| J^-1 J^-T (upper triangle)
+  const T* gdet;               // [n_cells] dt^2 / |det J|
   const int32_t* cell_start;   // [np+1]
   const int32_t* own_start;    // [np+1] interior DOFs, then the other owned DOFs
   const int32_t* sh_start;     // [np+1]
@@ -57,7 +58,7 @@ struct StepArgs {
   const T* part_prev;          // [n_shared_refs] partial K u of the previous step
   T* part_cur;                 // [n_shared_refs] partial K u of this step
   const T* c2;                 // c^2 at the DOFs
-  const T* gamma;              // dt^2 / (M (1+a))
+  const T* gamma;              // dt^2 / (M (1+a)) (read for non-interior DOFs)
   const T* beta;               // (1-a)/(1+a), or nullptr (no damping)
   const int32_t* damp_patch;   // [np] 1 if a DOF of the patch is damped (beta read only there)
   T* y_out;                    // mode 1

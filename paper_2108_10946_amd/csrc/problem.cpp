@@ -21,6 +21,14 @@
 #include "kernels.hpp"
 
 namespace kmv {
+
+namespace {
+thread_local hipStream_t t_alloc_stream = nullptr;
+}
+hipStream_t alloc_stream() { return t_alloc_stream; }
+AllocStreamScope::AllocStreamScope(hipStream_t s) : prev(t_alloc_stream) { t_alloc_stream = s; }
+AllocStreamScope::~AllocStreamScope() { t_alloc_stream = prev; }
+
 namespace {
 
 #define HIPTRY(expr)                                                                       \
@@ -38,15 +46,40 @@ namespace {
 
 const Status OK{KMV_OK, ""};
 
+// Device memory of a problem.  On a thread that set an allocation stream (the
+// server's workers), allocations and frees are stream-ordered (hipMallocAsync /
+// hipFreeAsync), so creating or destroying a problem does not wait for work that
+// other streams have in flight.
+Status dmalloc(void** dst, size_t bytes) {
+  const hipError_t e = alloc_stream() ? hipMallocAsync(dst, bytes, alloc_stream()) : hipMalloc(dst, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *dst = nullptr;
+    return Status{KMV_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+  }
+  return OK;
+}
+
+void dfree(void* p) {
+  if (!p) return;
+  if (alloc_stream())
+    (void)hipFreeAsync(p, alloc_stream());
+  else
+    (void)hipFree(p);
+}
+
 template <typename V>
 Status upload(void** dst, const V* src, size_t count) {
-  if (*dst) {
-    HIPTRY(hipFree(*dst));
-    *dst = nullptr;
-  }
+  dfree(*dst);
+  *dst = nullptr;
   if (count == 0) return OK;
-  HIPTRY(hipMalloc(dst, count * sizeof(V)));
-  HIPTRY(hipMemcpy(*dst, src, count * sizeof(V), hipMemcpyHostToDevice));
+  STTRY(dmalloc(dst, count * sizeof(V)));
+  if (alloc_stream()) {
+    HIPTRY(hipMemcpyAsync(*dst, src, count * sizeof(V), hipMemcpyHostToDevice, alloc_stream()));
+    HIPTRY(hipStreamSynchronize(alloc_stream()));  // the host source is a temporary
+  } else {
+    HIPTRY(hipMemcpy(*dst, src, count * sizeof(V), hipMemcpyHostToDevice));
+  }
   return OK;
 }
 
@@ -65,21 +98,10 @@ Status upload_real(void** dst, const std::vector<double>& v, int prec) {
 }
 
 Status alloc(void** dst, size_t bytes) {
-  if (*dst) {
-    HIPTRY(hipFree(*dst));
-    *dst = nullptr;
-  }
+  dfree(*dst);
+  *dst = nullptr;
   if (bytes == 0) return OK;
-  if (hipMalloc(dst, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    *dst = nullptr;
-    return Status{KMV_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
-  }
-  return OK;
-}
-
-void dfree(void* p) {
-  if (p) (void)hipFree(p);
+  return dmalloc(dst, bytes);
 }
 
 struct DeviceGuard {
@@ -104,6 +126,11 @@ Status upload_coefficients(Problem* p) {
     if (!beta.empty()) beta[i] = (1.0 - a) / (1.0 + a);
   }
   STTRY(upload_real(&p->d_gamma, gamma, p->prec));
+  {
+    std::vector<double> gd(m.n_cells);
+    for (int64_t e = 0; e < m.n_cells; ++e) gd[e] = dt2 / m.absdet[e];
+    STTRY(upload_real(&p->d_gdet, gd, p->prec));
+  }
   if (beta.empty()) {
     dfree(p->d_beta);
     p->d_beta = nullptr;
@@ -220,6 +247,7 @@ StepArgs<T> base_args(const Problem* p) {
   StepArgs<T> a{};
   a.lmap = p->d_lmap;
   a.geom = (const T*)p->d_geom;
+  a.gdet = (const T*)p->d_gdet;
   a.cell_start = p->d_cell_start;
   a.own_start = p->d_own_start;
   a.sh_start = p->d_sh_start;
@@ -627,7 +655,7 @@ Status alloc_sweep(Sweep& S, const Mesh& m, size_t ts, bool with_r) {
 Problem::~Problem() {
   for (void* q : {(void*)d_lmap, d_geom, (void*)d_cell_start, (void*)d_own_start, (void*)d_sh_start,
                   (void*)d_sh_idx, (void*)d_shp_ptr, (void*)d_shp_slot, (void*)d_ref_slots, (void*)d_gword,
-                  (void*)d_glist, (void*)d_gword_off, (void*)d_glist_off, (void*)d_damp_patch, d_gamma, d_beta, d_c2, d_minv_sqrt, d_lam[0], d_lam[1], (void*)d_gacc, (void*)d_red, d_slots,
+                  (void*)d_glist, (void*)d_gword_off, (void*)d_glist_off, (void*)d_damp_patch, d_gamma, d_gdet, d_beta, d_c2, d_minv_sqrt, d_lam[0], d_lam[1], (void*)d_gacc, (void*)d_red, d_slots,
                   d_ck_u, d_ck_du, d_resid, d_traces_tmp, d_wavelet})
     dfree(q);
   free_sweep(fwd);

@@ -15,6 +15,15 @@ struct Status {
   std::string msg;
 };
 
+// Stream for the device allocations of problems created or destroyed on this
+// thread (nullptr: plain hipMalloc / hipFree).  Set by the server's workers.
+hipStream_t alloc_stream();
+struct AllocStreamScope {
+  explicit AllocStreamScope(hipStream_t s);
+  ~AllocStreamScope();
+  hipStream_t prev;
+};
+
 // Point tables on the device: per patch, the entries (patch-local cell, point
 // index, phi_a(x_point) per node) of the points whose cell lies in the patch, used
 // for injection and for sampling inside k_step; and global sampling rows (DOF
@@ -75,6 +84,7 @@ struct Problem {
   // coefficients
   std::vector<double> eta;      // host damping (empty = none)
   void* d_gamma = nullptr;
+  void* d_gdet = nullptr;       // [n_cells] dt^2 / |det J|
   void* d_beta = nullptr;
   int32_t* d_damp_patch = nullptr;  // [np] patch touches a damped DOF
   void* d_c2 = nullptr;

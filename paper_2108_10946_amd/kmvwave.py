@@ -34,6 +34,8 @@ DECLARED = [
     "kmv_set_sources", "kmv_set_source_wavelet", "kmv_set_receivers", "kmv_forward",
     "kmv_misfit_gradient", "kmv_adjoint", "kmv_stiffness_apply", "kmv_problem_info",
     "kmv_profile_enable", "kmv_profile_read", "kmv_problem_destroy",
+    "kmv_server_create", "kmv_server_submit", "kmv_server_poll", "kmv_server_wait",
+    "kmv_server_release", "kmv_server_stats", "kmv_server_destroy",
 ]
 
 
@@ -46,6 +48,21 @@ class KMVError(RuntimeError):
 class kmv_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("dt", C.c_double), ("n_steps", C.c_int64),
                 ("checkpoint_every", C.c_int64), ("mem_budget", C.c_size_t)]
+
+
+class kmv_request(C.Structure):
+    _fields_ = [("mesh", C.c_void_p), ("precision", C.c_int), ("dt", C.c_double), ("n_steps", C.c_int64),
+                ("c", C.POINTER(C.c_double)), ("eta", C.POINTER(C.c_double)), ("xs", C.POINTER(C.c_double)),
+                ("n_src", C.c_int), ("f0", C.c_double), ("t0", C.c_double), ("amp", C.c_double),
+                ("xr", C.POINTER(C.c_double)), ("n_rec", C.c_int), ("forward_only", C.c_int),
+                ("observed", C.c_void_p)]
+
+
+class kmv_result(C.Structure):
+    _fields_ = [("status", C.c_int), ("J", C.c_double), ("traces", C.c_void_p),
+                ("grad", C.POINTER(C.c_double)), ("n_steps", C.c_int64), ("n_rec", C.c_int64),
+                ("n_dofs", C.c_int64), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double), ("device_bytes", C.c_size_t)]
 
 
 _lib = None
@@ -91,6 +108,13 @@ def lib():
         "kmv_profile_read": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                        C.POINTER(C.c_double)]),
         "kmv_problem_destroy": (C.c_int, [_P]),
+        "kmv_server_create": (C.c_int, [C.c_size_t, C.c_int, C.POINTER(_P)]),
+        "kmv_server_submit": (C.c_int, [_P, C.POINTER(kmv_request), C.POINTER(C.c_uint64)]),
+        "kmv_server_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(kmv_result)]),
+        "kmv_server_wait": (C.c_int, [_P, C.c_uint64, C.c_double, C.POINTER(kmv_result)]),
+        "kmv_server_release": (C.c_int, [_P, C.c_uint64]),
+        "kmv_server_stats": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_size_t)]),
+        "kmv_server_destroy": (C.c_int, [_P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -271,3 +295,81 @@ def kmv_profile_read(p, variant):
 
 def kmv_problem_destroy(p):
     _check(lib().kmv_problem_destroy(p))
+
+
+# -------------------------------------------------------------------- serving
+def kmv_server_create(mem_budget=0, max_slots=4):
+    h = _P()
+    _check(lib().kmv_server_create(mem_budget, max_slots, C.byref(h)))
+    return h
+
+
+def kmv_server_submit(s, mesh, precision, dt, n_steps, c, xs, xr, f0, t0, amp=1.0, eta=None,
+                      observed=None, forward_only=False):
+    """Queue one shot.  Host inputs are copied before this returns."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    xs = np.ascontiguousarray(np.atleast_2d(xs), dtype=np.float64)
+    xr = np.ascontiguousarray(np.atleast_2d(xr), dtype=np.float64)
+    eta = None if eta is None else np.ascontiguousarray(eta, dtype=np.float64)
+    obs = None
+    if not forward_only:
+        obs = np.ascontiguousarray(observed, dtype=np.float64 if precision == KMV_FP64 else np.float32)
+        if obs.size != n_steps * len(xr):
+            raise ValueError("observed must hold n_steps * n_rec values")
+    req = kmv_request(mesh, precision, dt, n_steps, _dptr(c), None if eta is None else _dptr(eta), _dptr(xs),
+                      len(xs), f0, t0, amp, _dptr(xr), len(xr), 1 if forward_only else 0,
+                      None if obs is None else obs.ctypes.data_as(C.c_void_p))
+    t = C.c_uint64()
+    _check(lib().kmv_server_submit(s, C.byref(req), C.byref(t)))
+    return t.value
+
+
+def _result_dict(r, precision_hint=None):
+    out = dict(status=r.status, J=r.J, n_steps=r.n_steps, n_rec=r.n_rec, n_dofs=r.n_dofs,
+               t_submit=r.t_submit, t_admit=r.t_admit, t_done=r.t_done, device_bytes=r.device_bytes,
+               traces=None, grad=None)
+    if r.status == KMV_OK:
+        n = r.n_steps * r.n_rec
+        if r.traces:
+            ct = C.c_double if precision_hint == KMV_FP64 else C.c_float
+            buf = (ct * n).from_address(r.traces)
+            out["traces"] = np.array(np.frombuffer(buf, dtype=np.float64 if ct is C.c_double else np.float32),
+                                     copy=True).reshape(r.n_steps, r.n_rec)
+        if r.grad:
+            out["grad"] = np.array(np.ctypeslib.as_array(r.grad, shape=(r.n_dofs,)), copy=True)
+    else:
+        out["error"] = kmv_last_error()
+    return out
+
+
+def kmv_server_poll(s, ticket, precision):
+    """None while pending, else the result (copied out of the library's buffers)."""
+    r = kmv_result()
+    rc = lib().kmv_server_poll(s, ticket, C.byref(r))
+    if rc == KMV_EBUSY:
+        return None
+    _check(rc)
+    return _result_dict(r, precision)
+
+
+def kmv_server_wait(s, ticket, precision, timeout_s=-1.0):
+    r = kmv_result()
+    rc = lib().kmv_server_wait(s, ticket, timeout_s, C.byref(r))
+    if rc == KMV_EBUSY:
+        return None
+    _check(rc)
+    return _result_dict(r, precision)
+
+
+def kmv_server_release(s, ticket):
+    _check(lib().kmv_server_release(s, ticket))
+
+
+def kmv_server_stats(s):
+    v = [C.c_int(), C.c_int(), C.c_size_t()]
+    _check(lib().kmv_server_stats(s, *[C.byref(x) for x in v]))
+    return dict(running=v[0].value, queued=v[1].value, bytes_in_use=v[2].value)
+
+
+def kmv_server_destroy(s):
+    _check(lib().kmv_server_destroy(s))
