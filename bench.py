@@ -120,7 +120,7 @@ def time_gpu(precision, steps, warmup, every, window=0):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        J, g, _ = prob.misfit_gradient(c, obs)
+        J, g, tr = prob.misfit_gradient(c, obs, keep_traces=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sec = (t1 - t0) / steps
@@ -130,9 +130,9 @@ def time_gpu(precision, steps, warmup, every, window=0):
     info = prob.info()
     out = dict(sec=sec, J=J, n_dofs=m.n_dofs, n_cells=m.n_cells, nt=nt, dt=dt, prof=prof,
                checkpoint_every=info["checkpoint_every"], n_patches=m.n_patches,
-               n_shared=m.n_shared_dofs)
+               n_shared=m.n_shared_dofs, grad=g.cpu().numpy(), traces=tr.double().cpu().numpy())
     prob.close()
-    del g
+    del g, tr
     torch.cuda.empty_cache()
     return out
 
@@ -147,7 +147,7 @@ def roofline(res, ts, dim=2):
         total = p["launches"] * p["mean_ms"]
         b = algorithmic_bytes(variant, res["n_dofs"], res["n_cells"], dim, ts)
         achieved = b / (p["mean_ms"] * 1e-3) / 1e9
-        r = {"kernel": f"k_patch ({variant})", "bound": "hbm", "achieved": round(achieved, 1),
+        r = {"kernel": f"k_step ({variant.split('_')[1]})", "bound": "hbm", "achieved": round(achieved, 1),
              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
              "traffic": traffic_from_profiles(variant, hash_), "algorithmic_bytes": int(b),
              "mean_launch_us": round(p["mean_ms"] * 1e3, 3), "launches": p["launches"],
@@ -191,6 +191,143 @@ def cpu_baseline(n_sample=120):
                       f"adjoint + gradient, FP64 assembled CSR, one thread; {sec:.1f}s"}
 
 
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - np.asarray(b, np.float64)) / np.linalg.norm(b))
+
+
+def serving_bench(n_requests=48, t_scale=0.1, slots=6, load=0.7, seed=11):
+    """The serving mix: Poisson arrivals of shot requests over three seeded layered
+    meshes (about 20k, 80k and 300k triangles), KMV degree uniform in {2,3,4,5},
+    duration uniform in [1, 4] s x t_scale, 10% forward-only, the rest misfit +
+    gradient against FP64 observed data of the model with anomalies (four shot
+    positions per mesh, cached).  The offered load is `load` x the saturation
+    throughput of the FP32 server (all requests submitted at once); the same
+    arrival trace is then replayed through the FP32 server and through the plain
+    per-shot FP64 path (one solve at a time, in arrival order)."""
+    import torch
+    from paper_2108_10946_amd import Mesh, Problem, Server
+    from synth import configs
+    from synth.models import sponge_eta, surface_receivers
+    rng = np.random.default_rng(seed)
+    rec = surface_receivers(300, 0.1, 7.9, 0.1)
+    positions = [np.array([[x, 0.01]]) for x in np.linspace(0.5, 7.5, 4)]
+    cuda = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    disc = {}
+    t = time.time()
+    for i in range(3):
+        coords, cells, vp, vpo = configs.serving_mesh(i)
+        for k in (2, 3, 4, 5):
+            m = Mesh(coords, cells, k)
+            x = m.dof_coords()
+            c, co = vp(x[:, 0], x[:, 1]), vpo(x[:, 0], x[:, 1])
+            eta = sponge_eta(x[:, 0], x[:, 1], 0.0, 8.0, 3.0, 0.75, c_max=4.5)
+            probe = Problem(m, 1e-4, 4, precision="fp64")
+            rho = max(probe.spectral_radius(cuda(c), iters=100), probe.spectral_radius(cuda(co), iters=100))
+            probe.close()
+            disc[(i, k)] = dict(mesh=m, c=c, c_obs=co, eta=eta, dt=0.9 * 2.0 / np.sqrt(rho),
+                                cells=len(cells))
+    log(f"serving: 12 discretisations ready ({time.time() - t:.1f}s)")
+    reqs = []
+    for r in range(n_requests):
+        key = (int(rng.integers(3)), int(rng.choice([2, 3, 4, 5])))
+        T = rng.uniform(1.0, 4.0) * t_scale
+        d = disc[key]
+        reqs.append(dict(key=key, pos=int(rng.integers(4)), nt=max(1, int(round(T / d["dt"]))),
+                         fwd=bool(rng.random() < 0.1)))
+    # observed data, FP64, per (mesh, degree, position) at the longest window used
+    t = time.time()
+    obs = {}
+    for (key, pos) in sorted({(q["key"], q["pos"]) for q in reqs}):
+        d = disc[key]
+        nt = max(q["nt"] for q in reqs if q["key"] == key and q["pos"] == pos)
+        pr = Problem(d["mesh"], d["dt"], nt, precision="fp64")
+        pr.set_damping(d["eta"])
+        pr.set_sources(positions[pos], f0=5.0, t0=0.2)
+        pr.set_receivers(rec)
+        obs[(key, pos)] = pr.forward(cuda(d["c_obs"])).cpu().numpy()
+        pr.close()
+    torch.cuda.synchronize()
+    log(f"serving: observed data for {len(obs)} shots ({time.time() - t:.1f}s)")
+
+    def submit(srv, q, precision):
+        d = disc[q["key"]]
+        o = None if q["fwd"] else obs[(q["key"], q["pos"])][:q["nt"]]
+        return srv.submit(d["mesh"], d["c"], positions[q["pos"]], rec, d["dt"], q["nt"], precision=precision,
+                          eta=d["eta"], observed=o, forward_only=q["fwd"], f0=5.0, t0=0.2)
+
+    dof_steps = sum(disc[q["key"]]["mesh"].n_dofs * q["nt"] for q in reqs)
+    # saturation: every request at once
+    srv = Server(max_slots=slots)
+    t0 = time.perf_counter()
+    tk = [submit(srv, q, "fp32") for q in reqs]
+    res_sat = [srv.result(x) for x in tk]
+    t_sat = time.perf_counter() - t0
+    srv.close()
+    assert all(r["status"] == 0 for r in res_sat), [r.get("error") for r in res_sat if r["status"]]
+    sat = n_requests / t_sat
+    lam = load * sat
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, n_requests))
+    log(f"serving: saturation {sat:.2f} shots/s over {t_sat:.1f}s; offered load {lam:.2f}/s")
+
+    # FP32 server, Poisson arrivals
+    srv = Server(max_slots=slots)
+    start = time.perf_counter()
+    tk = []
+    for q, ta in zip(reqs, arrivals):
+        wait = start + ta - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        tk.append(submit(srv, q, "fp32"))
+    res = [srv.result(x) for x in tk]
+    srv.close()
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+    span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+    # the served results equal the saturation run's (same requests, other mix)
+    same = all(np.array_equal(a["traces"], b["traces"]) and a["J"] == b["J"] for a, b in zip(res, res_sat))
+    log(f"serving fp32: p50 {np.median(lat):.3f}s p99 {np.percentile(lat, 99):.3f}s, "
+        f"{n_requests / span:.2f} shots/s; equal across mixes: {same}")
+
+    # plain per-shot FP64, same arrival trace
+    start = time.perf_counter()
+    lat64 = []
+    for q, ta in zip(reqs, arrivals):
+        now = time.perf_counter() - start
+        if now < ta:
+            time.sleep(ta - now)
+        d = disc[q["key"]]
+        pr = Problem(d["mesh"], d["dt"], q["nt"], precision="fp64", mem_budget=64 << 30)
+        pr.set_damping(d["eta"])
+        pr.set_sources(positions[q["pos"]], f0=5.0, t0=0.2)
+        pr.set_receivers(rec)
+        if q["fwd"]:
+            pr.forward(cuda(d["c"]))
+        else:
+            pr.misfit_gradient(cuda(d["c"]), cuda(obs[(q["key"], q["pos"])][:q["nt"]]))
+        torch.cuda.synchronize()
+        pr.close()
+        lat64.append(time.perf_counter() - start - ta)
+    lat64 = np.array(lat64)
+    span64 = time.perf_counter() - start - arrivals[0]
+    log(f"plain fp64: p50 {np.median(lat64):.3f}s p99 {np.percentile(lat64, 99):.3f}s, "
+        f"{n_requests / span64:.2f} shots/s")
+    return {
+        "workload": f"{n_requests} Poisson shot requests over 3 layered meshes "
+                    f"({', '.join(str(disc[(i, 2)]['cells']) for i in range(3))} cells), KMV k in {{2,3,4,5}}, "
+                    f"T ~ U[{1.0 * t_scale:g}, {4.0 * t_scale:g}] s, 10% forward-only, FP64 observed data",
+        "duration_scale": t_scale,
+        "offered_load_shots_per_s": round(lam, 3),
+        "saturation_shots_per_s": round(sat, 3),
+        "dof_timesteps_total": int(dof_steps),
+        "fp32_server": {"slots": slots, "p50_latency_s": round(float(np.median(lat)), 4),
+                        "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+                        "shots_per_s": round(n_requests / span, 3),
+                        "results_equal_across_mixes": bool(same)},
+        "fp64_plain": {"p50_latency_s": round(float(np.median(lat64)), 4),
+                       "p99_latency_s": round(float(np.percentile(lat64, 99)), 4),
+                       "shots_per_s": round(n_requests / span64, 3)},
+    }
+
+
 def copy_calibration(n_bytes=1 << 30, reps=3):
     """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE
     counters of a profiled run to bytes."""
@@ -215,6 +352,10 @@ def main():
     ap.add_argument("--window", type=int, default=0,
                     help="run only the first WINDOW time steps (hardware-counter runs: the "
                          "per-launch traffic does not depend on the window); not a bench line")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=48)
+    ap.add_argument("--serving-scale", type=float, default=0.1,
+                    help="request durations are U[1,4] s times this (1.0: the full mix)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -240,6 +381,9 @@ def main():
         res64 = time_gpu("fp64", max(1, args.steps // 2), min(1, args.warmup), args.profile_every,
                          args.window)
         roofline(res64, 8)
+    serving = None
+    if not args.no_serving and not args.window:
+        serving = serving_bench(n_requests=args.serving_requests, t_scale=args.serving_scale)
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 
     N, nt = res32["n_dofs"], res32["nt"]
@@ -273,6 +417,14 @@ def main():
         "kernel_mean_us": {k: round(v["mean_ms"] * 1e3, 3) for k, v in res32["prof"].items()},
         "cpu_baseline": cpu,
     }
+    if serving:
+        out["p50_shot_latency_s"] = serving["fp32_server"]["p50_latency_s"]
+        out["p99_shot_latency_s"] = serving["fp32_server"]["p99_latency_s"]
+        out["serving"] = serving
+    if res64:
+        out["fp32_vs_fp64"] = {"J": abs(res32["J"] - res64["J"]) / abs(res64["J"]),
+                               "traces": _rel(res32["traces"], res64["traces"]),
+                               "grad": _rel(res32["grad"], res64["grad"])}
     if args.window:
         out["window"] = args.window
         out["note"] = "time window cut for a hardware-counter run: not a bench line"

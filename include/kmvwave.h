@@ -229,7 +229,7 @@ typedef struct {
 } kmv_result;
 
 /* mem_budget: device bytes for requests (0 = 80% of the free memory).  Each
- * request keeps all its states if they fit in min(mem_budget, 8 GiB), else it
+ * request keeps all its states if they fit in min(mem_budget/2, 32 GiB), else it
  * checkpoints (as kmv_options.checkpoint_every = 0).
  * max_slots: requests that may run at once (1..64).
  * Errors: KMV_EINVAL, KMV_EDEVICE. */

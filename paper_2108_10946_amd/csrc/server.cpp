@@ -170,10 +170,10 @@ Status server_create(size_t budget, int slots, Server** out) {
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return Status{KMV_EDEVICE, "hipMemGetInfo failed"};
   S->budget = budget ? std::min(budget, free_b) : free_b / 10 * 8;
   S->slots = slots;
-  // state storage each request may use before it checkpoints (as a problem's
-  // default); independent of the slot count, so a request's plan and memory do
-  // not depend on how many others may run beside it
-  S->per_job_budget = std::min(S->budget, (size_t)8 << 30);
+  // state storage each request may use before it checkpoints; independent of the
+  // slot count, so a request's plan and memory do not depend on how many others
+  // may run beside it
+  S->per_job_budget = std::min(S->budget / 2, (size_t)32 << 30);
   S->epoch = std::chrono::steady_clock::now();
   // keep freed blocks in the stream-ordered pool instead of returning them
   hipMemPool_t pool;
