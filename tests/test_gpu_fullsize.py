@@ -1,0 +1,146 @@
+"""Parity at the full size of the layered KMV4 workload (150,022 triangles, 1.65 M
+DOFs), in the launch configuration bench.py times (default patches).
+
+The oracle computes these outputs directly at this size: one stiffness apply
+(assembled CSR), and misfit, traces and gradient over a short time window (a
+Ricker wavelet with an early delay so that the window holds signal).  Over the
+whole window only properties that hold at any size are checked: the dot-product
+identity of the adjoint, and central differences of the multi-shot misfit along
+a smooth seeded direction (the 40-shot gradient workload, with fewer shots and a
+shorter window).  Tolerances as in the small-case parity tests."""
+import numpy as np
+import pytest
+
+from gpu_util import say, dof_map, rel_l2
+from synth import configs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+torch = pytest.importorskip("torch")
+
+DT = 2.8e-4  # below the power-iteration bound 2/sqrt(rho) = 3.19e-4 of this model
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_10946_amd as kmv
+    kmv.lib()
+
+
+@pytest.fixture(scope="module")
+def c2():
+    from paper_2108_10946_amd import Mesh
+    from oracle.fem import Discretization
+    w = configs.layered_kmv4()
+    say("full size: oracle discretisation of the layered KMV4 mesh")
+    d = Discretization(w.coords, w.cells, w.degree)
+    m = Mesh(w.coords, w.cells, w.degree)
+    p = dof_map(m.dof_coords(), d.dof_coords)
+    return w, d, m, p
+
+
+def cuda(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_apply_full_size(c2, prec, tol):
+    from paper_2108_10946_amd import Problem
+    w, d, m, p = c2
+    say(f"full size: stiffness apply {prec}")
+    c = d.nodal_values(w.vp_obs)
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal(d.n_dofs)
+    y_or = d.stiffness(c) @ u
+    prob = Problem(m, DT, 4, precision=prec)
+    y = prob.stiffness_apply(cuda(c[p]), cuda(u[p], prob.dtype)).double().cpu().numpy()
+    assert rel_l2(y, y_or[p]) < tol
+
+
+def test_misfit_gradient_window_fp64(c2):
+    """Forward, misfit, adjoint and gradient over 120 steps against the oracle."""
+    from paper_2108_10946_amd import Problem
+    from oracle import solver
+    w, d, m, p = c2
+    nt, t0 = 120, 0.01
+    say("full size: 120-step misfit + gradient, FP64")
+    c_obs, c0 = d.nodal_values(w.vp_obs), d.nodal_values(w.vp)
+    eta = d.nodal_values(w.eta)
+    sh = solver.Shot(d, w.sources, w.receivers, DT, nt, f0=w.f0, t0=t0)
+    dobs, _ = sh.forward(c_obs, eta)
+    J, g, tr = sh.misfit_gradient(c0, dobs, eta)
+    for prec, tol_t, tol_g in (("fp64", 1e-10, 1e-10), ("fp32", 1e-4, 1e-3)):
+        prob = Problem(m, DT, nt, precision=prec)
+        prob.set_damping(eta[p])
+        prob.set_sources(w.sources, f0=w.f0, t0=t0)
+        prob.set_receivers(w.receivers)
+        Jg, gg, trg = prob.misfit_gradient(cuda(c0[p]), cuda(dobs, prob.dtype), keep_traces=True)
+        et, eg = rel_l2(trg.double().cpu().numpy(), tr), rel_l2(gg.cpu().numpy(), g[p])
+        say(f"  {prec}: J rel {abs(Jg - J) / J:.2e} traces {et:.2e} gradient {eg:.2e}")
+        assert et < tol_t and eg < tol_g
+        assert abs(Jg - J) < 10 * tol_t * J
+        prob.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_dot_product_full_size(c2, prec, tol):
+    """<y, P u(w)> = dt^2 sum_n w_n s . lambda^{n+1}(y) over 2000 steps."""
+    from paper_2108_10946_amd import Problem
+    w, d, m, p = c2
+    nt = 2000
+    say(f"full size: dot product {prec}")
+    x = m.dof_coords()
+    prob = Problem(m, DT, nt, precision=prec)
+    prob.set_damping(w.eta(x[:, 0], x[:, 1]))
+    prob.set_sources(w.sources, f0=w.f0, t0=0.05)
+    rng = np.random.default_rng(7)
+    wav = rng.standard_normal(nt)
+    prob.set_source_wavelet(wav)
+    prob.set_receivers(w.receivers)
+    c = cuda(w.vp_obs(x[:, 0], x[:, 1]))
+    tr = prob.forward(c).double().cpu().numpy()
+    y = rng.standard_normal((nt, len(w.receivers)))
+    _, st = prob.adjoint(c, cuda(y, prob.dtype), src_trace=True)
+    lhs = np.sum(y * tr)
+    rhs = DT * DT * np.sum(wav * st.double().cpu().numpy()[:, 0])
+    say(f"  lhs {lhs:.12e} rhs {rhs:.12e} rel {abs(lhs - rhs) / abs(lhs):.2e}")
+    assert abs(lhs - rhs) < tol * abs(lhs)
+
+
+@pytest.mark.parametrize("prec,h,tol", [("fp64", 5e-4, 1e-6), ("fp32", 1e-3, 1e-2)])
+def test_multishot_central_differences(c2, prec, h, tol):
+    """Sum over 4 surface shots (of the 40-shot workload's line), 1000 steps."""
+    from paper_2108_10946_amd import Problem, fwi_misfit
+    w, d, m, p = c2
+    nt = 1000
+    say(f"full size: 4-shot central differences {prec}")
+    x = m.dof_coords()
+    eta = w.eta(x[:, 0], x[:, 1])
+    c_true = cuda(w.vp_obs(x[:, 0], x[:, 1]))
+    c0 = w.vp(x[:, 0], x[:, 1])
+    probs, obs = [], []
+    for xs in np.linspace(0.1, 7.9, 40)[[5, 15, 25, 35]]:
+        pr = Problem(m, DT, nt, precision=prec)
+        pr.set_damping(eta)
+        pr.set_sources([[xs, 0.01]], f0=w.f0, t0=0.1)
+        pr.set_receivers(w.receivers)
+        obs.append(pr.forward(c_true))
+        probs.append(pr)
+    # seeded smooth direction: five Gaussians of radius 0.5 km, max 1 km/s, zero in the sponge
+    rng = np.random.default_rng(13)
+    dvec = np.zeros(len(x))
+    for _ in range(5):
+        cx, cz = rng.uniform([1.0, 0.3], [7.0, 2.7])
+        dvec += rng.choice([-1.0, 1.0]) * np.exp(-((x[:, 0] - cx) ** 2 + (x[:, 1] - cz) ** 2) / 0.25)
+    dvec[eta > 0] = 0.0
+    dvec /= np.abs(dvec).max()
+    c = cuda(c0).requires_grad_(True)
+    J = fwi_misfit(c, probs, obs)
+    J.backward()
+    an = float(c.grad.cpu().numpy() @ dvec)
+    fd = (float(fwi_misfit(cuda(c0 + h * dvec), probs, obs)) -
+          float(fwi_misfit(cuda(c0 - h * dvec), probs, obs))) / (2 * h)
+    say(f"  J {float(J):.6e} fd {fd:.9e} an {an:.9e} rel {abs(fd - an) / abs(an):.2e}")
+    assert abs(fd - an) < tol * abs(an)
