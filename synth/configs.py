@@ -17,8 +17,9 @@ Names describe the workload:
   layered_kmv4_40shots  the same with 40 shots along the surface.
   serving_meshes    three layered/anomaly meshes of about 20k, 80k, 300k cells.
   layered_tet_kmv3  3D 4 x 4 x 2 km layered + anomalies, 500 m sponge on five
-                    faces, Maubach-graded Kuhn tetrahedra, KMV3tet, 40x40
-                    receiver grid, T = 2 s.
+                    faces, Maubach-graded Kuhn tetrahedra (shortest edge below
+                    s * vp / (5 Hz * 2.5), s = 0.355 -> 1.33M tetrahedra, 16.9M KMV3 DOFs),
+                    KMV3tet, 40x40 receiver grid, T = 2 s.
 """
 from __future__ import annotations
 
@@ -140,7 +141,7 @@ def _sponge3d(x, y, z):
 
 
 @functools.lru_cache(maxsize=None)
-def layered_tet_kmv3(seed=21, coarse_h=0.5, scale=1.0):
+def layered_tet_kmv3(seed=21, coarse_h=0.5, scale=0.355):
     vp = layered_anomaly_vp_3d(seed)
 
     def hfun(x, y, z):

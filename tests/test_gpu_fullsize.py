@@ -2,12 +2,12 @@
 DOFs), in the launch configuration bench.py times (default patches).
 
 The oracle computes these outputs directly at this size: one stiffness apply
-(assembled CSR), and misfit, traces and gradient over a short time window (a
-Ricker wavelet with an early delay so that the window holds signal).  Over the
+(assembled CSR), and misfit, traces and gradient over a 300-step window (a Ricker
+wavelet with an early delay so that the window holds signal).  Over the
 whole window only properties that hold at any size are checked: the dot-product
 identity of the adjoint, and central differences of the multi-shot misfit along
-a smooth seeded direction (the 40-shot gradient workload, with fewer shots and a
-shorter window).  Tolerances as in the small-case parity tests."""
+a smooth seeded direction, converging as h^2 (the 40-shot gradient workload,
+with fewer shots and a shorter window).  Tolerances as in the small-case parity tests."""
 import numpy as np
 import pytest
 
@@ -60,13 +60,16 @@ def test_apply_full_size(c2, prec, tol):
 
 
 def test_misfit_gradient_window_fp64(c2):
-    """Forward, misfit, adjoint and gradient over 120 steps against the oracle."""
+    """Forward, misfit, adjoint and gradient over 300 steps against the oracle.  The
+    current model differs from the observed one by a -10% bump between the source
+    and the receivers, so the window's misfit is far above rounding level."""
     from paper_2108_10946_amd import Problem
     from oracle import solver
     w, d, m, p = c2
-    nt, t0 = 120, 0.01
-    say("full size: 120-step misfit + gradient, FP64")
-    c_obs, c0 = d.nodal_values(w.vp_obs), d.nodal_values(w.vp)
+    nt, t0 = 300, 0.02
+    say("full size: 300-step misfit + gradient")
+    c_obs = d.nodal_values(w.vp_obs)
+    c0 = d.nodal_values(lambda x, z: w.vp_obs(x, z) * (1.0 - 0.1 * np.exp(-((x - 4.0) ** 2 + (z - 0.05) ** 2) / 0.002)))
     eta = d.nodal_values(w.eta)
     sh = solver.Shot(d, w.sources, w.receivers, DT, nt, f0=w.f0, t0=t0)
     dobs, _ = sh.forward(c_obs, eta)
@@ -78,7 +81,7 @@ def test_misfit_gradient_window_fp64(c2):
         prob.set_receivers(w.receivers)
         Jg, gg, trg = prob.misfit_gradient(cuda(c0[p]), cuda(dobs, prob.dtype), keep_traces=True)
         et, eg = rel_l2(trg.double().cpu().numpy(), tr), rel_l2(gg.cpu().numpy(), g[p])
-        say(f"  {prec}: J rel {abs(Jg - J) / J:.2e} traces {et:.2e} gradient {eg:.2e}")
+        say(f"  {prec}: J {Jg:.6e} (oracle {J:.6e}) traces {et:.2e} gradient {eg:.2e}")
         assert et < tol_t and eg < tol_g
         assert abs(Jg - J) < 10 * tol_t * J
         prob.close()
@@ -109,38 +112,47 @@ def test_dot_product_full_size(c2, prec, tol):
     assert abs(lhs - rhs) < tol * abs(lhs)
 
 
-@pytest.mark.parametrize("prec,h,tol", [("fp64", 5e-4, 1e-6), ("fp32", 1e-3, 1e-2)])
-def test_multishot_central_differences(c2, prec, h, tol):
-    """Sum over 4 surface shots (of the 40-shot workload's line), 1000 steps."""
+@pytest.mark.parametrize("prec,hs,tol", [("fp64", (4e-4, 1e-4), 1e-6), ("fp32", (1e-3,), 1e-2)])
+def test_multishot_central_differences(c2, prec, hs, tol):
+    """Sum over 4 surface shots (of the 40-shot workload's line), 1000 steps.  The
+    observed model adds shallow bumps near the shots, so the misfit over this window
+    is large; the direction is a seeded sum of five shallow Gaussians."""
     from paper_2108_10946_amd import Problem, fwi_misfit
     w, d, m, p = c2
     nt = 1000
     say(f"full size: 4-shot central differences {prec}")
     x = m.dof_coords()
     eta = w.eta(x[:, 0], x[:, 1])
-    c_true = cuda(w.vp_obs(x[:, 0], x[:, 1]))
+    shots = np.linspace(0.1, 7.9, 40)[[5, 15, 25, 35]]
     c0 = w.vp(x[:, 0], x[:, 1])
+    bumps = sum(np.exp(-((x[:, 0] - xs - 0.1) ** 2 + (x[:, 1] - 0.12) ** 2) / 0.005) for xs in shots)
+    c_true = cuda(c0 * (1.0 + 0.1 * bumps))
     probs, obs = [], []
-    for xs in np.linspace(0.1, 7.9, 40)[[5, 15, 25, 35]]:
+    for xs in shots:
         pr = Problem(m, DT, nt, precision=prec)
         pr.set_damping(eta)
         pr.set_sources([[xs, 0.01]], f0=w.f0, t0=0.1)
         pr.set_receivers(w.receivers)
         obs.append(pr.forward(c_true))
         probs.append(pr)
-    # seeded smooth direction: five Gaussians of radius 0.5 km, max 1 km/s, zero in the sponge
     rng = np.random.default_rng(13)
     dvec = np.zeros(len(x))
-    for _ in range(5):
-        cx, cz = rng.uniform([1.0, 0.3], [7.0, 2.7])
-        dvec += rng.choice([-1.0, 1.0]) * np.exp(-((x[:, 0] - cx) ** 2 + (x[:, 1] - cz) ** 2) / 0.25)
+    for xs in shots:
+        cx, cz = xs + rng.uniform(-0.15, 0.15), rng.uniform(0.05, 0.2)
+        dvec += rng.choice([-1.0, 1.0]) * np.exp(-((x[:, 0] - cx) ** 2 + (x[:, 1] - cz) ** 2) / 0.01)
     dvec[eta > 0] = 0.0
     dvec /= np.abs(dvec).max()
     c = cuda(c0).requires_grad_(True)
     J = fwi_misfit(c, probs, obs)
     J.backward()
     an = float(c.grad.cpu().numpy() @ dvec)
-    fd = (float(fwi_misfit(cuda(c0 + h * dvec), probs, obs)) -
-          float(fwi_misfit(cuda(c0 - h * dvec), probs, obs))) / (2 * h)
-    say(f"  J {float(J):.6e} fd {fd:.9e} an {an:.9e} rel {abs(fd - an) / abs(an):.2e}")
-    assert abs(fd - an) < tol * abs(an)
+    errs = []
+    for h in hs:
+        fd = (float(fwi_misfit(cuda(c0 + h * dvec), probs, obs)) -
+              float(fwi_misfit(cuda(c0 - h * dvec), probs, obs))) / (2 * h)
+        errs.append(abs(fd - an) / abs(an))
+        say(f"  J {float(J):.6e} h {h:.0e} fd {fd:.9e} an {an:.9e} rel {errs[-1]:.2e}")
+    assert float(J) > 1e-6
+    assert errs[-1] < tol
+    if len(errs) > 1:  # central differences converge as h^2 (16x per halving of h twice)
+        assert errs[-1] < errs[0] / 8

@@ -1,0 +1,102 @@
+"""The 3D workload at full size: layered model with anomalies on 1.33 M
+Maubach-graded tetrahedra (bisection refines in discrete levels; the nearest level
+to the 1.5 M of the workload), KMV3tet (16.9 M DOFs), FP32 fields with float64
+accumulation, checkpointed reverse sweep.
+
+The oracle cannot assemble this operator in reasonable time, so full-size checks
+are properties that hold at any size: the dot-product identity of the adjoint
+and central differences of the misfit along a smooth seeded direction.  Oracle
+parity of the same kernels in 3D runs on small tetrahedral meshes
+(test_gpu_parity.py)."""
+import numpy as np
+import pytest
+
+from gpu_util import say
+from synth import configs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_10946_amd as kmv
+    kmv.lib()
+
+
+def cuda(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+@pytest.fixture(scope="module")
+def c5():
+    from paper_2108_10946_amd import Mesh, Problem
+    say("3D full size: generating the graded tetrahedral mesh")
+    w = configs.layered_tet_kmv3()
+    say(f"3D full size: {len(w.cells)} tetrahedra; building the discretisation")
+    m = Mesh(w.coords, w.cells, w.degree)
+    x = m.dof_coords()
+    c = w.vp(x[:, 0], x[:, 1], x[:, 2])
+    eta = w.eta(x[:, 0], x[:, 1], x[:, 2])
+    probe = Problem(m, 1e-4, 4, precision="fp32")
+    rho = probe.spectral_radius(cuda(c), iters=100)
+    probe.close()
+    dt = 0.7 * 2.0 / np.sqrt(rho)  # margin: 100 power iterations underestimate rho
+    say(f"3D full size: {m.n_dofs} DOFs, dt = {dt * 1e3:.4f} ms")
+    return w, m, x, c, eta, dt
+
+
+def test_dot_product_3d(c5):
+    from paper_2108_10946_amd import Problem
+    w, m, x, c, eta, dt = c5
+    nt = 300
+    say("3D full size: dot product, FP32")
+    prob = Problem(m, dt, nt, precision="fp32")
+    prob.set_damping(eta)
+    prob.set_sources(w.sources, f0=w.f0, t0=0.05)
+    rng = np.random.default_rng(9)
+    wav = rng.standard_normal(nt)
+    prob.set_source_wavelet(wav)
+    prob.set_receivers(w.receivers)
+    cd = cuda(c)
+    tr = prob.forward(cd).double().cpu().numpy()
+    y = rng.standard_normal((nt, len(w.receivers)))
+    _, st = prob.adjoint(cd, cuda(y, prob.dtype), src_trace=True)
+    lhs = np.sum(y * tr)
+    rhs = dt * dt * np.sum(wav * st.double().cpu().numpy()[:, 0])
+    say(f"  lhs {lhs:.9e} rhs {rhs:.9e} rel {abs(lhs - rhs) / abs(lhs):.2e}")
+    assert abs(lhs - rhs) < 1e-5 * abs(lhs)
+
+
+def test_checkpointed_gradient_central_differences_3d(c5):
+    """FP32 fields, float64 gradient accumulation, checkpoints every 25 steps."""
+    from paper_2108_10946_amd import Problem, fwi_misfit
+    w, m, x, c, eta, dt = c5
+    nt, h = 300, 1e-3
+    say("3D full size: checkpointed misfit gradient vs central differences, FP32")
+    prob = Problem(m, dt, nt, precision="fp32", checkpoint_every=25)
+    prob.set_damping(eta)
+    prob.set_sources(w.sources, f0=w.f0, t0=0.05)
+    prob.set_receivers(w.receivers)
+    # observed data from a model with a smooth bump under the source
+    bump = np.exp(-((x[:, 0] - 2.0) ** 2 + (x[:, 1] - 2.0) ** 2 + (x[:, 2] - 0.15) ** 2) / 0.01)
+    obs = prob.forward(cuda(c * (1.0 + 0.1 * bump)))
+    rng = np.random.default_rng(17)
+    d = np.zeros(len(x))
+    for _ in range(5):
+        cx, cy, cz = rng.uniform([1.5, 1.5, 0.05], [2.5, 2.5, 0.4])
+        d += rng.choice([-1.0, 1.0]) * np.exp(-((x[:, 0] - cx) ** 2 + (x[:, 1] - cy) ** 2 +
+                                                (x[:, 2] - cz) ** 2) / 0.02)
+    d[eta > 0] = 0.0
+    d /= np.abs(d).max()
+    cc = cuda(c).requires_grad_(True)
+    J = fwi_misfit(cc, prob, obs)
+    J.backward()
+    an = float(cc.grad.cpu().numpy() @ d)
+    fd = (float(fwi_misfit(cuda(c + h * d), prob, obs)) - float(fwi_misfit(cuda(c - h * d), prob, obs))) / (2 * h)
+    say(f"  J {float(J):.6e} fd {fd:.6e} an {an:.6e} rel {abs(fd - an) / abs(an):.2e}")
+    assert prob.info()["checkpoint_every"] == 25
+    assert abs(fd - an) < 1e-2 * abs(an)
