@@ -45,10 +45,11 @@ struct StepLds {
   }
 };
 
-// Items per thread whose global loads are issued together (latency hiding).
-template <typename T>
+// Items per thread whose global loads are issued together (latency hiding); the
+// adjoint holds fewer owned DOFs to stay within 168 VGPRs (three waves per SIMD).
+template <typename T, bool ADJ = false>
 struct Batch {
-  static constexpr int kOwned = sizeof(T) == 4 ? 5 : 2;   // owned non-interior DOFs in registers
+  static constexpr int kOwned = sizeof(T) == 4 ? 5 : 2;  // owned non-interior DOFs in registers
   static constexpr int kWords = sizeof(T) == 4 ? 6 : 4;   // gather words in registers
   static constexpr int kShared = 2;                       // shared refs in the first batch
   static constexpr int kList = 1;                         // 16-byte gather-list words
@@ -98,35 +99,32 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
 
   // ---- every global load first, as one straight run: indices of idle lanes are
   // clamped into range instead of branched on (their values are never used), so
-  // nothing forces a wait until the loads are all in flight.  Loads complete in
-  // issue order; the index loads of the first shared refs go out first.
+  // nothing forces a wait until the loads are all in flight.  What a shared ref
+  // needs to finish its DOF is stored at the ref's own index (the level's copy, the
+  // increment, c^2, gamma, beta), except the other patches' partial sums, whose
+  // slots are loaded here and which are read after the bulk loads.
   constexpr int KH = Batch<T>::kShared;
-  int gg[KH];
-  int2 sl[KH];
-#pragma unroll
-  for (int t = 0; t < KH; ++t) {
-    const int jc = sh0 + min(tid + t * bs, max(nsh - 1, 0));  // padded: always in range
-    gg[t] = A.sh_idx[jc];
-    sl[t] = reinterpret_cast<const int2*>(A.ref_slots)[jc];
-  }
+  const int64_t N = A.n_dofs;
   const bool damped = A.beta != nullptr && A.damp_patch[p] != 0;
-  const T* bsrc = damped ? A.beta : A.c2;  // undamped: a valid array already being read
-  // their dependent loads (all pointers valid: without a previous level u_prev is
-  // u_in and the partial and increment buffers are allocated)
-  const T* usrc = A.prev ? A.u_prev : A.u_in;
-  T y0[KH], y1[KH], up[KH], dp[KH], gm[KH], bt[KH], cc[KH], ff[KH];
+  const T* bsrc = damped ? A.beta : A.c2;          // undamped: a valid array already being read
+  const T* bref = damped ? A.beta_ref : A.c2_ref;
+  // shared-ref copies of level n-1 (or of level n without a previous level); the
+  // apply mode's input has no copies and points u_prev at any level vector
+  const T* uref = (step && !A.prev ? A.u_in : A.u_prev) + N;
+  int jc[KH], gg[KH];
+  int2 sl[KH];
+  T up[KH], dp[KH], gm[KH], bt[KH], cc[KH], ff[KH];
 #pragma unroll
   for (int t = 0; t < KH; ++t) {
-    const int g = gg[t];
-    const int64_t s = max(g - A.n_own, (int64_t)0);
-    y0[t] = A.part_prev[sl[t].x];
-    y1[t] = A.part_prev[sl[t].y >= 0 ? sl[t].y : sl[t].x];
-    cc[t] = A.c2[g];
-    if (ADJ) ff[t] = A.uf[g];
-    up[t] = usrc[g];
-    dp[t] = A.dsh_prev[s];
-    gm[t] = A.gamma[g];
-    bt[t] = bsrc[g];
+    jc[t] = sh0 + min(tid + t * bs, max(nsh - 1, 0));  // padded: always in range
+    gg[t] = A.sh_idx[jc[t]];
+    sl[t] = reinterpret_cast<const int2*>(A.ref_slots)[jc[t]];
+    cc[t] = A.c2_ref[jc[t]];
+    if (ADJ) ff[t] = A.uf[N + jc[t]];
+    up[t] = uref[jc[t]];
+    dp[t] = A.dsh_prev[jc[t]];
+    gm[t] = A.gamma_ref[jc[t]];
+    bt[t] = bref[jc[t]];
   }
   // gather lists of the DOFs with more than two contributions
   constexpr int KL = Batch<T>::kList;
@@ -169,7 +167,7 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
 #pragma unroll
   for (int k = 0; k < KW; ++k) gw[k] = gwp[min(tid + k * bs, nbl - 1)];
   // owned non-interior DOFs: level, c^2 [, u^m] and the update operands
-  constexpr int KO = Batch<T>::kOwned;
+  constexpr int KO = Batch<T, ADJ>::kOwned;
   T vu[KO], vc[KO], vf[ADJ ? KO : 1], pdu[KO], pg[KO], pb[KO];
 #pragma unroll
   for (int k = 0; k < KO; ++k) {
@@ -180,6 +178,24 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
     pdu[k] = A.du[gx];
     pg[k] = A.gamma[gx];
     pb[k] = bsrc[gx];
+  }
+  // partial sums of the shared refs' DOFs, at the slots loaded first.  The empty
+  // asm (no instruction) takes the slots as operands: the compiler cannot start
+  // the address arithmetic before it nor move the loads above across it, so every
+  // load above is in flight before these are issued, and waiting for the slots
+  // costs nothing by then.
+  T y0[KH], y1[KH], q0[ADJ ? KH : 1], q1[ADJ ? KH : 1];
+#pragma unroll
+  for (int t = 0; t < KH; ++t) {
+    int sx = sl[t].x, sy = sl[t].y;
+    asm volatile("" : "+v"(sx), "+v"(sy)::"memory");
+    const int sy2 = sy >= 0 ? sy : sx;
+    y0[t] = A.part_prev[sx];
+    y1[t] = A.part_prev[sy2];
+    if (ADJ) {
+      q0[ADJ ? t : 0] = A.partr_prev[sx];
+      q1[ADJ ? t : 0] = A.partr_prev[sy2];
+    }
   }
   if (!damped) {
 #pragma unroll
@@ -200,34 +216,37 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
   for (int b = 0; b < NB; ++b) m[b] = (int)((mp[b / 2] >> (16 * (b & 1))) & 0xFFFFu);
 
   // shared refs: finish the level from the previous step's partials
+  if (!step) {  // apply mode: the input is a plain vector, read by global id
+#pragma unroll
+    for (int t = 0; t < KH; ++t) up[t] = A.u_in[gg[t]];
+  }
   T uu[KH];
 #pragma unroll
   for (int t = 0; t < KH; ++t) {
     uu[t] = up[t];
-    if (!A.prev) continue;
     const int j = tid + t * bs;
-    const int g = gg[t];
-    const int64_t s = max(g - A.n_own, (int64_t)0);
+    if (!(step && A.prev) || j >= nsh) continue;
+    const int r = jc[t], g = gg[t];
+    const int64_t s = g - A.n_own;
     const bool pair = sl[t].y >= 0;  // else: three or more patches, CSR list
     T y = y0[t] + y1[t];
-    if (!pair && j < nsh) {
+    if (!pair) {
       y = T(0);
       for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) y += A.part_prev[A.shp_slot[k]];
     }
     const T dn = (damped ? bt[t] : T(1)) * dp[t] - gm[t] * y;
     uu[t] = up[t] + dn;
-    if (j < nsh && sl[t].x == sh0 + j) {  // the first touching patch stores the level
+    A.u_in_sh[N + r] = uu[t];  // every ref keeps its copy of the finished level
+    A.dsh_cur[r] = dn;
+    if (sl[t].x == r) {  // the first touching patch stores the level itself
       A.u_in_sh[g] = uu[t];
-      A.dsh_cur[s] = dn;
       if (ADJ) {
-        T r;
-        if (pair) {
-          r = A.partr_prev[sl[t].x] + A.partr_prev[sl[t].y];
-        } else {
-          r = T(0);
-          for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) r += A.partr_prev[A.shp_slot[k]];
+        T rr = q0[ADJ ? t : 0] + q1[ADJ ? t : 0];
+        if (!pair) {
+          rr = T(0);
+          for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) rr += A.partr_prev[A.shp_slot[k]];
         }
-        A.gacc[g] += (double)r;
+        A.gacc[g] += (double)rr;
       }
     }
   }
@@ -241,42 +260,37 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
   }
   // remaining shared refs (patches with more than KH * bs of them)
   for (int j = tid + KH * bs; j < nsh; j += bs) {
-    const int g = A.sh_idx[sh0 + j];
+    const int r = sh0 + j;
+    const int g = A.sh_idx[r];
     const int64_t s = g - A.n_own;
-    T u, c, f = T(0);
-    c = A.c2[g];
-    if (ADJ) f = A.uf[g];
-    if (A.prev) {
-      const int2 sj = reinterpret_cast<const int2*>(A.ref_slots)[sh0 + j];
-      T y;
-      if (sj.y >= 0) {
-        y = A.part_prev[sj.x] + A.part_prev[sj.y];
-      } else {
+    const int2 sj = reinterpret_cast<const int2*>(A.ref_slots)[r];
+    const bool pair = sj.y >= 0;
+    T u = step ? uref[r] : A.u_in[g];
+    if (step && A.prev) {
+      T y = A.part_prev[sj.x] + A.part_prev[pair ? sj.y : sj.x];
+      if (!pair) {
         y = T(0);
         for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) y += A.part_prev[A.shp_slot[k]];
       }
-      const T dn = (damped ? A.beta[g] : T(1)) * A.dsh_prev[s] - A.gamma[g] * y;
-      u = A.u_prev[g] + dn;
-      if (sj.x == sh0 + j) {
+      const T dn = (damped ? bref[r] : T(1)) * A.dsh_prev[r] - A.gamma_ref[r] * y;
+      u = u + dn;
+      A.u_in_sh[N + r] = u;
+      A.dsh_cur[r] = dn;
+      if (sj.x == r) {
         A.u_in_sh[g] = u;
-        A.dsh_cur[s] = dn;
         if (ADJ) {
-          T r;
-          if (sj.y >= 0) {
-            r = A.partr_prev[sj.x] + A.partr_prev[sj.y];
-          } else {
-            r = T(0);
-            for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) r += A.partr_prev[A.shp_slot[k]];
+          T rr = A.partr_prev[sj.x] + A.partr_prev[pair ? sj.y : sj.x];
+          if (!pair) {
+            rr = T(0);
+            for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) rr += A.partr_prev[A.shp_slot[k]];
           }
-          A.gacc[g] += (double)r;
+          A.gacc[g] += (double)rr;
         }
       }
-    } else {
-      u = A.u_in[g];
     }
     su[nbo + j] = u;
-    sc[nbo + j] = c;
-    if (ADJ) sf[nbo + j] = f;
+    sc[nbo + j] = A.c2_ref[r];
+    if (ADJ) sf[nbo + j] = A.uf[N + r];
   }
   {
     uint4* gldst = reinterpret_cast<uint4*>(gl);
@@ -419,6 +433,11 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
   }
   __syncthreads();
 
+  // partial sums of the shared DOFs, at this ref's slot
+  auto produce = [&](int j, T y, T r) {
+    A.part_cur[sh0 + j] = y;
+    if (ADJ) A.partr_cur[sh0 + j] = r;
+  };
   // ---- non-interior DOFs: fixed-order sums of their slots
 #pragma unroll
   for (int k = 0; k < KW; ++k) {
@@ -445,8 +464,7 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
         if (ADJ) A.gacc[gx] += (double)r;
       }
     } else {
-      A.part_cur[sh0 + l - nbo] = y;
-      if (ADJ) A.partr_cur[sh0 + l - nbo] = r;
+      produce(l - nbo, y, r);
     }
   }
   for (int l = tid + KW * bs; l < nbl; l += bs) {
@@ -464,8 +482,7 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
         if (ADJ) A.gacc[gx] += (double)r;
       }
     } else {
-      A.part_cur[sh0 + l - nbo] = y;
-      if (ADJ) A.partr_cur[sh0 + l - nbo] = r;
+      produce(l - nbo, y, r);
     }
   }
 }
@@ -476,21 +493,35 @@ __global__ void __launch_bounds__(256) k_finish(const FinishArgs<T> A) {
   if (s >= A.n_shared) return;
   const int64_t g = A.n_own + s;
   const int k0 = A.shp_ptr[s], k1 = A.shp_ptr[s + 1];
-  T y = T(0);
-  for (int k = k0; k < k1; ++k) y += A.part_prev[A.shp_slot[k]];
+  // the same fixed order as the step kernel (two patches: first + second)
+  T y = A.part_prev[A.shp_slot[k0]];
+  for (int k = k0 + 1; k < k1; ++k) y += A.part_prev[A.shp_slot[k]];
   if (A.mode == 1) {
     A.y_out[g] = y;
     return;
   }
+  const int64_t r0 = A.shp_slot[k0];
   const T b = A.beta ? A.beta[g] : T(1);
-  const T dn = b * A.dsh_prev[s] - A.gamma[g] * y;
-  A.u_cur[g] = A.u_prev[g] + dn;
-  A.dsh_cur[s] = dn;
-  if (ADJ) {
-    T r = T(0);
-    for (int k = k0; k < k1; ++k) r += A.partr_prev[A.shp_slot[k]];
-    A.gacc[g] += (double)r;
+  const T dn = b * A.dsh_prev[r0] - A.gamma[g] * y;
+  const T u = A.u_prev[A.n_dofs + r0] + dn;
+  A.u_cur[g] = u;
+  for (int k = k0; k < k1; ++k) {  // every ref's copies
+    const int64_t r = A.shp_slot[k];
+    A.u_cur[A.n_dofs + r] = u;
+    A.dsh_cur[r] = dn;
   }
+  if (ADJ) {
+    T rr = A.partr_prev[A.shp_slot[k0]];
+    for (int k = k0 + 1; k < k1; ++k) rr += A.partr_prev[A.shp_slot[k]];
+    A.gacc[g] += (double)rr;
+  }
+}
+
+template <typename T>
+__global__ void k_gather(const T* __restrict__ x, const int32_t* __restrict__ idx, T* __restrict__ out,
+                         int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = x[idx[i]];
 }
 
 // One thread per (point, node) pair, then a fixed-order sum per point: the
@@ -613,7 +644,8 @@ void launch_ev(K kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, hip
 template <typename T, int DIM, int ND, bool ADJ>
 hipError_t launch_step_t(const StepArgs<T>& a, int np, int block, hipStream_t s, hipEvent_t e0,
                          hipEvent_t e1) {
-  const size_t lds = StepLds(a.nbl_max, a.slot_stride, KmvTab<T, DIM, ND>::NB, a.glist_max, ADJ, sizeof(T)).total;
+  const size_t lds =
+      StepLds(a.nbl_max, a.slot_stride, KmvTab<T, DIM, ND>::NB, a.glist_max, ADJ, sizeof(T)).total;
   launch_ev(k_step<T, DIM, ND, ADJ>, dim3(np), dim3(block), (uint32_t)lds, s, e0, e1, a);
   return hipGetLastError();
 }
@@ -673,6 +705,13 @@ hipError_t launch_sample(const T* u, const int32_t* dof, const T* w, int npts, i
   const int per = 256 / nd;
   launch_ev(k_sample<T>, dim3(blocks_for(npts, per)), dim3(256), 0u, s, e0, e1, u, dof, w, npts, nd,
             out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gather(const T* x, const int32_t* idx, T* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_gather<T>), dim3(blocks_for(n, 256)), dim3(256), 0, s, x, idx, out, n);
   return hipGetLastError();
 }
 
@@ -738,6 +777,7 @@ hipError_t launch_normalize(T* v, const T* w, const double* dot_ww, int64_t n, h
   template hipError_t launch_sample<T>(const T*, const int32_t*, const T*, int, int, T*, hipStream_t,  \
                                       hipEvent_t, hipEvent_t);                                       \
   template hipError_t launch_square<T>(const double*, T*, int64_t, hipStream_t);                      \
+  template hipError_t launch_gather<T>(const T*, const int32_t*, T*, int64_t, hipStream_t);            \
   template hipError_t launch_fill<T>(T*, T, int64_t, hipStream_t);                                    \
   template hipError_t launch_misfit<T>(const T*, const T*, T*, int64_t, double*, int, double*,         \
                                        hipStream_t);                                                  \

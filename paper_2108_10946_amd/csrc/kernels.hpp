@@ -47,19 +47,24 @@ struct StepArgs {
   int nbl_max, slot_stride, glist_max;  // LDS sizing; cell-node slot = b*slot_stride + t
   int mode;                    // 0: leapfrog step, 1: y = K u
   int prev;                    // 1: shared DOFs of this level are finished here
-  // state (level n -> n+1; the adjoint runs the same recursion backwards)
-  const T* u_in;               // level n: owned entries (and shared ones if !prev)
+  // state (level n -> n+1; the adjoint runs the same recursion backwards).  A
+  // level vector holds the n_dofs DOF values, then one copy per shared ref of its
+  // DOF's value (index n_dofs + r), kept by the patch of ref r.
+  const T* u_in;               // level n (apply mode: a plain n_dofs vector)
   T* u_in_sh;                  // same buffer: finished shared entries are stored here
-  const T* u_prev;             // level n-1: shared entries
+  const T* u_prev;             // level n-1 (its shared-ref copies are read)
   T* u_out;                    // level n+1: owned entries
   T* du;                       // owned increments, updated in place
-  const T* dsh_prev;           // [n_shared] shared increments of level n-1
-  T* dsh_cur;                  // [n_shared] shared increments of level n
-  const T* part_prev;          // [n_shared_refs] partial K u of the previous step
-  T* part_cur;                 // [n_shared_refs] partial K u of this step
+  const T* dsh_prev;           // [n_shared_refs] increment of each ref's DOF, level n-1
+  T* dsh_cur;                  // [n_shared_refs] the same, level n
+  const T* part_prev;          // [n_shared_refs] partial K u of each ref, previous step
+  T* part_cur;                 // [n_shared_refs] partial K u of each ref, this step
   const T* c2;                 // c^2 at the DOFs
+  const T* c2_ref;             // [n_shared_refs] c^2 at each ref's DOF
   const T* gamma;              // dt^2 / (M (1+a)) (read for non-interior DOFs)
+  const T* gamma_ref;          // [n_shared_refs]
   const T* beta;               // (1-a)/(1+a), or nullptr (no damping)
+  const T* beta_ref;           // [n_shared_refs], or nullptr
   const int32_t* damp_patch;   // [np] 1 if a DOF of the patch is damped (beta read only there)
   T* y_out;                    // mode 1
   // point sources: entries (cell, point, phi_a(x_point) per node) per patch
@@ -77,7 +82,7 @@ struct StepArgs {
   const T* rec_w;
   T* trace_row;                // d^n row, or nullptr
   // adjoint + gradient
-  const T* uf;                 // forward state u^m
+  const T* uf;                 // forward state u^m (a level vector)
   const T* partr_prev;         // pairing partials of the previous step
   T* partr_cur;
   double* gacc;                // [n_dofs] float64 gradient accumulator
@@ -87,14 +92,14 @@ struct StepArgs {
 // sweep, checkpoints, segment ends), or y = K u for them (mode 1).
 template <typename T>
 struct FinishArgs {
-  int64_t n_own, n_shared;
+  int64_t n_own, n_shared, n_dofs;
   const int32_t* shp_ptr;
   const int32_t* shp_slot;
   int mode;
   const T* part_prev;
-  const T* u_prev;
+  const T* u_prev;             // level vectors (shared-ref copies after n_dofs)
   T* u_cur;
-  const T* dsh_prev;
+  const T* dsh_prev;           // per shared ref
   T* dsh_cur;
   const T* gamma;
   const T* beta;
@@ -103,8 +108,8 @@ struct FinishArgs {
   double* gacc;
 };
 
-template <typename T>
 // e0/e1: optional events recorded by the dispatch itself at kernel start and end.
+template <typename T>
 hipError_t launch_step(int dim, int nd, bool adjoint, const StepArgs<T>& a, int n_patches, int block,
                        hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Dynamic LDS bytes of one k_step workgroup.
@@ -126,6 +131,9 @@ hipError_t launch_misfit(const T* d, const T* obs, T* resid, int64_t n, double* 
                          int nblocks, double* J_out, hipStream_t s);
 hipError_t launch_finalize_grad(const double* c, const double* gacc, double scale, double* g,
                                 int64_t n, hipStream_t s);
+// out[r] = x[idx[r]], r < n (per-ref copies of a DOF vector)
+template <typename T>
+hipError_t launch_gather(const T* x, const int32_t* idx, T* out, int64_t n, hipStream_t s);
 // power iteration helpers
 template <typename T>
 hipError_t launch_scale(const T* x, const T* s, T* y, int64_t n, hipStream_t st);

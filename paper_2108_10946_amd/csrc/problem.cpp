@@ -127,6 +127,21 @@ Status upload_coefficients(Problem* p) {
   }
   STTRY(upload_real(&p->d_gamma, gamma, p->prec));
   {
+    std::vector<double> gr(std::max<int64_t>(1, m.n_shared_refs), 0.0), br;
+    for (int64_t r = 0; r < m.n_shared_refs; ++r) gr[r] = gamma[m.sh_idx[r]];
+    STTRY(upload_real(&p->d_gamma_ref, gr, p->prec));
+    if (!beta.empty()) {
+      br.assign(gr.size(), 0.0);
+      for (int64_t r = 0; r < m.n_shared_refs; ++r) br[r] = beta[m.sh_idx[r]];
+    }
+    if (br.empty()) {
+      dfree(p->d_beta_ref);
+      p->d_beta_ref = nullptr;
+    } else {
+      STTRY(upload_real(&p->d_beta_ref, br, p->prec));
+    }
+  }
+  {
     std::vector<double> gd(m.n_cells);
     for (int64_t e = 0; e < m.n_cells; ++e) gd[e] = dt2 / m.absdet[e];
     STTRY(upload_real(&p->d_gdet, gd, p->prec));
@@ -266,8 +281,11 @@ StepArgs<T> base_args(const Problem* p) {
   a.slot_stride = m.slot_stride;
   a.glist_max = m.max_glist;
   a.c2 = (const T*)p->d_c2;
+  a.c2_ref = (const T*)p->d_c2_ref;
   a.gamma = (const T*)p->d_gamma;
+  a.gamma_ref = (const T*)p->d_gamma_ref;
   a.beta = (const T*)p->d_beta;
+  a.beta_ref = (const T*)p->d_beta_ref;
   a.damp_patch = p->d_damp_patch;
   a.amp_scale = T(1);
   return a;
@@ -331,6 +349,7 @@ Status finish(Problem* p, Sweep& S, bool grad, const T* u_prev, T* u_cur, Par q,
   FinishArgs<T> f{};
   f.n_own = m.n_own_total;
   f.n_shared = m.n_shared;
+  f.n_dofs = m.n_dofs;
   f.shp_ptr = p->d_shp_ptr;
   f.shp_slot = p->d_shp_slot;
   f.mode = 0;
@@ -355,12 +374,12 @@ Par adj_par(int64_t m) { return Par{(int)(m & 1), (int)((m + 1) & 1), (int)((m +
 
 template <typename T>
 T* slot_ptr(Problem* p, int64_t k) {
-  return (T*)p->d_slots + k * p->mesh->n_dofs;
+  return (T*)p->d_slots + k * p->ls;
 }
 
 Status ensure_slots(Problem* p, int64_t n) {
   if (p->n_slots >= n) return OK;
-  STTRY(alloc(&p->d_slots, (size_t)n * p->mesh->n_dofs * p->ts));
+  STTRY(alloc(&p->d_slots, (size_t)n * p->ls * p->ts));
   p->n_slots = n;
   return OK;
 }
@@ -368,9 +387,9 @@ Status ensure_slots(Problem* p, int64_t n) {
 template <typename T>
 Status zero_level(Problem* p, Sweep& S, T* u, int lvl_par, hipStream_t s) {
   const Mesh& m = *p->mesh;
-  HIPTRY(launch_fill<T>(u, T(0), m.n_dofs, s));
+  HIPTRY(launch_fill<T>(u, T(0), p->ls, s));
   HIPTRY(launch_fill<T>((T*)S.d, T(0), m.n_dofs, s));
-  HIPTRY(launch_fill<T>((T*)S.dsh[lvl_par], T(0), m.n_shared, s));
+  HIPTRY(launch_fill<T>((T*)S.dsh[lvl_par], T(0), std::max<int64_t>(1, p->nref), s));
   return OK;
 }
 
@@ -381,16 +400,16 @@ template <typename T, typename F>
 Status run_forward(Problem* p, int64_t n0, int64_t n1, F slot_of, T* traces, bool save_ck, hipStream_t s) {
   const Mesh& m = *p->mesh;
   Sweep& S = p->fwd;
-  const size_t vb = (size_t)m.n_dofs * sizeof(T);
-  const size_t ob = (size_t)m.n_own_total * sizeof(T), shb = (size_t)m.n_shared * sizeof(T);
+  const size_t lb = (size_t)p->ls * sizeof(T);
+  const size_t ob = (size_t)m.n_own_total * sizeof(T), shb = (size_t)p->nref * sizeof(T);
   bool fresh = true;
   for (int64_t n = n0; n < n1; ++n) {
     if (save_ck && n % p->seg == 0) {
       if (!fresh) STTRY(finish<T>(p, S, false, slot_of(n - 1), slot_of(n), fwd_par(n), s));
       const int64_t k = n / p->seg;
-      T* cu = (T*)p->d_ck_u + k * m.n_dofs;
-      T* cd = (T*)p->d_ck_du + k * m.n_dofs;
-      HIPTRY(hipMemcpyAsync(cu, slot_of(n), vb, hipMemcpyDeviceToDevice, s));
+      T* cu = (T*)p->d_ck_u + k * p->ls;
+      T* cd = (T*)p->d_ck_du + k * (m.n_own_total + p->nref);
+      HIPTRY(hipMemcpyAsync(cu, slot_of(n), lb, hipMemcpyDeviceToDevice, s));
       HIPTRY(hipMemcpyAsync(cd, S.d, ob, hipMemcpyDeviceToDevice, s));
       if (shb) HIPTRY(hipMemcpyAsync(cd + m.n_own_total, S.dsh[n & 1], shb, hipMemcpyDeviceToDevice, s));
       fresh = true;
@@ -411,18 +430,26 @@ Status run_forward(Problem* p, int64_t n0, int64_t n1, F slot_of, T* traces, boo
   return OK;
 }
 
+// c^2 at the DOFs and its copies per shared ref.
+template <typename T>
+Status set_c2(Problem* p, const double* c, hipStream_t s) {
+  const Mesh& m = *p->mesh;
+  HIPTRY(launch_square<T>(c, (T*)p->d_c2, m.n_dofs, s));
+  HIPTRY(launch_gather<T>((const T*)p->d_c2, p->d_sh_idx, (T*)p->d_c2_ref, p->nref, s));
+  return OK;
+}
+
 template <typename T>
 Status forward_t(Problem* p, const double* c, T* traces, hipStream_t s) {
-  const Mesh& m = *p->mesh;
   STTRY(ensure_slots(p, 2));
-  HIPTRY(launch_square<T>(c, (T*)p->d_c2, m.n_dofs, s));
+  STTRY(set_c2<T>(p, c, s));
   STTRY(zero_level<T>(p, p->fwd, slot_ptr<T>(p, 0), 0, s));
   return run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n & 1); }, traces, false, s);
 }
 
 Status plan_storage(Problem* p) {
   const Mesh& m = *p->mesh;
-  const size_t vb = (size_t)m.n_dofs * p->ts;
+  const size_t vb = (size_t)p->ls * p->ts;
   const size_t all = (size_t)(p->nt + 1) * vb;
   if (p->ckpt_every <= 0 && all <= p->budget) {
     p->store_all = true;
@@ -440,7 +467,7 @@ Status plan_storage(Problem* p) {
     return Status{KMV_ENOMEM, "checkpoint storage (" + std::to_string(need) + " B) exceeds mem_budget"};
   if (p->seg != seg || p->n_ck != nck || !p->d_ck_u) {
     STTRY(alloc(&p->d_ck_u, (size_t)nck * vb));
-    STTRY(alloc(&p->d_ck_du, (size_t)nck * vb));
+    STTRY(alloc(&p->d_ck_du, (size_t)nck * (m.n_own_total + p->nref) * p->ts));
   }
   p->seg = seg;
   p->n_ck = nck;
@@ -459,9 +486,8 @@ Status adjoint_launch(Problem* p, int64_t m, bool grad, const T* adj_rows, const
 
 template <typename T>
 Status adjoint_start(Problem* p, hipStream_t s) {
-  const Mesh& m = *p->mesh;
   STTRY(zero_level<T>(p, p->adj, (T*)p->d_lam[(p->nt + 1) & 1], (int)((p->nt + 1) & 1), s));
-  HIPTRY(launch_fill<T>((T*)p->d_lam[p->nt & 1], T(0), m.n_dofs, s));
+  HIPTRY(launch_fill<T>((T*)p->d_lam[p->nt & 1], T(0), p->ls, s));
   return OK;
 }
 
@@ -478,7 +504,7 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
   const int64_t N = m.n_dofs;
   STTRY(plan_storage(p));
   T* traces = traces_out ? traces_out : (T*)p->d_traces_tmp;
-  HIPTRY(launch_square<T>(c, (T*)p->d_c2, N, s));
+  STTRY(set_c2<T>(p, c, s));
   STTRY(zero_level<T>(p, p->fwd, slot_ptr<T>(p, 0), 0, s));
   if (p->store_all) {
     STTRY(run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n); }, traces, false, s));
@@ -493,12 +519,12 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
   if (p->store_all) {
     for (int64_t mm = p->nt; mm >= 1; --mm) STTRY(adjoint_launch<T>(p, mm, true, resid, slot_ptr<T>(p, mm), s));
   } else {
-    const size_t vb = (size_t)N * sizeof(T);
-    const size_t ob = (size_t)m.n_own_total * sizeof(T), shb = (size_t)m.n_shared * sizeof(T);
+    const size_t lb = (size_t)p->ls * sizeof(T);
+    const size_t ob = (size_t)m.n_own_total * sizeof(T), shb = (size_t)p->nref * sizeof(T);
     for (int64_t k = p->n_ck - 1; k >= 0; --k) {
       const int64_t s0 = k * p->seg, s1 = std::min(s0 + p->seg, p->nt);
-      const T* cd = (const T*)p->d_ck_du + k * N;
-      HIPTRY(hipMemcpyAsync(slot_ptr<T>(p, 0), (T*)p->d_ck_u + k * N, vb, hipMemcpyDeviceToDevice, s));
+      const T* cd = (const T*)p->d_ck_du + k * (m.n_own_total + p->nref);
+      HIPTRY(hipMemcpyAsync(slot_ptr<T>(p, 0), (T*)p->d_ck_u + k * p->ls, lb, hipMemcpyDeviceToDevice, s));
       HIPTRY(hipMemcpyAsync(p->fwd.d, cd, ob, hipMemcpyDeviceToDevice, s));
       if (shb) HIPTRY(hipMemcpyAsync(p->fwd.dsh[s0 & 1], cd + m.n_own_total, shb, hipMemcpyDeviceToDevice, s));
       STTRY(run_forward<T>(p, s0, s1, [p, s0](int64_t n) { return slot_ptr<T>(p, n - s0); }, (T*)nullptr,
@@ -522,7 +548,7 @@ Status adjoint_t(Problem* p, const double* c, const T* adj, T* lambda_out, T* sr
   const Mesh& m = *p->mesh;
   const int64_t N = m.n_dofs;
   const size_t vb = (size_t)N * sizeof(T);
-  HIPTRY(launch_square<T>(c, (T*)p->d_c2, N, s));
+  STTRY(set_c2<T>(p, c, s));
   STTRY(adjoint_start<T>(p, s));
   if (lambda_out) HIPTRY(launch_fill<T>(lambda_out + p->nt * N, T(0), N, s));
   auto record = [&](int64_t lvl) -> Status {  // level lvl is complete: row lvl-1
@@ -546,7 +572,7 @@ Status adjoint_t(Problem* p, const double* c, const T* adj, T* lambda_out, T* sr
 template <typename T>
 Status apply_t(Problem* p, const double* c, const T* u, T* y, hipStream_t s) {
   const Mesh& m = *p->mesh;
-  if (c) HIPTRY(launch_square<T>(c, (T*)p->d_c2, m.n_dofs, s));
+  if (c) STTRY(set_c2<T>(p, c, s));
   StepArgs<T> a = base_args<T>(p);
   a.mode = 1;
   a.prev = 0;
@@ -554,7 +580,7 @@ Status apply_t(Problem* p, const double* c, const T* u, T* y, hipStream_t s) {
   a.y_out = y;
   // loaded (not used) by the branch-free prologue: any valid buffers
   a.du = y;
-  a.u_prev = u;
+  a.u_prev = (const T*)p->d_lam[0];  // any level vector: the apply input has no ref copies
   a.dsh_prev = (const T*)p->fwd.dsh[0];
   a.part_prev = (const T*)p->fwd.part[1];
   a.part_cur = (T*)p->fwd.part[0];
@@ -564,6 +590,7 @@ Status apply_t(Problem* p, const double* c, const T* u, T* y, hipStream_t s) {
   FinishArgs<T> f{};
   f.n_own = m.n_own_total;
   f.n_shared = m.n_shared;
+  f.n_dofs = m.n_dofs;
   f.shp_ptr = p->d_shp_ptr;
   f.shp_slot = p->d_shp_slot;
   f.mode = 1;
@@ -614,7 +641,7 @@ Status spectral_t(Problem* p, const double* c, int iters, uint64_t seed, double*
     cleanup();
     return st;
   }
-  HIPTRY(launch_square<T>(c, (T*)p->d_c2, N, s));
+  STTRY(set_c2<T>(p, c, s));
   const T* ms = (const T*)p->d_minv_sqrt;
   double* dots = p->d_red + p->red_blocks + 1;  // [2]
   for (int it = 0; it < iters; ++it) {
@@ -639,13 +666,12 @@ void free_sweep(Sweep& S) {
 }
 
 Status alloc_sweep(Sweep& S, const Mesh& m, size_t ts, bool with_r) {
-  const size_t pb = std::max<size_t>(1, m.n_shared_refs) * ts;
-  const size_t shb = std::max<int64_t>(1, m.n_shared) * ts;
+  const size_t rb = std::max<size_t>(1, m.n_shared_refs) * ts;
   STTRY(alloc(&S.d, (size_t)m.n_dofs * ts));
   for (int i = 0; i < 2; ++i) {
-    STTRY(alloc(&S.dsh[i], shb));
-    STTRY(alloc(&S.part[i], pb));
-    if (with_r) STTRY(alloc(&S.partr[i], pb));
+    STTRY(alloc(&S.dsh[i], rb));
+    STTRY(alloc(&S.part[i], rb));
+    if (with_r) STTRY(alloc(&S.partr[i], rb));
   }
   return OK;
 }
@@ -655,7 +681,7 @@ Status alloc_sweep(Sweep& S, const Mesh& m, size_t ts, bool with_r) {
 Problem::~Problem() {
   for (void* q : {(void*)d_lmap, d_geom, (void*)d_cell_start, (void*)d_own_start, (void*)d_sh_start,
                   (void*)d_sh_idx, (void*)d_shp_ptr, (void*)d_shp_slot, (void*)d_ref_slots, (void*)d_gword,
-                  (void*)d_glist, (void*)d_gword_off, (void*)d_glist_off, (void*)d_damp_patch, d_gamma, d_gdet, d_beta, d_c2, d_minv_sqrt, d_lam[0], d_lam[1], (void*)d_gacc, (void*)d_red, d_slots,
+                  (void*)d_glist, (void*)d_gword_off, (void*)d_glist_off, (void*)d_damp_patch, d_gamma, d_gdet, d_beta, d_c2, d_c2_ref, d_gamma_ref, d_beta_ref, d_minv_sqrt, d_lam[0], d_lam[1], (void*)d_gacc, (void*)d_red, d_slots,
                   d_ck_u, d_ck_du, d_resid, d_traces_tmp, d_wavelet})
     dfree(q);
   free_sweep(fwd);
@@ -710,6 +736,8 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
   p->budget = budget ? budget : ((size_t)8 << 30);
   HIPTRY(hipGetDevice(&p->device));
   p->block = std::max(64, ((m->max_patch_cells + 63) / 64) * 64);
+  p->nref = m->n_shared_refs;
+  p->ls = m->n_dofs + p->nref;
   for (bool adjv : {false, true}) {
     const size_t bytes = step_lds_bytes(m->max_nbl, m->slot_stride, m->nb, m->max_glist, adjv, p->ts);
     if (bytes > 160 * 1024) return Status{KMV_EINVAL, "patch LDS footprint above 160 KiB; use smaller patches"};
@@ -768,10 +796,11 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
   }
   const size_t vb = (size_t)m->n_dofs * p->ts;
   STTRY(alloc(&p->d_c2, vb));
+  STTRY(alloc(&p->d_c2_ref, std::max<size_t>(1, m->n_shared_refs) * p->ts));
   STTRY(alloc_sweep(p->fwd, *m, p->ts, false));
   STTRY(alloc_sweep(p->adj, *m, p->ts, true));
-  STTRY(alloc(&p->d_lam[0], vb));
-  STTRY(alloc(&p->d_lam[1], vb));
+  STTRY(alloc(&p->d_lam[0], (size_t)p->ls * p->ts));
+  STTRY(alloc(&p->d_lam[1], (size_t)p->ls * p->ts));
   STTRY(alloc((void**)&p->d_gacc, (size_t)m->n_dofs * 8));
   STTRY(alloc((void**)&p->d_red, (size_t)(p->red_blocks + 8) * 8));
   *out = guard.release();

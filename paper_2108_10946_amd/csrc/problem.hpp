@@ -53,13 +53,13 @@ struct Probe {
   std::vector<hipEvent_t> pool;
 };
 
-// Lagged state of one sweep: owned increments, the shared increments of the two
-// most recent levels and the partial sums of the two most recent steps.
+// Lagged state of one sweep: owned increments, the shared-ref increments of the
+// two most recent levels and the partial sums of the two most recent steps.
 struct Sweep {
-  void* d = nullptr;           // [n_dofs] owned increments
-  void* dsh[2] = {nullptr, nullptr};   // [n_shared] by level parity
-  void* part[2] = {nullptr, nullptr};  // [n_shared_refs] by step parity
-  void* partr[2] = {nullptr, nullptr}; // adjoint pairing partials
+  void* d = nullptr;                    // [n_dofs] owned increments
+  void* dsh[2] = {nullptr, nullptr};    // [n_shared_refs] by level parity
+  void* part[2] = {nullptr, nullptr};   // [n_shared_refs] by step parity
+  void* partr[2] = {nullptr, nullptr};  // adjoint pairing partials
 };
 
 struct Problem {
@@ -81,6 +81,8 @@ struct Problem {
           *d_glist_off = nullptr;
   uint32_t* d_gword = nullptr;
   uint16_t* d_glist = nullptr;
+  int64_t nref = 0;             // shared refs
+  int64_t ls = 0;               // level vector length: n_dofs + nref (copies per ref)
   // coefficients
   std::vector<double> eta;      // host damping (empty = none)
   void* d_gamma = nullptr;
@@ -88,6 +90,7 @@ struct Problem {
   void* d_beta = nullptr;
   int32_t* d_damp_patch = nullptr;  // [np] patch touches a damped DOF
   void* d_c2 = nullptr;
+  void *d_c2_ref = nullptr, *d_gamma_ref = nullptr, *d_beta_ref = nullptr;  // [nref]
   void* d_minv_sqrt = nullptr;  // for the power iteration
   // sweeps
   Sweep fwd, adj;

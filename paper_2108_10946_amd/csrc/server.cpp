@@ -142,11 +142,12 @@ size_t job_device_bytes(const Mesh& m, int prec, int64_t nt, int nrec, size_t bu
   b += (size_t)((m.nb + 1) / 2) * ne * 4 + (size_t)(m.ng + 1) * ne * ts + 4 * (np + 1) * 4;
   b += (size_t)(m.n_shared_refs + 1) * 12 + (size_t)(m.n_shared + 1) * 4 + m.gword.size() * 4 +
        (m.glist.size() + 8) * 2 + (np + 1) * 8;
-  // coefficient vectors, sweeps, adjoint levels, gradient accumulator
-  const size_t sh = std::max<size_t>(1, (size_t)m.n_shared), refs = std::max<size_t>(1, (size_t)m.n_shared_refs);
-  b += 4 * N * ts + 2 * (N + 2 * sh + 2 * refs) * ts + 2 * refs * ts + 2 * N * ts + N * 8 + 4096;
-  // state storage (the plan the problem will take under `budget`)
-  const size_t vb = N * ts;
+  // coefficient vectors (and per-ref copies), sweeps, adjoint levels, gradient accumulator
+  const size_t refs = std::max<size_t>(1, (size_t)m.n_shared_refs);
+  b += 4 * N * ts + 3 * refs * ts + 2 * (N + 6 * refs) * ts + 6 * refs * ts + 2 * (N + refs) * ts + N * 8 + 4096;
+  // state storage (the plan the problem will take under `budget`): level vectors
+  // hold a copy per shared ref after the DOFs
+  const size_t vb = (N + refs) * ts;
   if ((size_t)(nt + 1) * vb <= budget) {
     b += (size_t)(nt + 1) * vb;
   } else {
