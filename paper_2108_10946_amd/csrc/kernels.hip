@@ -45,11 +45,12 @@ struct StepLds {
   }
 };
 
-// Items per thread whose global loads are issued together (latency hiding); the
-// adjoint holds fewer owned DOFs to stay within 168 VGPRs (three waves per SIMD).
-template <typename T, bool ADJ = false>
+// Items per thread whose global loads are issued together (latency hiding).
+template <typename T, bool ADJ = false, int ND = 18>
 struct Batch {
-  static constexpr int kOwned = sizeof(T) == 4 ? 5 : 2;  // owned non-interior DOFs in registers
+  // owned non-interior DOFs in registers (fewer for the largest elements, whose
+  // element vectors already fill the register file)
+  static constexpr int kOwned = sizeof(T) == 4 ? (ND >= 30 ? 2 : 5) : 2;
   static constexpr int kWords = sizeof(T) == 4 ? 6 : 4;   // gather words in registers
   static constexpr int kShared = 2;                       // shared refs in the first batch
   static constexpr int kList = 1;                         // 16-byte gather-list words
@@ -167,7 +168,7 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
 #pragma unroll
   for (int k = 0; k < KW; ++k) gw[k] = gwp[min(tid + k * bs, nbl - 1)];
   // owned non-interior DOFs: level, c^2 [, u^m] and the update operands
-  constexpr int KO = Batch<T, ADJ>::kOwned;
+  constexpr int KO = Batch<T, ADJ, ND>::kOwned;
   T vu[KO], vc[KO], vf[ADJ ? KO : 1], pdu[KO], pg[KO], pb[KO];
 #pragma unroll
   for (int k = 0; k < KO; ++k) {

@@ -222,12 +222,12 @@ Mesh* build_mesh(int dim, int degree, const double* coords, int64_t nv, const in
   if (patch_cells <= 0) {
     // LDS holds the patch's non-interior DOFs (three float values each in the
     // adjoint, plus shared refs) and its cells' non-interior slots (two each): aim
-    // at about 4096 such DOFs and 48 KiB of float LDS, at most 256 cells (4 waves)
+    // at about 4096 such DOFs and 64 KiB of float LDS, at most 256 cells (4 waves)
     const double nonint_per_cell = dim == 2 ? 0.5 + 1.5 * el.n_edge
                                             : 1.0 / 6.0 + 7.0 / 6.0 * el.n_edge + 2.0 * el.n_face;
     const int nb_cell = el.n - el.n_cell;
     const double lds_per_cell = 4.0 * (3.0 * 1.2 * nonint_per_cell + 2.0 * nb_cell);
-    int P = (int)std::min(4096.0 / (std::max(nonint_per_cell, 1.0) * 1.25), 49152.0 / lds_per_cell);
+    int P = (int)std::min(4096.0 / (std::max(nonint_per_cell, 1.0) * 1.25), 65536.0 / lds_per_cell);
     P = (P / 64) * 64;
     patch_cells = std::max(64, std::min(256, P));
   }
