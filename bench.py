@@ -57,6 +57,25 @@ def algorithmic_bytes(variant, n_dofs, n_cells, dim, ts):
     raise ValueError(variant)
 
 
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X, packed FP32
+FP32_NONPACKED_TFLOPS = 78.6      # 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (no packed FP32 here)
+
+
+def algorithmic_flops(variant, n_cells, dim, degree):
+    """Flops per launch of the element work: the two reference-gradient
+    contractions over the nonzero table entries (2 flops per multiply-add), the
+    geometry product at each node, and in the adjoint the forward-state gradient
+    and the pairing."""
+    from paper_2108_10946_amd import kmv_element_tables
+    nodes, w, g = kmv_element_tables(dim, degree)
+    nnz = int(np.count_nonzero(np.abs(g) > 1e-14 * np.abs(g).max()))
+    nd = len(w)
+    per_cell = 2 * 2 * nnz + nd * 2 * (dim * dim + dim)
+    if variant == "patch_adjoint":
+        per_cell += 2 * nnz + nd * 2 * dim
+    return per_cell * n_cells
+
+
 def traffic_from_profiles(variant, hash_):
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -71,11 +90,15 @@ def traffic_from_profiles(variant, hash_):
     return rec.get("bytes_per_launch")
 
 
-def setup_workload(precision, budget_frac=0.75, window=0, mesh_cache={}):
+WORKLOADS = ("layered_kmv4", "layered_tet_kmv3")
+
+
+def setup_workload(precision, budget_frac=0.75, window=0, workload="layered_kmv4", checkpoint_every=0,
+                   mesh_cache={}):
     import torch
     from paper_2108_10946_amd import Mesh, Problem
     from synth import configs
-    w = configs.layered_kmv4()
+    w = getattr(configs, workload)()
     if "mesh" not in mesh_cache:
         t = time.time()
         mesh_cache["mesh"] = Mesh(w.coords, w.cells, w.degree)
@@ -83,9 +106,9 @@ def setup_workload(precision, budget_frac=0.75, window=0, mesh_cache={}):
             f"{mesh_cache['mesh'].n_patches} patches ({time.time() - t:.1f}s)")
     m = mesh_cache["mesh"]
     x = m.dof_coords()
-    c_cur = torch.tensor(w.vp(x[:, 0], x[:, 1]), dtype=torch.float64, device="cuda")
-    c_obs = torch.tensor(w.vp_obs(x[:, 0], x[:, 1]), dtype=torch.float64, device="cuda")
-    eta = w.eta(x[:, 0], x[:, 1])
+    c_cur = torch.tensor(w.vp(*x.T), dtype=torch.float64, device="cuda")
+    c_obs = torch.tensor(w.vp_obs(*x.T), dtype=torch.float64, device="cuda")
+    eta = w.eta(*x.T)
     free, _ = torch.cuda.mem_get_info()
     budget = int(free * budget_frac)
     if "dt" not in mesh_cache:
@@ -98,7 +121,7 @@ def setup_workload(precision, budget_frac=0.75, window=0, mesh_cache={}):
     dt, nt = mesh_cache["dt"]
     if window:
         nt = window
-    prob = Problem(m, dt, nt, precision=precision, mem_budget=budget)
+    prob = Problem(m, dt, nt, precision=precision, mem_budget=budget, checkpoint_every=checkpoint_every)
     prob.set_damping(eta)
     prob.set_sources(w.sources, f0=w.f0, t0=w.t0, amp=w.amp)
     prob.set_receivers(w.receivers)
@@ -107,10 +130,11 @@ def setup_workload(precision, budget_frac=0.75, window=0, mesh_cache={}):
     return w, m, prob, c_cur, obs, dt, nt
 
 
-def time_gpu(precision, steps, warmup, every, window=0):
+def time_gpu(precision, steps, warmup, every, window=0, workload="layered_kmv4", checkpoint_every=0):
     import torch
     from paper_2108_10946_amd import kmvwave as K
-    w, m, prob, c, obs, dt, nt = setup_workload(precision, window=window)
+    w, m, prob, c, obs, dt, nt = setup_workload(precision, window=window, workload=workload,
+                                                checkpoint_every=checkpoint_every)
     K.kmv_profile_enable(prob.handle, every)
     for i in range(warmup):
         t = time.time()
@@ -328,6 +352,47 @@ def serving_bench(n_requests=48, t_scale=0.1, slots=6, load=0.7, seed=11):
     }
 
 
+def bench_3d(args):
+    """The 3D workload: layered model with anomalies on 1.33 M graded tetrahedra,
+    KMV3tet (16.9 M DOFs), T = 2 s, FP32 fields, float64 misfit and gradient,
+    reverse sweep from checkpoints (segments of sqrt(2 N_t) steps).  The element
+    work dominates here, so the roofline is the FP32 vector ALU."""
+    res = time_gpu("fp32", args.steps, args.warmup, args.profile_every, args.window,
+                   workload="layered_tet_kmv3", checkpoint_every=-1)
+    N, nt = res["n_dofs"], res["nt"]
+    value = N * nt / res["sec"]
+    roof = {}
+    for variant in ("patch_forward", "patch_adjoint"):
+        p = res["prof"][variant]
+        if not p["timed"]:
+            continue
+        fl = algorithmic_flops(variant, res["n_cells"], 3, 3)
+        ach = fl / (p["mean_ms"] * 1e-3) / 1e12
+        roof[variant] = {"kernel": f"k_step ({variant.split('_')[1]})", "bound": "alu",
+                         "achieved": round(ach, 2), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4),
+                         "frac_of_nonpacked_peak": round(ach / FP32_NONPACKED_TFLOPS, 4),
+                         "traffic": None, "algorithmic_flops": int(fl),
+                         "mean_launch_us": round(p["mean_ms"] * 1e3, 3)}
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "DOF-timesteps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res["sec"] * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "layered_tet_kmv3: 3D 4x4x2 km, 8 layers 1.5-4.5 km/s + 3 seeded anomalies, "
+                               "500 m sponge on five faces, graded Kuhn/Maubach tetrahedra, KMV3tet, 1 Ricker "
+                               "shot (5 Hz), 40x40 receivers, T=2 s at 0.9x the power-iteration CFL step, "
+                               "checkpointed reverse sweep",
+                   "n_cells": res["n_cells"], "n_dofs": N, "n_steps": nt, "dt_s": res["dt"],
+                   "checkpoint_every": res["checkpoint_every"], "n_patches": res["n_patches"]},
+        "roofline": roof.get("patch_adjoint"),
+        "rooflines": roof,
+        "kernel_mean_us": {k: round(v["mean_ms"] * 1e3, 3) for k, v in res["prof"].items()},
+        "note": "the 3D workload; the bench line is the default (layered_kmv4) run",
+    }
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration(n_bytes=1 << 30, reps=3):
     """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE
     counters of a profiled run to bytes."""
@@ -352,6 +417,9 @@ def main():
     ap.add_argument("--window", type=int, default=0,
                     help="run only the first WINDOW time steps (hardware-counter runs: the "
                          "per-launch traffic does not depend on the window); not a bench line")
+    ap.add_argument("--workload", choices=WORKLOADS, default="layered_kmv4",
+                    help="layered_tet_kmv3: the 3D workload (FP32, checkpointed reverse sweep, "
+                         "ALU roofline); not the bench line")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=48)
     ap.add_argument("--serving-scale", type=float, default=0.1,
@@ -370,6 +438,9 @@ def main():
         sys.exit(1)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "layered_tet_kmv3":
+        bench_3d(args)
         return
     import paper_2108_10946_amd as kmv
     kmv.lib()

@@ -119,7 +119,9 @@ typedef struct {
   double dt;                /* time step (s) */
   int64_t n_steps;          /* N_t: steps n = 0..N_t-1 produce u^1..u^N_t */
   int64_t checkpoint_every; /* reverse sweep: 0 = store every state if it fits
-                               mem_budget, else segments of this many steps */
+                               mem_budget (else as < 0); > 0 = checkpoints every
+                               this many steps; < 0 = checkpoints every
+                               ceil(sqrt(2 N_t)) steps */
   size_t mem_budget;        /* bytes of device memory for stored states (0 = 8 GiB) */
 } kmv_options;
 

@@ -13,7 +13,7 @@ def _torch():
 
 class Mesh:
     """A simplicial mesh discretised with KMV elements of one degree (host-side
-    preprocessing: DOF numbering, patches, colouring, geometry, lumped mass)."""
+    preprocessing: DOF numbering, patches, gather words, geometry, lumped mass)."""
 
     def __init__(self, coords, cells, degree, patch_cells=0):
         coords = np.asarray(coords, dtype=np.float64)

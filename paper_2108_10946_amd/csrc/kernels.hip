@@ -46,13 +46,14 @@ struct StepLds {
 };
 
 // Items per thread whose global loads are issued together (latency hiding).
-template <typename T, bool ADJ = false, int ND = 18>
+template <typename T, bool ADJ = false, int ND = 18, int DIM = 2>
 struct Batch {
   // owned non-interior DOFs in registers (fewer for the largest elements, whose
   // element vectors already fill the register file)
   static constexpr int kOwned = sizeof(T) == 4 ? (ND >= 30 ? 2 : 5) : 2;
   static constexpr int kWords = sizeof(T) == 4 ? 6 : 4;   // gather words in registers
-  static constexpr int kShared = 2;                       // shared refs in the first batch
+  // shared refs in the first batch (3D patches have several times more)
+  static constexpr int kShared = DIM == 3 && !ADJ ? 4 : 2;
   static constexpr int kList = 1;                         // 16-byte gather-list words
 };
 
@@ -104,7 +105,7 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
   // needs to finish its DOF is stored at the ref's own index (the level's copy, the
   // increment, c^2, gamma, beta), except the other patches' partial sums, whose
   // slots are loaded here and which are read after the bulk loads.
-  constexpr int KH = Batch<T>::kShared;
+  constexpr int KH = Batch<T, ADJ, ND, DIM>::kShared;
   const int64_t N = A.n_dofs;
   const bool damped = A.beta != nullptr && A.damp_patch[p] != 0;
   const T* bsrc = damped ? A.beta : A.c2;          // undamped: a valid array already being read
@@ -259,39 +260,70 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
     sc[nbo + j] = cc[t];
     if (ADJ) sf[nbo + j] = ff[t];
   }
-  // remaining shared refs (patches with more than KH * bs of them)
-  for (int j = tid + KH * bs; j < nsh; j += bs) {
-    const int r = sh0 + j;
-    const int g = A.sh_idx[r];
-    const int64_t s = g - A.n_own;
-    const int2 sj = reinterpret_cast<const int2*>(A.ref_slots)[r];
-    const bool pair = sj.y >= 0;
-    T u = step ? uref[r] : A.u_in[g];
-    if (step && A.prev) {
-      T y = A.part_prev[sj.x] + A.part_prev[pair ? sj.y : sj.x];
-      if (!pair) {
-        y = T(0);
-        for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) y += A.part_prev[A.shp_slot[k]];
+  // remaining shared refs (patches with more than KH * bs of them), two per pass
+  // with every load of a pass issued before any is used
+  for (int j0 = tid + KH * bs; j0 < nsh; j0 += 2 * bs) {
+    int r2[2], g2[2];
+    int2 s2[2];
+    T u2[2], c2v[2], f2[2], d2[2], gm2[2], b2[2], p0[2], p1[2], pr0[2], pr1[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      r2[t] = sh0 + min(j0 + t * bs, nsh - 1);
+      g2[t] = A.sh_idx[r2[t]];
+      s2[t] = reinterpret_cast<const int2*>(A.ref_slots)[r2[t]];
+      u2[t] = uref[r2[t]];
+      c2v[t] = A.c2_ref[r2[t]];
+      if (ADJ) f2[t] = A.uf[N + r2[t]];
+      d2[t] = A.dsh_prev[r2[t]];
+      gm2[t] = A.gamma_ref[r2[t]];
+      b2[t] = bref[r2[t]];
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int sy = s2[t].y >= 0 ? s2[t].y : s2[t].x;
+      p0[t] = A.part_prev[s2[t].x];
+      p1[t] = A.part_prev[sy];
+      if (ADJ) {
+        pr0[t] = A.partr_prev[s2[t].x];
+        pr1[t] = A.partr_prev[sy];
       }
-      const T dn = (damped ? bref[r] : T(1)) * A.dsh_prev[r] - A.gamma_ref[r] * y;
-      u = u + dn;
-      A.u_in_sh[N + r] = u;
-      A.dsh_cur[r] = dn;
-      if (sj.x == r) {
-        A.u_in_sh[g] = u;
-        if (ADJ) {
-          T rr = A.partr_prev[sj.x] + A.partr_prev[pair ? sj.y : sj.x];
-          if (!pair) {
-            rr = T(0);
-            for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) rr += A.partr_prev[A.shp_slot[k]];
+      if (!step) u2[t] = A.u_in[g2[t]];
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int j = j0 + t * bs;
+      if (j >= nsh) continue;
+      const int r = r2[t], g = g2[t];
+      const int64_t s = g - A.n_own;
+      const int2 sj = s2[t];
+      const bool pair = sj.y >= 0;
+      T u = u2[t];
+      if (step && A.prev) {
+        T y = p0[t] + p1[t];
+        if (!pair) {
+          y = T(0);
+          for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) y += A.part_prev[A.shp_slot[k]];
+        }
+        const T dn = (damped ? b2[t] : T(1)) * d2[t] - gm2[t] * y;
+        u = u + dn;
+        A.u_in_sh[N + r] = u;
+        A.dsh_cur[r] = dn;
+        if (sj.x == r) {
+          A.u_in_sh[g] = u;
+          if (ADJ) {
+            T rr = pr0[t] + pr1[t];
+            if (!pair) {
+              rr = T(0);
+              for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) rr += A.partr_prev[A.shp_slot[k]];
+            }
+            A.gacc[g] += (double)rr;
           }
-          A.gacc[g] += (double)rr;
         }
       }
+      su[nbo + j] = u;
+      sc[nbo + j] = c2v[t];
+      if (ADJ) sf[nbo + j] = f2[t];
     }
-    su[nbo + j] = u;
-    sc[nbo + j] = A.c2_ref[r];
-    if (ADJ) sf[nbo + j] = A.uf[N + r];
   }
   {
     uint4* gldst = reinterpret_cast<uint4*>(gl);

@@ -23,7 +23,7 @@ struct Mesh {
   int64_t n_vertices = 0, n_cells = 0, n_dofs = 0;
   std::vector<double> coords;        // [n_vertices*dim]
   std::vector<int32_t> cells_in;     // [n_cells*(dim+1)], input order
-  // internal cell order (patch-major, colour-sorted inside a patch)
+  // internal cell order (patch-major, recursive-bisection order inside a patch)
   std::vector<int64_t> cell_input;   // internal -> input cell id
   std::vector<int64_t> cell_dofs;    // [n_cells*nd] internal order, final DOF ids
   std::vector<double> x0;            // [n_cells*dim] first vertex (internal order)

@@ -451,7 +451,7 @@ Status plan_storage(Problem* p) {
   const Mesh& m = *p->mesh;
   const size_t vb = (size_t)p->ls * p->ts;
   const size_t all = (size_t)(p->nt + 1) * vb;
-  if (p->ckpt_every <= 0 && all <= p->budget) {
+  if (p->ckpt_every == 0 && all <= p->budget) {
     p->store_all = true;
     p->seg = p->nt;
     p->n_ck = 0;

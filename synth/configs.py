@@ -19,7 +19,8 @@ Names describe the workload:
   layered_tet_kmv3  3D 4 x 4 x 2 km layered + anomalies, 500 m sponge on five
                     faces, Maubach-graded Kuhn tetrahedra (shortest edge below
                     s * vp / (5 Hz * 2.5), s = 0.355 -> 1.33M tetrahedra, 16.9M KMV3 DOFs),
-                    KMV3tet, 40x40 receiver grid, T = 2 s.
+                    KMV3tet, 40x40 receiver grid, T = 2 s.  Observed data from
+                    the full model, current model = layers only.
 """
 from __future__ import annotations
 
@@ -151,6 +152,7 @@ def layered_tet_kmv3(seed=21, coarse_h=0.5, scale=0.355):
     coords = jitter_vertices(coords, cells, 0.15, seed + 1000)
     return Workload(
         name="layered_tet_kmv3", dim=3, degree=3, coords=coords, cells=cells,
-        vp=vp, vp_obs=vp, eta=_sponge3d, sources=np.array([[2.0, 2.0, 0.01]]),
+        vp=layered_anomaly_vp_3d(seed, n_anom=0), vp_obs=vp, eta=_sponge3d,
+        sources=np.array([[2.0, 2.0, 0.01]]),
         receivers=grid_receivers_3d(40, 40, (0.1, 0.1), (3.9, 3.9), 0.1),
         T=2.0, dt=None, extra={"seed": seed, "scale": scale})

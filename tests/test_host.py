@@ -109,7 +109,7 @@ def test_mesh_matches_oracle(kind, k, patch):
 
 def test_large_graded_mesh_invariants():
     """The full-size graded layered mesh (about 150k triangles) preprocesses
-    with valid colouring and patch maps at degree 4."""
+    with valid patch maps and gather words at degree 4."""
     w = configs.layered_kmv4()
     m = Mesh(w.coords, w.cells, 4)
     m.validate()
