@@ -123,11 +123,25 @@ typedef struct {
                                this many steps; < 0 = checkpoints every
                                ceil(sqrt(2 N_t)) steps */
   size_t mem_budget;        /* bytes of device memory for stored states (0 = 8 GiB) */
+  int n_shots;              /* shots stepped together (0 or 1 = one; at most 1024) */
 } kmv_options;
 
-/* Allocate device state for one shot configuration on the current device.
+/* Allocate device state for n_shots shots on the current device.
+ *
+ * The shots of one problem share the mesh, the wave speed, the damping, dt, the
+ * wavelet and the receivers, and differ in their source positions (the shots of
+ * one acquisition, section "Parallelism": independent wave equations whose
+ * misfits and gradients are summed, eq. gradient3).  Every step kernel launch
+ * advances all shots; each shot's arithmetic is the same as in a one-shot
+ * problem, so its traces are bitwise those of a one-shot problem with its
+ * sources.  Per-shot inputs and outputs are shot-major: sources
+ * [n_shots][n_src/n_shots][dim], traces, observed and adjoint-source data
+ * [n_shots][n_steps][n_rec], source traces [n_shots][n_steps][n_src/n_shots].
+ * J and grad are sums over the shots (float64, fixed order).
  * Errors: KMV_EINVAL, KMV_ENOMEM, KMV_EDEVICE. */
 int kmv_problem_create(kmv_mesh m, const kmv_options* opt, kmv_problem* out);
+/* Shots of a problem. */
+int kmv_problem_num_shots(kmv_problem p, int* n_shots);
 /* Spectral radius of M^-1 K(c) by a seeded power iteration on the GPU (the step
  * bound of eq. spectral without the Gershgorin over-estimate).  The start vector
  * is a normal deviate per DOF hashed from the seed and the DOF coordinates, so the
@@ -140,7 +154,9 @@ int kmv_set_damping(kmv_problem p, const double* eta);
 /* Point sources x_s [n_src*dim] firing together with a Ricker wavelet
  * w(t) = amp (1 - 2 pi^2 f0^2 (t-t0)^2) exp(-pi^2 f0^2 (t-t0)^2) sampled at
  * t_n = n dt; injected as w(t_n) phi_a(x_s) (section "Receivers and sources").
- * Errors: KMV_EOUTSIDE. */
+ * With n_shots > 1 the points are shot-major and n_src is a multiple of
+ * n_shots: shot s fires points s*n_src/n_shots .. (s+1)*n_src/n_shots - 1.
+ * Errors: KMV_EOUTSIDE, KMV_EINVAL. */
 int kmv_set_sources(kmv_problem p, const double* xs, int n_src, double f0, double t0,
                     double amp);
 /* Replace the wavelet by w[n_steps] (host). */
@@ -150,26 +166,29 @@ int kmv_set_source_wavelet(kmv_problem p, const double* w);
 int kmv_set_receivers(kmv_problem p, const double* xr, int n_rec);
 
 /* Forward solve (eqs. Leapfrog/forward3).  c_dev: double [n_dofs] wavespeed (DOF
- * order).  traces_dev: [n_steps*n_rec] of the problem's type, row n-1 = d^n.
- * Asynchronous on stream. */
+ * order).  traces_dev: [n_shots*n_steps*n_rec] of the problem's type, row n-1 of
+ * a shot = d^n.  Asynchronous on stream. */
 int kmv_forward(kmv_problem p, const void* c_dev, void* traces_dev, void* stream);
 /* Misfit and gradient: forward with stored or checkpointed states, J (eq.
  * l2error, no dt), adjoint sweep (eq. acoustic_pml_FEM_adj) fused with the
- * gradient accumulation (eq. gradient3).  observed_dev: [n_steps*n_rec] of the
- * problem's type.  grad_dev: double [n_dofs] receives dJ/dc_i (Euclidean; the
- * mesh-independent gradient is grad/M).  traces_dev: optional [n_steps*n_rec]
- * output of the forward traces (NULL = not kept).  J_out (host) and the
- * synchronisation: the stream is synchronised before return. */
+ * gradient accumulation (eq. gradient3).  observed_dev: [n_shots*n_steps*n_rec]
+ * of the problem's type.  grad_dev: double [n_dofs] receives dJ/dc_i summed over
+ * the shots (Euclidean; the mesh-independent gradient is grad/M).  traces_dev:
+ * optional [n_shots*n_steps*n_rec] output of the forward traces (NULL = not
+ * kept).  J_out (host) and the synchronisation: the stream is synchronised
+ * before return. */
 int kmv_misfit_gradient(kmv_problem p, const void* c_dev, const void* observed_dev,
                         double* J_out, double* grad_dev, void* traces_dev, void* stream);
 /* Adjoint of the forward map for arbitrary receiver data y: lambda from the
  * transposed scheme, (1+a) lambda^m = 2 lambda^{m+1} - dt^2 M^-1 K lambda^{m+1}
  * - (1-a) lambda^{m+2} + M^-1 P^T y^m, m = N_t..1 (eq. acoustic_pml_FEM_adj).
- * adj_src_dev: [n_steps*n_rec] of the problem's type, row m-1 = y^m.
- * lambda_out_dev (optional): [(n_steps+1)*n_dofs], row m-1 = lambda^m.
- * src_trace_dev (optional): [n_steps*n_src], row n = lambda^{n+1} sampled at the
- * source points, so that <y, P u> = dt^2 sum_n w(t_n) sum_s src_trace[n][s]
- * (the dot-product identity of the discrete adjoint). */
+ * adj_src_dev: [n_shots*n_steps*n_rec] of the problem's type, row m-1 of a shot
+ * = y^m.  lambda_out_dev (optional, one-shot problems only):
+ * [(n_steps+1)*n_dofs], row m-1 = lambda^m.
+ * src_trace_dev (optional): [n_shots*n_steps*(n_src/n_shots)], row n of a shot =
+ * lambda^{n+1} sampled at the shot's source points, so that for each shot
+ * <y, P u> = dt^2 sum_n w(t_n) sum_s src_trace[n][s] (the dot-product identity
+ * of the discrete adjoint). */
 int kmv_adjoint(kmv_problem p, const void* c_dev, const void* adj_src_dev,
                 void* lambda_out_dev, void* src_trace_dev, void* stream);
 /* Matrix-free stiffness apply y = K(c) u (appendix, matrix K).  u_dev, y_dev of

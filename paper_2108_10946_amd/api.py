@@ -60,15 +60,21 @@ class Mesh:
 
 
 class Problem:
-    """Device state for one shot layout on one mesh (see kmv_problem_create)."""
+    """Device state for n_shots shots on one mesh (see kmv_problem_create).
 
-    def __init__(self, mesh: Mesh, dt, n_steps, precision="fp64", checkpoint_every=0, mem_budget=0):
+    With n_shots > 1 the shots share wave speed, damping, wavelet and receivers;
+    sources are given shot-major, traces and observed data are
+    [n_shots, n_steps, n_rec], and J and the gradient are sums over the shots."""
+
+    def __init__(self, mesh: Mesh, dt, n_steps, precision="fp64", checkpoint_every=0, mem_budget=0,
+                 n_shots=1):
         self.mesh = mesh
         self.dt = float(dt)
         self.n_steps = int(n_steps)
+        self.n_shots = int(n_shots)
         self.precision = K.KMV_FP32 if precision in ("fp32", K.KMV_FP32) else K.KMV_FP64
         self.handle = K.kmv_problem_create(mesh.handle, self.precision, self.dt, self.n_steps,
-                                           checkpoint_every, mem_budget)
+                                           checkpoint_every, mem_budget, self.n_shots)
         self.n_rec = 0
         self.n_src = 0
 
@@ -90,7 +96,8 @@ class Problem:
         K.kmv_set_damping(self.handle, eta)
 
     def set_sources(self, xs, f0=5.0, t0=None, amp=1.0):
-        xs = np.atleast_2d(np.asarray(xs, dtype=np.float64))
+        xs = np.asarray(xs, dtype=np.float64)
+        xs = xs.reshape(-1, xs.shape[-1]) if xs.ndim == 3 else np.atleast_2d(xs)  # [n_shots, n, dim] or flat
         K.kmv_set_sources(self.handle, xs, f0, 1.0 / f0 if t0 is None else t0, amp)
         self.n_src = len(xs)
 
@@ -101,6 +108,10 @@ class Problem:
         xr = np.atleast_2d(np.asarray(xr, dtype=np.float64))
         K.kmv_set_receivers(self.handle, xr)
         self.n_rec = len(xr)
+
+    def _shape(self, *tail):
+        """Shape of a per-shot array: [n_steps, ...] for one shot, else [n_shots, n_steps, ...]."""
+        return (self.n_steps, *tail) if self.n_shots == 1 else (self.n_shots, self.n_steps, *tail)
 
     def _c(self, c):
         torch = _torch()
@@ -113,8 +124,10 @@ class Problem:
     def forward(self, c, out=None):
         torch = _torch()
         c = self._c(c)
-        tr = out if out is not None else torch.empty((self.n_steps, self.n_rec), dtype=self.dtype,
+        tr = out if out is not None else torch.empty(self._shape(self.n_rec), dtype=self.dtype,
                                                       device=c.device)
+        if tr.numel() != self.n_shots * self.n_steps * self.n_rec or not tr.is_contiguous():
+            raise ValueError("out must be a contiguous " + str(self._shape(self.n_rec)) + " tensor")
         K.kmv_forward(self.handle, c, tr)
         return tr
 
@@ -122,8 +135,8 @@ class Problem:
         torch = _torch()
         c = self._c(c)
         obs = observed.to(dtype=self.dtype).contiguous()
-        if obs.shape != (self.n_steps, self.n_rec):
-            raise ValueError("observed must be [n_steps, n_rec]")
+        if tuple(obs.shape) != self._shape(self.n_rec):
+            raise ValueError("observed must be " + str(list(self._shape(self.n_rec))))
         g = torch.empty(self.mesh.n_dofs, dtype=torch.float64, device=c.device)
         tr = torch.empty_like(obs) if keep_traces else None
         J = K.kmv_misfit_gradient(self.handle, c, obs, g, tr)
@@ -133,9 +146,13 @@ class Problem:
         torch = _torch()
         c = self._c(c)
         adj = adj.to(dtype=self.dtype).contiguous()
+        if tuple(adj.shape) != self._shape(self.n_rec):
+            raise ValueError("adj must be " + str(list(self._shape(self.n_rec))))
+        if keep_lambda and self.n_shots != 1:
+            raise ValueError("keep_lambda needs a one-shot problem")
         lam = (torch.empty((self.n_steps + 1, self.mesh.n_dofs), dtype=self.dtype, device=c.device)
                if keep_lambda else None)
-        st = (torch.empty((self.n_steps, self.n_src), dtype=self.dtype, device=c.device)
+        st = (torch.empty(self._shape(self.n_src // self.n_shots), dtype=self.dtype, device=c.device)
               if src_trace else None)
         K.kmv_adjoint(self.handle, c, adj, lam, st)
         return lam, st

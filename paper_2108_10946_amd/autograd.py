@@ -3,7 +3,8 @@
 The forward pass runs the GPU forward solve, the float64 misfit J (eq. l2error
 without a dt factor) and the fused adjoint + gradient sweep (eq. gradient3) in one
 call of kmv_misfit_gradient, and keeps dJ/dc for the backward pass, which returns
-grad_output * dJ/dc.  Several shots (one Problem each) are summed.
+grad_output * dJ/dc.  Several shots (one Problem each, or Problems holding several
+shots each) are summed.
 """
 from __future__ import annotations
 

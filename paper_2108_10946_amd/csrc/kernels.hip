@@ -69,7 +69,43 @@ __device__ __forceinline__ T gather_sum(uint32_t w, const T* x, const uint16_t* 
 }
 
 template <typename T, int DIM, int ND, bool ADJ>
-__global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
+__global__ void __launch_bounds__(512) k_step(const StepArgs<T> A0) {
+  // XCD-aware work order: the dispatcher deals workgroups round-robin over the 8
+  // XCDs (separate L2 caches), so workgroup b runs on XCD b % 8.  Each XCD gets a
+  // contiguous run of work items, patch-major: neighbouring patches, which
+  // exchange shared-DOF partials and read each other's levels, and the shots of
+  // one patch, which read the same mesh tables and coefficients, mostly share one
+  // L2.
+  int p, shot;
+  {
+    const int b = blockIdx.x, nw = gridDim.x, x = b & 7, k = b >> 3;
+    const int base = nw >> 3, rem = nw & 7;
+    const int i = x * base + min(x, rem) + k;
+    const int ns = A0.n_shots;
+    p = ns == 1 ? i : i / ns;
+    shot = i - p * ns;
+  }
+  StepArgs<T> A = A0;
+  if (shot != 0) {
+    A.u_in += shot * A.ss_level;
+    A.u_in_sh += shot * A.ss_level;
+    A.u_prev += shot * A.ss_level;
+    A.u_out += shot * A.ss_level;
+    A.du += shot * A.ss_dof;
+    A.dsh_prev += shot * A.ss_ref;
+    A.dsh_cur += shot * A.ss_ref;
+    A.part_prev += shot * A.ss_ref;
+    A.part_cur += shot * A.ss_ref;
+    if (A.amp != nullptr) A.amp += shot * A.ss_amp;
+    if (A.trace_row != nullptr) A.trace_row += shot * A.ss_trace;
+    if (A.inj_ptr != nullptr) A.inj_ptr += shot * A.ss_inj;
+    if (ADJ) {
+      A.uf += shot * A.ss_level;
+      A.partr_prev += shot * A.ss_ref;
+      A.partr_cur += shot * A.ss_ref;
+      A.gacc += shot * A.ss_dof;
+    }
+  }
   using Tab = KmvTab<T, DIM, ND>;  // compile-time reference gradients, weights, node classes
   constexpr int NI = Tab::NI, NB = Tab::NB;
   constexpr int NIa = NI > 0 ? NI : 1, NBa = NB > 0 ? NB : 1;
@@ -83,16 +119,6 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
   T* sr = sx + (NB * CS + 1);                       // gradient pairing per cell node (ADJ)
   uint16_t* gl = reinterpret_cast<uint16_t*>(smem_raw + lay.gl);
   const int tid = threadIdx.x, bs = blockDim.x;
-  // XCD-aware patch order: the dispatcher deals workgroups round-robin over the 8
-  // XCDs (separate L2 caches), so workgroup b runs on XCD b % 8.  Each XCD gets a
-  // contiguous run of patches: neighbouring patches, which exchange shared-DOF
-  // partials and read each other's levels, then mostly share one L2.
-  int p;
-  {
-    const int b = blockIdx.x, np = gridDim.x, x = b & 7, k = b >> 3;
-    const int base = np >> 3, rem = np & 7;
-    p = x * base + min(x, rem) + k;
-  }
   const int c0 = A.cell_start[p], nc = A.cell_start[p + 1] - c0;
   const int own0 = A.own_start[p], bo0 = own0 + NI * nc, nbo = A.own_start[p + 1] - bo0;
   const int sh0 = A.sh_start[p], nsh = A.sh_start[p + 1] - sh0;
@@ -521,9 +547,22 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs<T> A) {
 }
 
 template <typename T, bool ADJ>
-__global__ void __launch_bounds__(256) k_finish(const FinishArgs<T> A) {
+__global__ void __launch_bounds__(256) k_finish(const FinishArgs<T> A0) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= A.n_shared) return;
+  if (s >= A0.n_shared) return;
+  FinishArgs<T> A = A0;
+  const int shot = blockIdx.y;
+  if (shot != 0) {
+    A.part_prev += shot * A.ss_ref;
+    A.u_prev += shot * A.ss_level;
+    A.u_cur += shot * A.ss_level;
+    A.dsh_prev += shot * A.ss_ref;
+    A.dsh_cur += shot * A.ss_ref;
+    if (ADJ) {
+      A.partr_prev += shot * A.ss_ref;
+      A.gacc += shot * A.ss_dof;
+    }
+  }
   const int64_t g = A.n_own + s;
   const int k0 = A.shp_ptr[s], k1 = A.shp_ptr[s + 1];
   // the same fixed order as the step kernel (two patches: first + second)
@@ -628,10 +667,13 @@ __global__ void __launch_bounds__(256) k_reduce_parts(const double* __restrict__
   if (threadIdx.x == 0) *out = scale * s;
 }
 
-__global__ void k_finalize_grad(const double* __restrict__ c, const double* __restrict__ gacc,
+__global__ void k_finalize_grad(const double* __restrict__ c, const double* __restrict__ gacc, int ns,
                                 double scale, double* __restrict__ g, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) g[i] = scale * c[i] * gacc[i];
+  if (i >= n) return;
+  double a = gacc[i];
+  for (int s = 1; s < ns; ++s) a += gacc[s * n + i];
+  g[i] = scale * c[i] * a;
 }
 
 template <typename T>
@@ -679,7 +721,7 @@ hipError_t launch_step_t(const StepArgs<T>& a, int np, int block, hipStream_t s,
                          hipEvent_t e1) {
   const size_t lds =
       StepLds(a.nbl_max, a.slot_stride, KmvTab<T, DIM, ND>::NB, a.glist_max, ADJ, sizeof(T)).total;
-  launch_ev(k_step<T, DIM, ND, ADJ>, dim3(np), dim3(block), (uint32_t)lds, s, e0, e1, a);
+  launch_ev(k_step<T, DIM, ND, ADJ>, dim3(np * a.n_shots), dim3(block), (uint32_t)lds, s, e0, e1, a);
   return hipGetLastError();
 }
 
@@ -722,11 +764,11 @@ template <typename T>
 hipError_t launch_finish(bool adjoint, const FinishArgs<T>& a, hipStream_t s, hipEvent_t e0,
                          hipEvent_t e1) {
   if (a.n_shared == 0) return hipSuccess;
-  const unsigned nb = blocks_for(a.n_shared, 256);
+  const unsigned nb = blocks_for(a.n_shared, 256), ns = (unsigned)(a.n_shots > 0 ? a.n_shots : 1);
   if (adjoint)
-    launch_ev(k_finish<T, true>, dim3(nb), dim3(256), 0u, s, e0, e1, a);
+    launch_ev(k_finish<T, true>, dim3(nb, ns), dim3(256), 0u, s, e0, e1, a);
   else
-    launch_ev(k_finish<T, false>, dim3(nb), dim3(256), 0u, s, e0, e1, a);
+    launch_ev(k_finish<T, false>, dim3(nb, ns), dim3(256), 0u, s, e0, e1, a);
   return hipGetLastError();
 }
 
@@ -773,9 +815,10 @@ hipError_t launch_misfit(const T* d, const T* obs, T* resid, int64_t n, double* 
   return hipGetLastError();
 }
 
-hipError_t launch_finalize_grad(const double* c, const double* gacc, double scale, double* g, int64_t n,
-                                hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_grad, dim3(blocks_for(n, 256)), dim3(256), 0, s, c, gacc, scale, g, n);
+hipError_t launch_finalize_grad(const double* c, const double* gacc, int n_shots, double scale, double* g,
+                                int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_grad, dim3(blocks_for(n, 256)), dim3(256), 0, s, c, gacc, n_shots, scale, g,
+                     n);
   return hipGetLastError();
 }
 

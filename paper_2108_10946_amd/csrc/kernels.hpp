@@ -86,6 +86,17 @@ struct StepArgs {
   const T* partr_prev;         // pairing partials of the previous step
   T* partr_cur;
   double* gacc;                // [n_dofs] float64 gradient accumulator
+  // shots stepped together: the launch has n_patches * n_shots workgroups, work
+  // item i being (patch i / n_shots, shot i % n_shots).  Every per-shot buffer of
+  // shot s starts s times its stride after shot 0's; mesh tables and coefficients
+  // are shared.  A stride of 0 shares the buffer between shots.
+  int n_shots;                 // >= 1 (1 in apply mode)
+  int64_t ss_level;            // u_in, u_in_sh, u_prev, u_out, uf
+  int64_t ss_dof;              // du, gacc
+  int64_t ss_ref;              // dsh_prev, dsh_cur, part_prev, part_cur, partr_prev, partr_cur
+  int64_t ss_amp;              // amp
+  int64_t ss_trace;            // trace_row
+  int64_t ss_inj;              // inj_ptr (a [np+1] block per shot, or shared)
 };
 
 // Finisher: the shared DOFs of a level from the last step's partials (end of a
@@ -106,6 +117,9 @@ struct FinishArgs {
   T* y_out;
   const T* partr_prev;
   double* gacc;
+  // shots: blockIdx.y; per-shot strides as in StepArgs
+  int n_shots;
+  int64_t ss_level, ss_dof, ss_ref;
 };
 
 // e0/e1: optional events recorded by the dispatch itself at kernel start and end.
@@ -129,7 +143,8 @@ hipError_t launch_fill_f64(double* x, double v, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_misfit(const T* d, const T* obs, T* resid, int64_t n, double* scratch,
                          int nblocks, double* J_out, hipStream_t s);
-hipError_t launch_finalize_grad(const double* c, const double* gacc, double scale, double* g,
+// g = scale * c * sum_s gacc[s*n + i], shots summed in order
+hipError_t launch_finalize_grad(const double* c, const double* gacc, int n_shots, double scale, double* g,
                                 int64_t n, hipStream_t s);
 // out[r] = x[idx[r]], r < n (per-ref copies of a DOF vector)
 template <typename T>

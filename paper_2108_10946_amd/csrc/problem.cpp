@@ -168,8 +168,11 @@ Status upload_coefficients(Problem* p) {
 
 // Point tables: each point is located in one cell (lowest input id on ties); its
 // entry (patch-local cell, point index, phi_a(x) per node) goes to the patch of
-// that cell, entries in point order.  Global rows: DOF ids and weights.
-Status build_points(Problem* p, const double* xyz, int npts, PointTables& T) {
+// that cell, entries in point order.  Global rows: DOF ids and weights.  With
+// nshot > 1 the points are shot-major, npts/nshot per shot, and each shot gets its
+// own [np+1] block of patch offsets (into the shared entry arrays) and point
+// indices counted within the shot.
+Status build_points(Problem* p, const double* xyz, int npts, int nshot, PointTables& T) {
   const Mesh& m = *p->mesh;
   const int nd = m.nd, dim = m.dim;
   std::vector<int32_t> sdof((size_t)npts * nd);
@@ -191,18 +194,27 @@ Status build_points(Problem* p, const double* xyz, int npts, PointTables& T) {
     patch_of[j] = (int32_t)(std::upper_bound(m.patch_cell_start.begin(), m.patch_cell_start.end(),
                                              (int32_t)cell_of[j]) - m.patch_cell_start.begin() - 1);
   }
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return patch_of[a] < patch_of[b]; });
-  std::vector<int32_t> ptr(m.n_patches + 1, 0), pcell(npts), ppt(npts);
+  const int nps = npts / nshot;
+  const int64_t np1 = m.n_patches + 1;
+  std::vector<int32_t> ptr((size_t)nshot * np1, 0), pcell(npts), ppt(npts);
   std::vector<double> pw((size_t)npts * nd);
-  for (int k = 0; k < npts; ++k) {
-    const int j = order[k];
-    ptr[patch_of[j] + 1]++;
-    pcell[k] = (int32_t)(cell_of[j] - m.patch_cell_start[patch_of[j]]);
-    ppt[k] = j;
-    for (int a = 0; a < nd; ++a) pw[(size_t)k * nd + a] = sw[(size_t)j * nd + a];
+  for (int s = 0; s < nshot; ++s) {
+    const int j0 = s * nps;
+    std::stable_sort(order.begin() + j0, order.begin() + j0 + nps,
+                     [&](int32_t a, int32_t b) { return patch_of[a] < patch_of[b]; });
+    int32_t* pt = ptr.data() + (size_t)s * np1;
+    for (int k = j0; k < j0 + nps; ++k) {
+      const int j = order[k];
+      pt[patch_of[j] + 1]++;
+      pcell[k] = (int32_t)(cell_of[j] - m.patch_cell_start[patch_of[j]]);
+      ppt[k] = j - j0;
+      for (int a = 0; a < nd; ++a) pw[(size_t)k * nd + a] = sw[(size_t)j * nd + a];
+    }
+    pt[0] = j0;
+    for (int64_t q = 0; q < m.n_patches; ++q) pt[q + 1] += pt[q];
   }
-  for (int64_t q = 0; q < m.n_patches; ++q) ptr[q + 1] += ptr[q];
   T.npts = npts;
+  T.shot_stride = nshot > 1 ? np1 : 0;
   STTRY(upload_i(&T.pp_ptr, ptr));
   STTRY(upload_i(&T.pp_cell, pcell));
   STTRY(upload_i(&T.pp_pt, ppt));
@@ -288,6 +300,11 @@ StepArgs<T> base_args(const Problem* p) {
   a.beta_ref = (const T*)p->d_beta_ref;
   a.damp_patch = p->d_damp_patch;
   a.amp_scale = T(1);
+  a.n_shots = p->nshot;
+  a.ss_level = p->ls;
+  a.ss_dof = m.n_dofs;
+  a.ss_ref = p->rs;
+  a.ss_trace = p->nt * p->rec.npts;
   return a;
 }
 
@@ -299,8 +316,8 @@ struct Par {
 
 template <typename T>
 Status step(Problem* p, Sweep& S, bool grad, bool prev, const T* u_in, const T* u_prev, T* u_out, Par q,
-            const PointTables* inj, const T* amp, int amp_stride, T scale, const T* uf, T* trace_row,
-            hipStream_t s) {
+            const PointTables* inj, const T* amp, int amp_stride, int64_t amp_shot_stride, T scale,
+            const T* uf, T* trace_row, hipStream_t s) {
   const Mesh& m = *p->mesh;
   StepArgs<T> a = base_args<T>(p);
   a.mode = 0;
@@ -322,6 +339,8 @@ Status step(Problem* p, Sweep& S, bool grad, bool prev, const T* u_in, const T* 
     a.amp = amp;
     a.amp_stride = amp_stride;
     a.amp_scale = scale;
+    a.ss_inj = inj->shot_stride;
+    a.ss_amp = amp_shot_stride;
   }
   if (trace_row) {
     a.rec_ptr = p->rec.pp_ptr;
@@ -364,6 +383,10 @@ Status finish(Problem* p, Sweep& S, bool grad, const T* u_prev, T* u_cur, Par q,
     f.partr_prev = (const T*)S.partr[q.step_prev];
     f.gacc = p->d_gacc;
   }
+  f.n_shots = p->nshot;
+  f.ss_level = p->ls;
+  f.ss_dof = m.n_dofs;
+  f.ss_ref = p->rs;
   return probed(p, grad ? 3 : 2, s,
                 [&](hipEvent_t e0, hipEvent_t e1) { return launch_finish<T>(grad, f, s, e0, e1); });
 }
@@ -374,12 +397,12 @@ Par adj_par(int64_t m) { return Par{(int)(m & 1), (int)((m + 1) & 1), (int)((m +
 
 template <typename T>
 T* slot_ptr(Problem* p, int64_t k) {
-  return (T*)p->d_slots + k * p->ls;
+  return (T*)p->d_slots + k * p->ls * p->nshot;
 }
 
 Status ensure_slots(Problem* p, int64_t n) {
   if (p->n_slots >= n) return OK;
-  STTRY(alloc(&p->d_slots, (size_t)n * p->ls * p->ts));
+  STTRY(alloc(&p->d_slots, (size_t)n * p->ls * p->nshot * p->ts));
   p->n_slots = n;
   return OK;
 }
@@ -387,9 +410,9 @@ Status ensure_slots(Problem* p, int64_t n) {
 template <typename T>
 Status zero_level(Problem* p, Sweep& S, T* u, int lvl_par, hipStream_t s) {
   const Mesh& m = *p->mesh;
-  HIPTRY(launch_fill<T>(u, T(0), p->ls, s));
-  HIPTRY(launch_fill<T>((T*)S.d, T(0), m.n_dofs, s));
-  HIPTRY(launch_fill<T>((T*)S.dsh[lvl_par], T(0), std::max<int64_t>(1, p->nref), s));
+  HIPTRY(launch_fill<T>(u, T(0), p->ls * p->nshot, s));
+  HIPTRY(launch_fill<T>((T*)S.d, T(0), m.n_dofs * p->nshot, s));
+  HIPTRY(launch_fill<T>((T*)S.dsh[lvl_par], T(0), p->rs * p->nshot, s));
   return OK;
 }
 
@@ -400,32 +423,35 @@ template <typename T, typename F>
 Status run_forward(Problem* p, int64_t n0, int64_t n1, F slot_of, T* traces, bool save_ck, hipStream_t s) {
   const Mesh& m = *p->mesh;
   Sweep& S = p->fwd;
-  const size_t lb = (size_t)p->ls * sizeof(T);
-  const size_t ob = (size_t)m.n_own_total * sizeof(T), shb = (size_t)p->nref * sizeof(T);
+  const int64_t ns = p->nshot;
+  const size_t lb = (size_t)(p->ls * ns) * sizeof(T);
+  const size_t ob = (size_t)(m.n_dofs * ns) * sizeof(T), shb = (size_t)(p->rs * ns) * sizeof(T);
   bool fresh = true;
   for (int64_t n = n0; n < n1; ++n) {
     if (save_ck && n % p->seg == 0) {
       if (!fresh) STTRY(finish<T>(p, S, false, slot_of(n - 1), slot_of(n), fwd_par(n), s));
       const int64_t k = n / p->seg;
-      T* cu = (T*)p->d_ck_u + k * p->ls;
-      T* cd = (T*)p->d_ck_du + k * (m.n_own_total + p->nref);
+      T* cu = (T*)p->d_ck_u + k * p->ls * ns;
+      T* cd = (T*)p->d_ck_du + k * (m.n_dofs + p->rs) * ns;
       HIPTRY(hipMemcpyAsync(cu, slot_of(n), lb, hipMemcpyDeviceToDevice, s));
       HIPTRY(hipMemcpyAsync(cd, S.d, ob, hipMemcpyDeviceToDevice, s));
-      if (shb) HIPTRY(hipMemcpyAsync(cd + m.n_own_total, S.dsh[n & 1], shb, hipMemcpyDeviceToDevice, s));
+      HIPTRY(hipMemcpyAsync(cd + m.n_dofs * ns, S.dsh[n & 1], shb, hipMemcpyDeviceToDevice, s));
       fresh = true;
     }
     T* row = (traces && n >= 1) ? traces + (n - 1) * p->rec.npts : nullptr;
     STTRY(step<T>(p, S, false, !fresh, slot_of(n), n > n0 ? slot_of(n - 1) : nullptr, slot_of(n + 1),
-                  fwd_par(n), &p->src, (const T*)p->d_wavelet + n, 0, T(1), nullptr, row, s));
+                  fwd_par(n), &p->src, (const T*)p->d_wavelet + n, 0, 0, T(1), nullptr, row, s));
     fresh = false;
   }
   if (n1 > n0) STTRY(finish<T>(p, S, false, slot_of(n1 - 1), slot_of(n1), fwd_par(n1), s));
   if (traces && n1 >= 1) {
-    T* un = slot_of(n1);
-    STTRY(probed(p, 4, s, [&](hipEvent_t e0, hipEvent_t e1) {
-      return launch_sample<T>(un, p->rec.s_dof, (const T*)p->rec.s_w, p->rec.npts, m.nd,
-                              traces + (n1 - 1) * p->rec.npts, s, e0, e1);
-    }));
+    for (int64_t sh = 0; sh < ns; ++sh) {
+      T* un = slot_of(n1) + sh * p->ls;
+      T* out = traces + sh * p->nt * p->rec.npts + (n1 - 1) * p->rec.npts;
+      STTRY(probed(p, 4, s, [&](hipEvent_t e0, hipEvent_t e1) {
+        return launch_sample<T>(un, p->rec.s_dof, (const T*)p->rec.s_w, p->rec.npts, m.nd, out, s, e0, e1);
+      }));
+    }
   }
   return OK;
 }
@@ -449,7 +475,7 @@ Status forward_t(Problem* p, const double* c, T* traces, hipStream_t s) {
 
 Status plan_storage(Problem* p) {
   const Mesh& m = *p->mesh;
-  const size_t vb = (size_t)p->ls * p->ts;
+  const size_t vb = (size_t)p->ls * p->nshot * p->ts;
   const size_t all = (size_t)(p->nt + 1) * vb;
   if (p->ckpt_every == 0 && all <= p->budget) {
     p->store_all = true;
@@ -467,7 +493,7 @@ Status plan_storage(Problem* p) {
     return Status{KMV_ENOMEM, "checkpoint storage (" + std::to_string(need) + " B) exceeds mem_budget"};
   if (p->seg != seg || p->n_ck != nck || !p->d_ck_u) {
     STTRY(alloc(&p->d_ck_u, (size_t)nck * vb));
-    STTRY(alloc(&p->d_ck_du, (size_t)nck * (m.n_own_total + p->nref) * p->ts));
+    STTRY(alloc(&p->d_ck_du, (size_t)nck * (m.n_dofs + p->rs) * p->nshot * p->ts));
   }
   p->seg = seg;
   p->n_ck = nck;
@@ -481,13 +507,13 @@ Status adjoint_launch(Problem* p, int64_t m, bool grad, const T* adj_rows, const
   T* lam_in = (T*)p->d_lam[(m + 1) & 1];
   T* lam_out = (T*)p->d_lam[m & 1];
   return step<T>(p, p->adj, grad, m != p->nt, lam_in, lam_out, lam_out, adj_par(m), &p->rec,
-                 adj_rows + (m - 1) * p->rec.npts, 1, (T)inv_dt2, uf, nullptr, s);
+                 adj_rows + (m - 1) * p->rec.npts, 1, p->nt * p->rec.npts, (T)inv_dt2, uf, nullptr, s);
 }
 
 template <typename T>
 Status adjoint_start(Problem* p, hipStream_t s) {
   STTRY(zero_level<T>(p, p->adj, (T*)p->d_lam[(p->nt + 1) & 1], (int)((p->nt + 1) & 1), s));
-  HIPTRY(launch_fill<T>((T*)p->d_lam[p->nt & 1], T(0), p->ls, s));
+  HIPTRY(launch_fill<T>((T*)p->d_lam[p->nt & 1], T(0), p->ls * p->nshot, s));
   return OK;
 }
 
@@ -511,22 +537,23 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
   } else {
     STTRY(run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n & 1); }, traces, true, s));
   }
-  HIPTRY(launch_misfit<T>(traces, obs, (T*)p->d_resid, p->nt * p->rec.npts, p->d_red, p->red_blocks,
-                          p->d_red + p->red_blocks, s));
+  HIPTRY(launch_misfit<T>(traces, obs, (T*)p->d_resid, p->nt * p->rec.npts * p->nshot, p->d_red,
+                          p->red_blocks, p->d_red + p->red_blocks, s));
   STTRY(adjoint_start<T>(p, s));
-  HIPTRY(launch_fill_f64(p->d_gacc, 0.0, N, s));
+  HIPTRY(launch_fill_f64(p->d_gacc, 0.0, N * p->nshot, s));
   const T* resid = (const T*)p->d_resid;
   if (p->store_all) {
     for (int64_t mm = p->nt; mm >= 1; --mm) STTRY(adjoint_launch<T>(p, mm, true, resid, slot_ptr<T>(p, mm), s));
   } else {
-    const size_t lb = (size_t)p->ls * sizeof(T);
-    const size_t ob = (size_t)m.n_own_total * sizeof(T), shb = (size_t)p->nref * sizeof(T);
+    const int64_t ns = p->nshot;
+    const size_t lb = (size_t)(p->ls * ns) * sizeof(T);
+    const size_t ob = (size_t)(m.n_dofs * ns) * sizeof(T), shb = (size_t)(p->rs * ns) * sizeof(T);
     for (int64_t k = p->n_ck - 1; k >= 0; --k) {
       const int64_t s0 = k * p->seg, s1 = std::min(s0 + p->seg, p->nt);
-      const T* cd = (const T*)p->d_ck_du + k * (m.n_own_total + p->nref);
-      HIPTRY(hipMemcpyAsync(slot_ptr<T>(p, 0), (T*)p->d_ck_u + k * p->ls, lb, hipMemcpyDeviceToDevice, s));
+      const T* cd = (const T*)p->d_ck_du + k * (m.n_dofs + p->rs) * ns;
+      HIPTRY(hipMemcpyAsync(slot_ptr<T>(p, 0), (T*)p->d_ck_u + k * p->ls * ns, lb, hipMemcpyDeviceToDevice, s));
       HIPTRY(hipMemcpyAsync(p->fwd.d, cd, ob, hipMemcpyDeviceToDevice, s));
-      if (shb) HIPTRY(hipMemcpyAsync(p->fwd.dsh[s0 & 1], cd + m.n_own_total, shb, hipMemcpyDeviceToDevice, s));
+      HIPTRY(hipMemcpyAsync(p->fwd.dsh[s0 & 1], cd + m.n_dofs * ns, shb, hipMemcpyDeviceToDevice, s));
       STTRY(run_forward<T>(p, s0, s1, [p, s0](int64_t n) { return slot_ptr<T>(p, n - s0); }, (T*)nullptr,
                            false, s));
       for (int64_t mm = s1; mm > s0; --mm)
@@ -534,7 +561,7 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
     }
   }
   STTRY(adjoint_end<T>(p, true, s));
-  HIPTRY(launch_finalize_grad(c, p->d_gacc, 2.0 * p->dt * p->dt, grad, N, s));
+  HIPTRY(launch_finalize_grad(c, p->d_gacc, p->nshot, 2.0 * p->dt * p->dt, grad, N, s));
   double hJ = 0;
   HIPTRY(hipMemcpyAsync(&hJ, p->d_red + p->red_blocks, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPTRY(hipStreamSynchronize(s));
@@ -551,14 +578,19 @@ Status adjoint_t(Problem* p, const double* c, const T* adj, T* lambda_out, T* sr
   STTRY(set_c2<T>(p, c, s));
   STTRY(adjoint_start<T>(p, s));
   if (lambda_out) HIPTRY(launch_fill<T>(lambda_out + p->nt * N, T(0), N, s));
+  // shot sh samples its own sources: points [sh*nps, (sh+1)*nps) of the table
+  const int nps = p->src.npts / p->nshot;
   auto record = [&](int64_t lvl) -> Status {  // level lvl is complete: row lvl-1
     const T* lam = (const T*)p->d_lam[lvl & 1];
     if (lambda_out) HIPTRY(hipMemcpyAsync(lambda_out + (lvl - 1) * N, lam, vb, hipMemcpyDeviceToDevice, s));
     if (src_trace)
-      STTRY(probed(p, 4, s, [&](hipEvent_t e0, hipEvent_t e1) {
-        return launch_sample<T>(lam, p->src.s_dof, (const T*)p->src.s_w, p->src.npts, m.nd,
-                                src_trace + (lvl - 1) * p->src.npts, s, e0, e1);
-      }));
+      for (int sh = 0; sh < p->nshot; ++sh) {
+        const size_t o = (size_t)sh * nps * m.nd;
+        STTRY(probed(p, 4, s, [&](hipEvent_t e0, hipEvent_t e1) {
+          return launch_sample<T>(lam + sh * p->ls, p->src.s_dof + o, (const T*)p->src.s_w + o, nps, m.nd,
+                                  src_trace + (sh * p->nt + lvl - 1) * nps, s, e0, e1);
+        }));
+      }
     return OK;
   };
   for (int64_t mm = p->nt; mm >= 1; --mm) {
@@ -576,6 +608,7 @@ Status apply_t(Problem* p, const double* c, const T* u, T* y, hipStream_t s) {
   StepArgs<T> a = base_args<T>(p);
   a.mode = 1;
   a.prev = 0;
+  a.n_shots = 1;  // one vector
   a.u_in = u;
   a.y_out = y;
   // loaded (not used) by the branch-free prologue: any valid buffers
@@ -594,6 +627,7 @@ Status apply_t(Problem* p, const double* c, const T* u, T* y, hipStream_t s) {
   f.shp_ptr = p->d_shp_ptr;
   f.shp_slot = p->d_shp_slot;
   f.mode = 1;
+  f.n_shots = 1;
   f.part_prev = (const T*)p->fwd.part[0];
   f.y_out = y;
   return probed(p, 2, s,
@@ -665,9 +699,9 @@ void free_sweep(Sweep& S) {
   S = Sweep();
 }
 
-Status alloc_sweep(Sweep& S, const Mesh& m, size_t ts, bool with_r) {
-  const size_t rb = std::max<size_t>(1, m.n_shared_refs) * ts;
-  STTRY(alloc(&S.d, (size_t)m.n_dofs * ts));
+Status alloc_sweep(Sweep& S, const Mesh& m, size_t ts, bool with_r, int nshot) {
+  const size_t rb = std::max<size_t>(1, m.n_shared_refs) * nshot * ts;
+  STTRY(alloc(&S.d, (size_t)m.n_dofs * nshot * ts));
   for (int i = 0; i < 2; ++i) {
     STTRY(alloc(&S.dsh[i], rb));
     STTRY(alloc(&S.part[i], rb));
@@ -721,9 +755,11 @@ Status profile_read(Problem* p, int variant, int64_t* launches, int64_t* timed, 
 }
 
 Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_every, size_t budget,
-                      Problem** out) {
+                      int n_shots, Problem** out) {
   if (prec != KMV_FP64 && prec != KMV_FP32) return Status{KMV_EINVAL, "precision must be KMV_FP64 or KMV_FP32"};
   if (!(dt > 0) || nt <= 0) return Status{KMV_EINVAL, "dt and n_steps must be positive"};
+  if (n_shots < 1 || n_shots > 1024 || (int64_t)n_shots * m->n_patches > INT32_MAX)
+    return Status{KMV_EINVAL, "n_shots must be in 1..1024"};
   if (m->max_patch_cells > 512) return Status{KMV_EINVAL, "patches larger than 512 cells"};
   auto p = new Problem();
   std::unique_ptr<Problem> guard(p);
@@ -737,7 +773,9 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
   HIPTRY(hipGetDevice(&p->device));
   p->block = std::max(64, ((m->max_patch_cells + 63) / 64) * 64);
   p->nref = m->n_shared_refs;
+  p->rs = std::max<int64_t>(1, p->nref);
   p->ls = m->n_dofs + p->nref;
+  p->nshot = n_shots;
   for (bool adjv : {false, true}) {
     const size_t bytes = step_lds_bytes(m->max_nbl, m->slot_stride, m->nb, m->max_glist, adjv, p->ts);
     if (bytes > 160 * 1024) return Status{KMV_EINVAL, "patch LDS footprint above 160 KiB; use smaller patches"};
@@ -797,11 +835,11 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
   const size_t vb = (size_t)m->n_dofs * p->ts;
   STTRY(alloc(&p->d_c2, vb));
   STTRY(alloc(&p->d_c2_ref, std::max<size_t>(1, m->n_shared_refs) * p->ts));
-  STTRY(alloc_sweep(p->fwd, *m, p->ts, false));
-  STTRY(alloc_sweep(p->adj, *m, p->ts, true));
-  STTRY(alloc(&p->d_lam[0], (size_t)p->ls * p->ts));
-  STTRY(alloc(&p->d_lam[1], (size_t)p->ls * p->ts));
-  STTRY(alloc((void**)&p->d_gacc, (size_t)m->n_dofs * 8));
+  STTRY(alloc_sweep(p->fwd, *m, p->ts, false, n_shots));
+  STTRY(alloc_sweep(p->adj, *m, p->ts, true, n_shots));
+  STTRY(alloc(&p->d_lam[0], (size_t)p->ls * n_shots * p->ts));
+  STTRY(alloc(&p->d_lam[1], (size_t)p->ls * n_shots * p->ts));
+  STTRY(alloc((void**)&p->d_gacc, (size_t)m->n_dofs * n_shots * 8));
   STTRY(alloc((void**)&p->d_red, (size_t)(p->red_blocks + 8) * 8));
   *out = guard.release();
   return OK;
@@ -828,8 +866,9 @@ Status set_wavelet(Problem* p, const double* w) {
 Status set_sources(Problem* p, const double* xs, int nsrc, double f0, double t0, double amp) {
   DeviceGuard dg(p->device);
   if (nsrc <= 0 || !xs) return Status{KMV_EINVAL, "need at least one source"};
+  if (nsrc % p->nshot != 0) return Status{KMV_EINVAL, "n_src must be a multiple of n_shots (shot-major)"};
   free_points(p->src);
-  STTRY(build_points(p, xs, nsrc, p->src));
+  STTRY(build_points(p, xs, nsrc, p->nshot, p->src));
   std::vector<double> w(p->nt);
   const double pi = 3.14159265358979323846;
   for (int64_t n = 0; n < p->nt; ++n) {
@@ -845,8 +884,8 @@ Status set_receivers(Problem* p, const double* xr, int nrec) {
   DeviceGuard dg(p->device);
   if (nrec <= 0 || !xr) return Status{KMV_EINVAL, "need at least one receiver"};
   free_points(p->rec);
-  STTRY(build_points(p, xr, nrec, p->rec));
-  const size_t tb = (size_t)p->nt * nrec * p->ts;
+  STTRY(build_points(p, xr, nrec, 1, p->rec));
+  const size_t tb = (size_t)p->nt * nrec * p->nshot * p->ts;
   STTRY(alloc(&p->d_resid, tb));
   STTRY(alloc(&p->d_traces_tmp, tb));
   return OK;
@@ -873,6 +912,7 @@ Status adjoint(Problem* p, const double* c, const void* adj, void* lambda_out, v
   DeviceGuard dg(p->device);
   if (p->rec.npts == 0) return Status{KMV_ESTATE, "receivers must be set first"};
   if (src_trace && !p->has_src) return Status{KMV_ESTATE, "sources must be set to record at them"};
+  if (lambda_out && p->nshot != 1) return Status{KMV_EINVAL, "lambda_out needs a one-shot problem"};
   if (!c || !adj) return Status{KMV_EINVAL, "null device pointer"};
   return p->prec == KMV_FP64
              ? adjoint_t<double>(p, c, (const double*)adj, (double*)lambda_out, (double*)src_trace, s)

@@ -29,7 +29,8 @@ struct AllocStreamScope {
 // for injection and for sampling inside k_step; and global sampling rows (DOF
 // ids and weights) for k_sample.
 struct PointTables {
-  int npts = 0;
+  int npts = 0;                 // all points (shot-major when the table is per shot)
+  int64_t shot_stride = 0;      // np+1 when each shot has its own pp_ptr block, else 0
   int32_t* pp_ptr = nullptr;    // [np+1]
   int32_t* pp_cell = nullptr;   // patch-local cell
   int32_t* pp_pt = nullptr;     // point index
@@ -82,7 +83,13 @@ struct Problem {
   uint32_t* d_gword = nullptr;
   uint16_t* d_glist = nullptr;
   int64_t nref = 0;             // shared refs
+  int64_t rs = 1;               // per-shot length of the per-ref arrays: max(1, nref)
   int64_t ls = 0;               // level vector length: n_dofs + nref (copies per ref)
+  // Shots stepped together.  Every per-shot buffer holds n_shots copies, shot s
+  // at s times the per-shot length (level vectors ls, DOF vectors n_dofs, ref
+  // arrays rs, traces n_steps * n_rec); mesh tables, coefficients, the wavelet
+  // and the receivers are shared.
+  int nshot = 1;
   // coefficients
   std::vector<double> eta;      // host damping (empty = none)
   void* d_gamma = nullptr;
@@ -116,7 +123,7 @@ struct Problem {
 };
 
 Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_every, size_t budget,
-                      Problem** out);
+                      int n_shots, Problem** out);
 Status set_damping(Problem* p, const double* eta);
 Status set_sources(Problem* p, const double* xs, int nsrc, double f0, double t0, double amp);
 Status set_wavelet(Problem* p, const double* w);

@@ -32,7 +32,7 @@ DECLARED = [
     "kmv_mesh_destroy",
     "kmv_problem_create", "kmv_cfl_dt", "kmv_spectral_radius", "kmv_set_damping",
     "kmv_set_sources", "kmv_set_source_wavelet", "kmv_set_receivers", "kmv_forward",
-    "kmv_misfit_gradient", "kmv_adjoint", "kmv_stiffness_apply", "kmv_problem_info",
+    "kmv_misfit_gradient", "kmv_adjoint", "kmv_stiffness_apply", "kmv_problem_info", "kmv_problem_num_shots",
     "kmv_profile_enable", "kmv_profile_read", "kmv_problem_destroy",
     "kmv_server_create", "kmv_server_submit", "kmv_server_poll", "kmv_server_wait",
     "kmv_server_release", "kmv_server_stats", "kmv_server_destroy",
@@ -47,7 +47,7 @@ class KMVError(RuntimeError):
 
 class kmv_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("dt", C.c_double), ("n_steps", C.c_int64),
-                ("checkpoint_every", C.c_int64), ("mem_budget", C.c_size_t)]
+                ("checkpoint_every", C.c_int64), ("mem_budget", C.c_size_t), ("n_shots", C.c_int)]
 
 
 class kmv_request(C.Structure):
@@ -102,6 +102,7 @@ def lib():
         "kmv_misfit_gradient": (C.c_int, [_P, _P, _P, _D, _P, _P, _P]),
         "kmv_adjoint": (C.c_int, [_P, _P, _P, _P, _P, _P]),
         "kmv_stiffness_apply": (C.c_int, [_P, _P, _P, _P, _P]),
+        "kmv_problem_num_shots": (C.c_int, [_P, C.POINTER(C.c_int)]),
         "kmv_problem_info": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int),
                                        C.POINTER(C.c_int), C.POINTER(C.c_int64)]),
         "kmv_profile_enable": (C.c_int, [_P, C.c_int]),
@@ -205,8 +206,8 @@ def kmv_mesh_destroy(m):
     _check(lib().kmv_mesh_destroy(m))
 
 
-def kmv_problem_create(m, precision, dt, n_steps, checkpoint_every=0, mem_budget=0):
-    opt = kmv_options(precision, dt, n_steps, checkpoint_every, mem_budget)
+def kmv_problem_create(m, precision, dt, n_steps, checkpoint_every=0, mem_budget=0, n_shots=1):
+    opt = kmv_options(precision, dt, n_steps, checkpoint_every, mem_budget, n_shots)
     h = _P()
     _check(lib().kmv_problem_create(m, C.byref(opt), C.byref(h)))
     return h
@@ -217,6 +218,12 @@ def kmv_problem_info(p):
     _check(lib().kmv_problem_info(p, *[C.byref(x) for x in v]))
     return dict(n_dofs=v[0].value, n_steps=v[1].value, n_rec=v[2].value, precision=v[3].value,
                 checkpoint_every=v[4].value)
+
+
+def kmv_problem_num_shots(p):
+    n = C.c_int()
+    _check(lib().kmv_problem_num_shots(p, C.byref(n)))
+    return n.value
 
 
 def kmv_cfl_dt(m, c_host):
