@@ -68,8 +68,17 @@ __device__ __forceinline__ T gather_sum(uint32_t w, const T* x, const uint16_t* 
   return y;
 }
 
+// Minimum waves per SIMD asked of the register allocator: 4 (at most 128 VGPRs)
+// for the FP32 forward kernels whose natural allocation lands just above it, so
+// that four workgroups fit per CU when many are queued (several shots).
 template <typename T, int DIM, int ND, bool ADJ>
-__global__ void __launch_bounds__(512) k_step(const StepArgs<T> A0) {
+struct StepWaves {
+  static constexpr int kMin = sizeof(T) == 4 && !ADJ && ((DIM == 2 && ND == 18) || (DIM == 3 && ND == 15)) ? 4 : 1;
+};
+
+template <typename T, int DIM, int ND, bool ADJ>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(StepWaves<T, DIM, ND, ADJ>::kMin)))
+k_step(const StepArgs<T> A0) {
   // XCD-aware work order: the dispatcher deals workgroups round-robin over the 8
   // XCDs (separate L2 caches), so workgroup b runs on XCD b % 8.  Each XCD gets a
   // contiguous run of work items, patch-major: neighbouring patches, which
