@@ -40,20 +40,23 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(variant, n_dofs, n_cells, dim, ts):
-    """Bytes the method must move per launch ('Algorithmic bytes'):
-    per DOF  forward step: read u^n, du^n, c^2, gamma, beta; write u^{n+1}, du^{n+1}
-             adjoint step: the same for lambda, plus read u^m and a float64
-                           read-modify-write of the gradient accumulator
-    per cell compact topology (vertex + edge [+ face] ids, 4 B each) and the
-             symmetric geometry factor |det J| J^-1 J^-T (3 or 6 values)."""
+def algorithmic_bytes(variant, n_dofs, n_cells, dim, ts, shots=1):
+    """Bytes the method must move per launch of `shots` shots on one mesh and model:
+    per DOF and shot  forward step: read u^n, du^n; write u^{n+1}, du^{n+1}
+                      adjoint step: the same for lambda, plus read u^m and a
+                                    float64 read-modify-write of the gradient
+                                    accumulator
+    per DOF           c^2, gamma, beta (shared by the shots)
+    per cell          compact topology (vertex + edge [+ face] ids, 4 B each) and
+                      the symmetric geometry factor |det J| J^-1 J^-T (3 or 6 values)."""
     topo = 4 * (6 if dim == 2 else 14)
     geom = (3 if dim == 2 else 6) * ts
     per_cell = n_cells * (topo + geom)
+    shared = n_dofs * 3 * ts
     if variant == "patch_forward":
-        return n_dofs * 7 * ts + per_cell
+        return shots * n_dofs * 4 * ts + shared + per_cell
     if variant == "patch_adjoint":
-        return n_dofs * (8 * ts + 16) + per_cell
+        return shots * n_dofs * (5 * ts + 16) + shared + per_cell
     raise ValueError(variant)
 
 
@@ -94,7 +97,7 @@ WORKLOADS = ("layered_kmv4", "layered_tet_kmv3")
 
 
 def setup_workload(precision, budget_frac=0.75, window=0, workload="layered_kmv4", checkpoint_every=0,
-                   mesh_cache={}):
+                   mesh_cache={}, problem=True):
     import torch
     from paper_2108_10946_amd import Mesh, Problem
     from synth import configs
@@ -121,6 +124,8 @@ def setup_workload(precision, budget_frac=0.75, window=0, workload="layered_kmv4
     dt, nt = mesh_cache["dt"]
     if window:
         nt = window
+    if not problem:
+        return w, m, None, c_cur, None, dt, nt
     prob = Problem(m, dt, nt, precision=precision, mem_budget=budget, checkpoint_every=checkpoint_every)
     prob.set_damping(eta)
     prob.set_sources(w.sources, f0=w.f0, t0=w.t0, amp=w.amp)
@@ -161,7 +166,7 @@ def time_gpu(precision, steps, warmup, every, window=0, workload="layered_kmv4",
     return out
 
 
-def roofline(res, ts, dim=2):
+def roofline(res, ts, dim=2, shots=1):
     hash_ = kernel_hash()
     best = None
     for variant in ("patch_forward", "patch_adjoint"):
@@ -169,11 +174,12 @@ def roofline(res, ts, dim=2):
         if p["timed"] == 0:
             continue
         total = p["launches"] * p["mean_ms"]
-        b = algorithmic_bytes(variant, res["n_dofs"], res["n_cells"], dim, ts)
+        b = algorithmic_bytes(variant, res["n_dofs"], res["n_cells"], dim, ts, shots)
         achieved = b / (p["mean_ms"] * 1e-3) / 1e9
         r = {"kernel": f"k_step ({variant.split('_')[1]})", "bound": "hbm", "achieved": round(achieved, 1),
              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-             "traffic": traffic_from_profiles(variant, hash_), "algorithmic_bytes": int(b),
+             "traffic": traffic_from_profiles(variant, hash_) if shots == 1 else None,
+             "algorithmic_bytes": int(b),
              "mean_launch_us": round(p["mean_ms"] * 1e3, 3), "launches": p["launches"],
              "timed_launches": p["timed"], "total_ms": total}
         if best is None or total > best["total_ms"]:
@@ -393,6 +399,61 @@ def bench_3d(args):
     print(json.dumps(out), flush=True)
 
 
+def multi_shot_bench(shots=8, every=16):
+    """Several shots of the 40-shot line (x_s = linspace(0.1, 7.9, 40), every fifth
+    one) in one problem: one launch per step advances all of them.  Observed data
+    from the layered model with anomalies, current model the layers only; the whole
+    T = 4 s window; reverse sweep from checkpoints (segments of sqrt(2 N_t) steps),
+    since the stored states of several shots exceed the GPU's memory."""
+    import torch
+    from paper_2108_10946_amd import Problem, kmvwave as K
+    from synth import configs
+    w, m, _, c_cur, _, dt, nt = setup_workload("fp32", workload="layered_kmv4", problem=False)
+    x = m.dof_coords()
+    c_obs = torch.tensor(w.vp_obs(*x.T), dtype=torch.float64, device="cuda")
+    line = np.linspace(0.1, 7.9, 40)
+    pick = line[::40 // shots][:shots]
+    xs = np.stack([[[xx, 0.01]] for xx in pick])
+    free, _ = torch.cuda.mem_get_info()
+    prob = Problem(m, dt, nt, precision="fp32", n_shots=shots, checkpoint_every=-1,
+                   mem_budget=int(free * 0.6))
+    prob.set_damping(w.eta(*x.T))
+    prob.set_sources(xs, f0=w.f0, t0=w.t0, amp=w.amp)
+    prob.set_receivers(w.receivers)
+    t = time.time()
+    obs = prob.forward(c_obs)
+    torch.cuda.synchronize()
+    log(f"multi-shot: observed data for {shots} shots ({time.time() - t:.1f}s)")
+    J, g, _ = prob.misfit_gradient(c_cur, obs)  # warm-up
+    K.kmv_profile_enable(prob.handle, every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, g, _ = prob.misfit_gradient(c_cur, obs)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    prof = {K.PROFILE_VARIANTS[v]: K.kmv_profile_read(prob.handle, v) for v in K.PROFILE_VARIANTS}
+    info = prob.info()
+    prob.close()
+    res = dict(n_dofs=m.n_dofs, n_cells=m.n_cells, prof=prof)
+    roofline(res, 4, shots=shots)
+    value = m.n_dofs * nt * shots / sec
+    log(f"multi-shot: {shots} shots, {sec:.2f} s per misfit+gradient, {value:.4g} DOF-timesteps/s, J={J:.6g}")
+    us = {k: round(v["mean_ms"] * 1e3, 3) for k, v in prof.items()}
+    return {
+        "workload": f"{shots} shots (every fifth of the 40-shot surface line) of the layered KMV4 workload "
+                    "in one problem: one launch per step for all shots, FP32 fields, float64 misfit and "
+                    "gradient summed over the shots, checkpointed reverse sweep",
+        "shots": shots, "value": round(value, 1), "unit": "DOF-timesteps/s",
+        "sec_per_misfit_gradient": round(sec, 3), "n_steps": nt,
+        "checkpoint_every": info["checkpoint_every"], "J": J,
+        "kernel_mean_us": us,
+        "per_shot_step_us": {"forward": round(us["patch_forward"] / shots, 3),
+                             "adjoint": round(us["patch_adjoint"] / shots, 3)},
+        "rooflines": {k: {kk: vv for kk, vv in v.items() if kk != "total_ms"}
+                      for k, v in res.get("rooflines", {}).items()},
+    }
+
+
 def copy_calibration(n_bytes=1 << 30, reps=3):
     """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE
     counters of a profiled run to bytes."""
@@ -421,6 +482,10 @@ def main():
                     help="layered_tet_kmv3: the 3D workload (FP32, checkpointed reverse sweep, "
                          "ALU roofline); not the bench line")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-multi-shot", action="store_true")
+    ap.add_argument("--multi-shot", type=int, default=8, help="shots per problem in the multi-shot leg")
+    ap.add_argument("--multi-shot-only", action="store_true",
+                    help="run only the multi-shot leg and print its object (profiling runs)")
     ap.add_argument("--serving-requests", type=int, default=48)
     ap.add_argument("--serving-scale", type=float, default=0.1,
                     help="request durations are U[1,4] s times this (1.0: the full mix)")
@@ -442,6 +507,9 @@ def main():
     if args.workload == "layered_tet_kmv3":
         bench_3d(args)
         return
+    if args.multi_shot_only:
+        print(json.dumps({"multi_shot": multi_shot_bench(args.multi_shot)}), flush=True)
+        return
     import paper_2108_10946_amd as kmv
     kmv.lib()
 
@@ -452,6 +520,9 @@ def main():
         res64 = time_gpu("fp64", max(1, args.steps // 2), min(1, args.warmup), args.profile_every,
                          args.window)
         roofline(res64, 8)
+    multi = None
+    if not args.no_multi_shot and not args.window:
+        multi = multi_shot_bench(args.multi_shot)
     serving = None
     if not args.no_serving and not args.window:
         serving = serving_bench(n_requests=args.serving_requests, t_scale=args.serving_scale)
@@ -488,6 +559,8 @@ def main():
         "kernel_mean_us": {k: round(v["mean_ms"] * 1e3, 3) for k, v in res32["prof"].items()},
         "cpu_baseline": cpu,
     }
+    if multi:
+        out["multi_shot"] = multi
     if serving:
         out["p50_shot_latency_s"] = serving["fp32_server"]["p50_latency_s"]
         out["p99_shot_latency_s"] = serving["fp32_server"]["p99_latency_s"]

@@ -221,7 +221,10 @@ k_step(const StepArgs<T> A0) {
   // the address arithmetic before it nor move the loads above across it, so every
   // load above is in flight before these are issued, and waiting for the slots
   // costs nothing by then.
+  // (adjoint: also the gradient accumulators of the refs' DOFs, which the first
+  // touching patch updates while finishing them)
   T y0[KH], y1[KH], q0[ADJ ? KH : 1], q1[ADJ ? KH : 1];
+  double gs[ADJ ? KH : 1];
 #pragma unroll
   for (int t = 0; t < KH; ++t) {
     int sx = sl[t].x, sy = sl[t].y;
@@ -232,6 +235,7 @@ k_step(const StepArgs<T> A0) {
     if (ADJ) {
       q0[ADJ ? t : 0] = A.partr_prev[sx];
       q1[ADJ ? t : 0] = A.partr_prev[sy2];
+      gs[ADJ ? t : 0] = A.gacc[gg[t]];
     }
   }
   if (!damped) {
@@ -283,7 +287,7 @@ k_step(const StepArgs<T> A0) {
           rr = T(0);
           for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) rr += A.partr_prev[A.shp_slot[k]];
         }
-        A.gacc[g] += (double)rr;
+        A.gacc[g] = gs[ADJ ? t : 0] + (double)rr;
       }
     }
   }
