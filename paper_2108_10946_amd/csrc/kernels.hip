@@ -35,12 +35,21 @@ __host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) / 16 * 
 // c^2 [and the forward state] of the patch's non-interior DOFs; sx [and sr] the
 // cell-node contributions, slot b*CS + t for node b of cell t plus a zero slot;
 // then the gather lists (uint16).
+// With ovl the slots start right after the level and overlay the c^2 [and u^m]
+// staging, which is dead once every thread has read its element's values (3D:
+// the slot arrays are the largest part, and LDS limits the resident workgroups).
 struct StepLds {
   size_t sx, gl, total;
-  __host__ __device__ StepLds(int LB, int cs, int nb, int glmax, bool adj, size_t ts) {
+  __host__ __device__ StepLds(int LB, int cs, int nb, int glmax, bool adj, size_t ts, bool ovl) {
     const size_t nslot = (size_t)nb * cs + 1;
-    sx = align16((size_t)(adj ? 3 : 2) * LB * ts);
-    gl = sx + align16((adj ? 2 : 1) * nslot * ts);
+    const size_t stage = (size_t)(adj ? 3 : 2) * LB * ts, slots = (adj ? 2 : 1) * nslot * ts;
+    if (ovl) {
+      sx = align16((size_t)LB * ts);
+      gl = align16(sx + slots > stage ? sx + slots : stage);
+    } else {
+      sx = align16(stage);
+      gl = sx + align16(slots);
+    }
     total = gl + align16((size_t)glmax * 2);
   }
 };
@@ -120,7 +129,8 @@ k_step(const StepArgs<T> A0) {
   constexpr int NIa = NI > 0 ? NI : 1, NBa = NB > 0 ? NB : 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int LB = A.nbl_max, CS = A.slot_stride;
-  const StepLds lay(LB, CS, NB, A.glist_max, ADJ, sizeof(T));
+  constexpr bool OVL = DIM == 3;  // slots overlay the c^2 [and u^m] staging
+  const StepLds lay(LB, CS, NB, A.glist_max, ADJ, sizeof(T), OVL);
   T* su = reinterpret_cast<T*>(smem_raw);  // level n of the non-interior DOFs
   T* sc = su + LB;                         // c^2
   T* sf = sc + LB;                         // forward state u^m (ADJ)
@@ -388,15 +398,15 @@ k_step(const StepArgs<T> A0) {
     sc[i] = A.c2[bo0 + i];
     if (ADJ) sf[i] = A.uf[bo0 + i];
   }
-  if (tid == 0) {
+  if (!OVL && tid == 0) {
     sx[NB * CS] = T(0);
     if (ADJ) sr[NB * CS] = T(0);
   }
   __syncthreads();
 
   // ---- per cell: receivers, element stiffness (and pairing), sources, interior DOFs
+  T ue[ND], ce[ND], fe[ADJ ? ND : 1], ye[ND], re[ADJ ? ND : 1];
   if (active) {
-    T ue[ND], ce[ND], fe[ADJ ? ND : 1], ye[ND], re[ADJ ? ND : 1];
 #pragma unroll
     for (int a = 0; a < ND; ++a) {
       const int x = Tab::IDX[a];
@@ -412,6 +422,15 @@ k_step(const StepArgs<T> A0) {
       }
       ye[a] = T(0);
     }
+  }
+  if constexpr (OVL) {
+    __syncthreads();  // the staged c^2 [and u^m] have been read: the slots may overwrite them
+    if (tid == 0) {
+      sx[NB * CS] = T(0);
+      if (ADJ) sr[NB * CS] = T(0);
+    }
+  }
+  if (active) {
     if (A.trace_row != nullptr) {
       for (int r = A.rec_ptr[p]; r < A.rec_ptr[p + 1]; ++r)
         if (A.rec_cell[r] == tid) {
@@ -733,7 +752,7 @@ template <typename T, int DIM, int ND, bool ADJ>
 hipError_t launch_step_t(const StepArgs<T>& a, int np, int block, hipStream_t s, hipEvent_t e0,
                          hipEvent_t e1) {
   const size_t lds =
-      StepLds(a.nbl_max, a.slot_stride, KmvTab<T, DIM, ND>::NB, a.glist_max, ADJ, sizeof(T)).total;
+      StepLds(a.nbl_max, a.slot_stride, KmvTab<T, DIM, ND>::NB, a.glist_max, ADJ, sizeof(T), DIM == 3).total;
   launch_ev(k_step<T, DIM, ND, ADJ>, dim3(np * a.n_shots), dim3(block), (uint32_t)lds, s, e0, e1, a);
   return hipGetLastError();
 }
@@ -758,8 +777,9 @@ hipError_t set_lds_t(int bytes) {
   }
 }  // namespace
 
-size_t step_lds_bytes(int nbl_max, int slot_stride, int nb, int glist_max, bool adjoint, size_t elem_size) {
-  return StepLds(nbl_max, slot_stride, nb, glist_max, adjoint, elem_size).total;
+size_t step_lds_bytes(int dim, int nbl_max, int slot_stride, int nb, int glist_max, bool adjoint,
+                      size_t elem_size) {
+  return StepLds(nbl_max, slot_stride, nb, glist_max, adjoint, elem_size, dim == 3).total;
 }
 
 template <typename T>
