@@ -230,6 +230,10 @@ Mesh* build_mesh(int dim, int degree, const double* coords, int64_t nv, const in
     int P = (int)std::min(4096.0 / (std::max(nonint_per_cell, 1.0) * 1.25), 65536.0 / lds_per_cell);
     P = (P / 64) * 64;
     patch_cells = std::max(64, std::min(256, P));
+    // measured on the GPU: KMV4 triangles step about 4% faster with 224-cell
+    // patches than with 256 (both directions); degrees 2, 3 are flat and 5 is
+    // slower there
+    if (dim == 2 && degree == 4) patch_cells = std::min(patch_cells, 224);
   }
   m->patch_cells = patch_cells;
   std::vector<int64_t> order(ne);
