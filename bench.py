@@ -79,8 +79,10 @@ def algorithmic_flops(variant, n_cells, dim, degree):
     return per_cell * n_cells
 
 
-def traffic_from_profiles(variant, hash_):
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+def traffic_from_profiles(variant, hash_, path=None):
+    """HBM bytes per launch of a kernel variant from the committed counter summary,
+    or None when there is none or it was taken on another version of kernels.hip."""
+    path = path or os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
@@ -88,7 +90,7 @@ def traffic_from_profiles(variant, hash_):
     except Exception:
         return None
     rec = d.get(variant)
-    if not rec or rec.get("kernels_hip_sha") != hash_:
+    if not rec or d.get("kernels_hip_sha") != hash_:
         return None
     return rec.get("bytes_per_launch")
 
