@@ -19,6 +19,10 @@ Plain float64 three-level recursions, written from the paper:
       g_i = 2 c_i dt^2 sum_{n=0}^{N_t-1} sum_{(e,q)->i} w_q|det J_e|
             grad lam^{n+1}(x_eq) . grad u^n(x_eq),
   and the mesh-independent (Riesz) gradient G = M^{-1} g.
+* Gradient subsampling (section on gradient subsampling): the forward state is
+  kept every r steps and the pairing is taken only there, n = m with
+  m = offset (mod r); the sum is scaled by r, so r = 1 is the exact gradient and
+  r > 1 approximates it (a reading: the paper does not state the scale).
 * CFL bound (eq. spectral): dt <= 2 / sqrt(rho(M^{-1}K)), rho by Gershgorin
   discs, plus a seeded power iteration for the actual spectral radius.
 """
@@ -118,10 +122,11 @@ def adjoint(K, M, a, dt, P, y, record=None):
     return out
 
 
-def gradient(disc, c, K, M, a, dt, P, dobs, states):
+def gradient(disc, c, K, M, a, dt, P, dobs, states, r=1, offset=0):
     """Misfit J, dJ/dc (Euclidean) and the traces d, from stored forward states
     u^0..u^nt.  The pairing at reverse step m is (lam^{m+1}, u^m), m = nt..1; the
-    n = 0 term vanishes because u^0 = 0."""
+    n = 0 term vanishes because u^0 = 0.  With r > 1 only the steps with
+    m % r == offset are paired and the sum is multiplied by r."""
     nt = dobs.shape[0]
     d = np.stack([P @ states[n] for n in range(1, nt + 1)])
     J = misfit(d, dobs)
@@ -129,10 +134,11 @@ def gradient(disc, c, K, M, a, dt, P, dobs, states):
     acc = np.zeros(disc.n_dofs)
 
     def record(m, lam_mp1):
-        acc[:] += disc.gradient_pairing(lam_mp1, states[m])
+        if m % r == offset:
+            acc[:] += disc.gradient_pairing(lam_mp1, states[m])
 
     adjoint(K, M, a, dt, P, y, record=record)
-    g = 2.0 * np.asarray(c) * dt * dt * acc
+    g = 2.0 * np.asarray(c) * dt * dt * r * acc
     return J, g, d
 
 
@@ -160,7 +166,7 @@ class Shot:
         return forward(K, M, a, self.dt, self.nt, point_source_load(self.s_vec, self.wavelet),
                        P=self.P, keep_states=keep_states)
 
-    def misfit_gradient(self, c, dobs, eta=None):
+    def misfit_gradient(self, c, dobs, eta=None, r=1, offset=0):
         disc = self.disc
         K = disc.stiffness(c)
         M = disc.lumped_mass()
@@ -168,4 +174,4 @@ class Shot:
         _, states = forward(K, M, a, self.dt, self.nt,
                             point_source_load(self.s_vec, self.wavelet), P=None,
                             keep_states=True)
-        return gradient(disc, c, K, M, a, self.dt, self.P, dobs, states)
+        return gradient(disc, c, K, M, a, self.dt, self.P, dobs, states, r=r, offset=offset)

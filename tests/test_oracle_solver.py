@@ -112,6 +112,45 @@ def test_gradient_central_fd(small):
     assert J0 == 0.0 and np.all(g0 == 0.0)
 
 
+def _grad_case(small):
+    d, c, K, M, dt, eta = small
+    rng = np.random.default_rng(12)
+    rec = rng.random((6, 2)) * 0.8 + 0.1
+    sh = solver.Shot(d, [[0.45, 0.55]], rec, dt, 250, f0=8.0, t0=0.1)
+    c_true = c * (1 + 0.05 * np.sin(3 * d.dof_coords[:, 0]))
+    dobs, _ = sh.forward(c_true, eta)
+    return sh, c, dobs, eta
+
+
+def test_gradient_subsampling_partitions_the_full_gradient(small):
+    """Gradient subsampling (section on gradient subsampling): the r offsets of the
+    pairing steps partition the reverse steps, so the mean of the r subsampled
+    gradients (each scaled by r) is the full gradient, which the central-difference
+    test pins.  A wrong step selection, a dropped step or a wrong scale breaks it."""
+    sh, c, dobs, eta = _grad_case(small)
+    J1, g1, d1 = sh.misfit_gradient(c, dobs, eta)
+    for r in (2, 3, 5):
+        gs = []
+        for o in range(r):
+            J, g, d = sh.misfit_gradient(c, dobs, eta, r=r, offset=o)
+            assert J == J1 and np.array_equal(d, d1)  # the forward and misfit are untouched
+            gs.append(g)
+        assert np.linalg.norm(np.mean(gs, axis=0) - g1) <= 1e-13 * np.linalg.norm(g1)
+        assert np.linalg.norm(gs[0] - g1) > 1e-8 * np.linalg.norm(g1)  # a genuine subsample
+
+
+def test_gradient_subsampling_follows_the_sampling_theorem(small):
+    """The pairing is a product of two wavefields band-limited by the 8 Hz Ricker
+    (about 20 Hz), so about 40 Hz: sampled every r dt it converges to the full sum
+    once r dt is below the 12.5 ms Nyquist interval (dt = 7.1 ms here), and not far
+    above it."""
+    sh, c, dobs, eta = _grad_case(small)
+    _, g1, _ = sh.misfit_gradient(c, dobs, eta)
+    err = {r: np.linalg.norm(sh.misfit_gradient(c, dobs, eta, r=r)[1] - g1) / np.linalg.norm(g1)
+           for r in (2, 3, 5)}
+    assert err[2] < 1e-4 < err[3] < 1e-2 < err[5]
+
+
 def test_gradient_fd_c1():
     """C1 (homogeneous KMV2, 1000 steps): central FD at h = 1e-3 along a seeded
     direction agrees with c~ . g to O(h^2)."""
