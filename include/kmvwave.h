@@ -124,6 +124,13 @@ typedef struct {
                                ceil(sqrt(2 N_t)) steps */
   size_t mem_budget;        /* bytes of device memory for stored states (0 = 8 GiB) */
   int n_shots;              /* shots stepped together (0 or 1 = one; at most 1024) */
+  int64_t gradient_every;   /* r, gradient subsampling (section "Gradient subsampling"):
+                               the reverse sweep pairs lambda^{n+1} with u^n only
+                               for n % r == 0 and scales the sum by r, and with
+                               checkpoint_every = 0 only every r-th forward state
+                               is kept (floor(N_t/r) + 3 levels, no recompute) if
+                               that fits mem_budget.  0 or 1 = every step (the
+                               exact gradient of J). */
 } kmv_options;
 
 /* Allocate device state for n_shots shots on the current device.

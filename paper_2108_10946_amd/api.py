@@ -64,17 +64,20 @@ class Problem:
 
     With n_shots > 1 the shots share wave speed, damping, wavelet and receivers;
     sources are given shot-major, traces and observed data are
-    [n_shots, n_steps, n_rec], and J and the gradient are sums over the shots."""
+    [n_shots, n_steps, n_rec], and J and the gradient are sums over the shots.
+    gradient_every = r > 1 subsamples the gradient pairing (and the stored
+    forward states) every r steps, scaled by r."""
 
     def __init__(self, mesh: Mesh, dt, n_steps, precision="fp64", checkpoint_every=0, mem_budget=0,
-                 n_shots=1):
+                 n_shots=1, gradient_every=1):
         self.mesh = mesh
         self.dt = float(dt)
         self.n_steps = int(n_steps)
         self.n_shots = int(n_shots)
         self.precision = K.KMV_FP32 if precision in ("fp32", K.KMV_FP32) else K.KMV_FP64
+        self.gradient_every = int(gradient_every)
         self.handle = K.kmv_problem_create(mesh.handle, self.precision, self.dt, self.n_steps,
-                                           checkpoint_every, mem_budget, self.n_shots)
+                                           checkpoint_every, mem_budget, self.n_shots, self.gradient_every)
         self.n_rec = 0
         self.n_src = 0
 

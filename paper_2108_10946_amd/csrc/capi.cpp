@@ -131,7 +131,8 @@ int kmv_problem_create(kmv_mesh m, const kmv_options* opt, kmv_problem* out) {
     *out = nullptr;
     kmv::Problem* p = nullptr;
     kmv::Status s = kmv::problem_create(m->m, opt->precision, opt->dt, opt->n_steps, opt->checkpoint_every,
-                                        opt->mem_budget, opt->n_shots > 0 ? opt->n_shots : 1, &p);
+                                        opt->mem_budget, opt->n_shots == 0 ? 1 : opt->n_shots,
+                                        opt->gradient_every == 0 ? 1 : opt->gradient_every, &p);
     if (s.code != KMV_OK) return done(s);
     *out = new kmv_problem_s{p};
     return (int)KMV_OK;
@@ -146,7 +147,7 @@ int kmv_problem_info(kmv_problem h, int64_t* n_dofs, int64_t* n_steps, int* n_re
   if (n_steps) *n_steps = p.nt;
   if (n_rec) *n_rec = p.rec.npts;
   if (precision) *precision = p.prec;
-  if (checkpoint_every) *checkpoint_every = p.store_all ? 0 : p.seg;
+  if (checkpoint_every) *checkpoint_every = p.store_all || p.store_sub ? 0 : p.seg;
   return KMV_OK;
 }
 

@@ -291,7 +291,7 @@ k_step(const StepArgs<T> A0) {
     A.dsh_cur[r] = dn;
     if (sl[t].x == r) {  // the first touching patch stores the level itself
       A.u_in_sh[g] = uu[t];
-      if (ADJ) {
+      if (ADJ && A.pair_prev) {
         T rr = q0[ADJ ? t : 0] + q1[ADJ ? t : 0];
         if (!pair) {
           rr = T(0);
@@ -359,7 +359,7 @@ k_step(const StepArgs<T> A0) {
         A.dsh_cur[r] = dn;
         if (sj.x == r) {
           A.u_in_sh[g] = u;
-          if (ADJ) {
+          if (ADJ && A.pair_prev) {
             T rr = pr0[t] + pr1[t];
             if (!pair) {
               rr = T(0);
@@ -597,6 +597,12 @@ __global__ void __launch_bounds__(256) k_finish(const FinishArgs<T> A0) {
   }
   const int64_t g = A.n_own + s;
   const int k0 = A.shp_ptr[s], k1 = A.shp_ptr[s + 1];
+  if (ADJ && A.mode == 2) {  // pairing partials only
+    T rr = A.partr_prev[A.shp_slot[k0]];
+    for (int k = k0 + 1; k < k1; ++k) rr += A.partr_prev[A.shp_slot[k]];
+    A.gacc[g] += (double)rr;
+    return;
+  }
   // the same fixed order as the step kernel (two patches: first + second)
   T y = A.part_prev[A.shp_slot[k0]];
   for (int k = k0 + 1; k < k1; ++k) y += A.part_prev[A.shp_slot[k]];

@@ -47,6 +47,8 @@ struct StepArgs {
   int nbl_max, slot_stride, glist_max;  // LDS sizing; cell-node slot = b*slot_stride + t
   int mode;                    // 0: leapfrog step, 1: y = K u
   int prev;                    // 1: shared DOFs of this level are finished here
+  int pair_prev;               // adjoint: 1 if the previous launch's pairing partials are finished here
+                               // (0 when a separate pass finishes them, as with gradient subsampling)
   // state (level n -> n+1; the adjoint runs the same recursion backwards).  A
   // level vector holds the n_dofs DOF values, then one copy per shared ref of its
   // DOF's value (index n_dofs + r), kept by the patch of ref r.
@@ -100,7 +102,9 @@ struct StepArgs {
 };
 
 // Finisher: the shared DOFs of a level from the last step's partials (end of a
-// sweep, checkpoints, segment ends), or y = K u for them (mode 1).
+// sweep, checkpoints, segment ends), or y = K u for them (mode 1), or (adjoint,
+// mode 2) only the gradient pairing partials of the last step, added to the
+// accumulators of the shared DOFs.
 template <typename T>
 struct FinishArgs {
   int64_t n_own, n_shared, n_dofs;

@@ -322,6 +322,7 @@ Status step(Problem* p, Sweep& S, bool grad, bool prev, const T* u_in, const T* 
   StepArgs<T> a = base_args<T>(p);
   a.mode = 0;
   a.prev = prev ? 1 : 0;
+  a.pair_prev = grad && p->grad_every == 1 ? 1 : 0;
   a.u_in = u_in;
   a.u_in_sh = const_cast<T*>(u_in);
   a.u_prev = u_prev ? u_prev : u_in;  // never dereferenced as a previous level when !prev
@@ -389,6 +390,27 @@ Status finish(Problem* p, Sweep& S, bool grad, const T* u_prev, T* u_cur, Par q,
   f.ss_ref = p->rs;
   return probed(p, grad ? 3 : 2, s,
                 [&](hipEvent_t e0, hipEvent_t e1) { return launch_finish<T>(grad, f, s, e0, e1); });
+}
+
+// Gradient subsampling: the pairing partials of the shared DOFs written by
+// adjoint launch m (parities q), added to their accumulators right away.
+template <typename T>
+Status pair_finish(Problem* p, Par q, hipStream_t s) {
+  const Mesh& m = *p->mesh;
+  FinishArgs<T> f{};
+  f.n_own = m.n_own_total;
+  f.n_shared = m.n_shared;
+  f.n_dofs = m.n_dofs;
+  f.shp_ptr = p->d_shp_ptr;
+  f.shp_slot = p->d_shp_slot;
+  f.mode = 2;
+  f.partr_prev = (const T*)p->adj.partr[q.step_cur];
+  f.gacc = p->d_gacc;
+  f.n_shots = p->nshot;
+  f.ss_level = p->ls;
+  f.ss_dof = m.n_dofs;
+  f.ss_ref = p->rs;
+  return probed(p, 3, s, [&](hipEvent_t e0, hipEvent_t e1) { return launch_finish<T>(true, f, s, e0, e1); });
 }
 
 Par fwd_par(int64_t n) { return Par{(int)((n + 1) & 1), (int)(n & 1), (int)((n + 1) & 1), (int)(n & 1)}; }
@@ -477,6 +499,17 @@ Status plan_storage(Problem* p) {
   const Mesh& m = *p->mesh;
   const size_t vb = (size_t)p->ls * p->nshot * p->ts;
   const size_t all = (size_t)(p->nt + 1) * vb;
+  p->store_sub = false;
+  if (p->grad_every > 1 && p->ckpt_every == 0) {  // keep every r-th state only
+    const int64_t nsub = p->nt / p->grad_every + 1;
+    if ((size_t)(2 + nsub) * vb <= p->budget) {
+      p->store_all = false;
+      p->store_sub = true;
+      p->seg = p->nt;
+      p->n_ck = 0;
+      return ensure_slots(p, 2 + nsub);
+    }
+  }
   if (p->ckpt_every == 0 && all <= p->budget) {
     p->store_all = true;
     p->seg = p->nt;
@@ -531,9 +564,13 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
   STTRY(plan_storage(p));
   T* traces = traces_out ? traces_out : (T*)p->d_traces_tmp;
   STTRY(set_c2<T>(p, c, s));
-  STTRY(zero_level<T>(p, p->fwd, slot_ptr<T>(p, 0), 0, s));
+  const int64_t r = p->grad_every;
+  auto sub_slot = [p, r](int64_t n) { return n % r == 0 ? slot_ptr<T>(p, 2 + n / r) : slot_ptr<T>(p, n & 1); };
+  STTRY(zero_level<T>(p, p->fwd, p->store_sub ? sub_slot(0) : slot_ptr<T>(p, 0), 0, s));
   if (p->store_all) {
     STTRY(run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n); }, traces, false, s));
+  } else if (p->store_sub) {
+    STTRY(run_forward<T>(p, 0, p->nt, sub_slot, traces, false, s));
   } else {
     STTRY(run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n & 1); }, traces, true, s));
   }
@@ -542,8 +579,18 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
   STTRY(adjoint_start<T>(p, s));
   HIPTRY(launch_fill_f64(p->d_gacc, 0.0, N * p->nshot, s));
   const T* resid = (const T*)p->d_resid;
+  // reverse launch mm pairs lambda^{mm+1} with u^mm when mm % r == 0 (every launch
+  // for r = 1); with r > 1 the shared DOFs' pairing partials are finished at once
+  auto reverse = [&](int64_t mm, const T* uf) -> Status {
+    const bool g = mm % r == 0;
+    STTRY(adjoint_launch<T>(p, mm, g, resid, g ? uf : nullptr, s));
+    if (g && r > 1) STTRY(pair_finish<T>(p, adj_par(mm), s));
+    return OK;
+  };
   if (p->store_all) {
-    for (int64_t mm = p->nt; mm >= 1; --mm) STTRY(adjoint_launch<T>(p, mm, true, resid, slot_ptr<T>(p, mm), s));
+    for (int64_t mm = p->nt; mm >= 1; --mm) STTRY(reverse(mm, slot_ptr<T>(p, mm)));
+  } else if (p->store_sub) {
+    for (int64_t mm = p->nt; mm >= 1; --mm) STTRY(reverse(mm, sub_slot(mm)));
   } else {
     const int64_t ns = p->nshot;
     const size_t lb = (size_t)(p->ls * ns) * sizeof(T);
@@ -556,12 +603,11 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
       HIPTRY(hipMemcpyAsync(p->fwd.dsh[s0 & 1], cd + m.n_dofs * ns, shb, hipMemcpyDeviceToDevice, s));
       STTRY(run_forward<T>(p, s0, s1, [p, s0](int64_t n) { return slot_ptr<T>(p, n - s0); }, (T*)nullptr,
                            false, s));
-      for (int64_t mm = s1; mm > s0; --mm)
-        STTRY(adjoint_launch<T>(p, mm, true, resid, slot_ptr<T>(p, mm - s0), s));
+      for (int64_t mm = s1; mm > s0; --mm) STTRY(reverse(mm, slot_ptr<T>(p, mm - s0)));
     }
   }
-  STTRY(adjoint_end<T>(p, true, s));
-  HIPTRY(launch_finalize_grad(c, p->d_gacc, p->nshot, 2.0 * p->dt * p->dt, grad, N, s));
+  STTRY(adjoint_end<T>(p, r == 1, s));
+  HIPTRY(launch_finalize_grad(c, p->d_gacc, p->nshot, 2.0 * p->dt * p->dt * (double)r, grad, N, s));
   double hJ = 0;
   HIPTRY(hipMemcpyAsync(&hJ, p->d_red + p->red_blocks, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPTRY(hipStreamSynchronize(s));
@@ -755,11 +801,12 @@ Status profile_read(Problem* p, int variant, int64_t* launches, int64_t* timed, 
 }
 
 Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_every, size_t budget,
-                      int n_shots, Problem** out) {
+                      int n_shots, int64_t grad_every, Problem** out) {
   if (prec != KMV_FP64 && prec != KMV_FP32) return Status{KMV_EINVAL, "precision must be KMV_FP64 or KMV_FP32"};
   if (!(dt > 0) || nt <= 0) return Status{KMV_EINVAL, "dt and n_steps must be positive"};
   if (n_shots < 1 || n_shots > 1024 || (int64_t)n_shots * m->n_patches > INT32_MAX)
     return Status{KMV_EINVAL, "n_shots must be in 1..1024"};
+  if (grad_every < 1) return Status{KMV_EINVAL, "gradient_every must be >= 1"};
   if (m->max_patch_cells > 512) return Status{KMV_EINVAL, "patches larger than 512 cells"};
   auto p = new Problem();
   std::unique_ptr<Problem> guard(p);
@@ -776,6 +823,7 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
   p->rs = std::max<int64_t>(1, p->nref);
   p->ls = m->n_dofs + p->nref;
   p->nshot = n_shots;
+  p->grad_every = grad_every;
   for (bool adjv : {false, true}) {
     const size_t bytes = step_lds_bytes(m->dim, m->max_nbl, m->slot_stride, m->nb, m->max_glist, adjv, p->ts);
     if (bytes > 160 * 1024) return Status{KMV_EINVAL, "patch LDS footprint above 160 KiB; use smaller patches"};

@@ -71,6 +71,7 @@ struct Problem {
   double dt = 0;
   int64_t nt = 0;
   int64_t ckpt_every = 0;
+  int64_t grad_every = 1;  // gradient subsampling ratio r: pair (and keep states) every r-th step
   size_t budget = 0;
   int device = 0;
   int block = 64;
@@ -111,6 +112,7 @@ struct Problem {
   void* d_ck_du = nullptr;
   int64_t n_ck = 0, seg = 0;
   bool store_all = false;
+  bool store_sub = false;       // r > 1: slots 0, 1 a ring, slot 2 + n/r holds level n (n % r == 0)
   void* d_resid = nullptr;      // [nt*nrec]
   void* d_traces_tmp = nullptr; // [nt*nrec]
   // sources / receivers
@@ -123,7 +125,7 @@ struct Problem {
 };
 
 Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_every, size_t budget,
-                      int n_shots, Problem** out);
+                      int n_shots, int64_t grad_every, Problem** out);
 Status set_damping(Problem* p, const double* eta);
 Status set_sources(Problem* p, const double* xs, int nsrc, double f0, double t0, double amp);
 Status set_wavelet(Problem* p, const double* w);

@@ -31,7 +31,7 @@ Status run_job(Server* S, Job* j, hipStream_t st) {
   const size_t ts = j->prec == KMV_FP64 ? 8 : 4;
   const size_t N = (size_t)m.n_dofs, rows = (size_t)j->nt * j->nrec;
   Problem* p = nullptr;
-  Status s = problem_create(j->mesh, j->prec, j->dt, j->nt, 0, S->per_job_budget, 1, &p);
+  Status s = problem_create(j->mesh, j->prec, j->dt, j->nt, 0, S->per_job_budget, 1, 1, &p);
   if (s.code != KMV_OK) return s;
   std::unique_ptr<Problem> guard(p);
   void *c_dev = nullptr, *obs = nullptr, *tr = nullptr, *g = nullptr;

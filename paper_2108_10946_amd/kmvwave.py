@@ -47,7 +47,8 @@ class KMVError(RuntimeError):
 
 class kmv_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("dt", C.c_double), ("n_steps", C.c_int64),
-                ("checkpoint_every", C.c_int64), ("mem_budget", C.c_size_t), ("n_shots", C.c_int)]
+                ("checkpoint_every", C.c_int64), ("mem_budget", C.c_size_t), ("n_shots", C.c_int),
+                ("gradient_every", C.c_int64)]
 
 
 class kmv_request(C.Structure):
@@ -206,8 +207,9 @@ def kmv_mesh_destroy(m):
     _check(lib().kmv_mesh_destroy(m))
 
 
-def kmv_problem_create(m, precision, dt, n_steps, checkpoint_every=0, mem_budget=0, n_shots=1):
-    opt = kmv_options(precision, dt, n_steps, checkpoint_every, mem_budget, n_shots)
+def kmv_problem_create(m, precision, dt, n_steps, checkpoint_every=0, mem_budget=0, n_shots=1,
+                       gradient_every=1):
+    opt = kmv_options(precision, dt, n_steps, checkpoint_every, mem_budget, n_shots, gradient_every)
     h = _P()
     _check(lib().kmv_problem_create(m, C.byref(opt), C.byref(h)))
     return h
