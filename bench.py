@@ -483,6 +483,26 @@ def multi_shot_bench(shots=8, every=16, subsample=10):
     }
 
 
+def copy_bandwidth(n_bytes=2 << 30, reps=10):
+    """Achievable HBM bandwidth: a plain device-to-device copy of n_bytes (read +
+    write = 2 n_bytes per copy, far above the 256 MB Infinity Cache), timed with
+    events; the second roofline denominator beside the datasheet 8 TB/s."""
+    import torch
+    a = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n_bytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def copy_calibration(n_bytes=1 << 30, reps=3):
     """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE
     counters of a profiled run to bytes."""
@@ -564,6 +584,12 @@ def main():
 
     N, nt = res32["n_dofs"], res32["nt"]
     value = N * nt / res32["sec"]
+    copy_gbs = copy_bandwidth()
+    log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
+    rls = list(res32.get("rooflines", {}).values()) + (list(multi["rooflines"].values()) if multi else [])
+    for r in rls:
+        r["measured_copy_GBs"] = round(copy_gbs, 1)
+        r["frac_of_measured_copy"] = round(r["achieved"] / copy_gbs, 4)
     out = {
         "metric": METRIC,
         "value": round(value, 1),

@@ -9,10 +9,12 @@ behind a C ABI; this package is the Python binding).
     prob.set_receivers(receivers)
     traces = prob.forward(c)                       # c: float64 cuda tensor, DOF order
     J, grad, traces = prob.misfit_gradient(c, observed)
+    result = invert(library_objective([prob], [observed]), c0, mesh.lumped_mass())  # Algorithm 1
 """
 from .kmvwave import (KMVError, KMV_FP32, KMV_FP64, kmv_element_tables, lib)
 from .api import Mesh, Problem, Server
 from .autograd import FWIMisfit, fwi_misfit
+from .fwi import InversionResult, invert, library_objective
 
-__all__ = ["Mesh", "Problem", "Server", "FWIMisfit", "fwi_misfit", "KMVError", "KMV_FP32", "KMV_FP64",
-           "kmv_element_tables", "lib"]
+__all__ = ["Mesh", "Problem", "Server", "FWIMisfit", "fwi_misfit", "invert", "library_objective",
+           "InversionResult", "KMVError", "KMV_FP32", "KMV_FP64", "kmv_element_tables", "lib"]

@@ -1,0 +1,67 @@
+"""The inversion loop (Algorithm 1, paper_2108_10946_amd/fwi.py) on the CPU, driven by
+the oracle's misfit and gradient: L-BFGS with strong-Wolfe line searches and box
+bounds in the mass inner product, with a fixed water layer."""
+import numpy as np
+import pytest
+
+from oracle.fem import Discretization
+from oracle import solver
+from synth import configs
+
+
+SOURCES = (0.25, 0.5, 0.75)  # x of the three surface shots (z = 0.05 km)
+
+
+def water_case(layout=False):
+    coords, cells = configs.small_tri(6, seed=4)
+    d = Discretization(coords, cells, 2)
+    x, z = d.dof_coords[:, 0], d.dof_coords[:, 1]
+    water = z < 0.15
+    c_true = np.where(water, 1.5, 1.8 + 0.6 * z + 0.25 * np.exp(-((x - 0.5) ** 2 + (z - 0.55) ** 2) / 0.02))
+    c0 = np.where(water, 1.5, 1.8 + 0.6 * z)
+    M = d.lumped_mass()
+    dt = 0.8 * solver.cfl_dt_gershgorin(d.stiffness(c_true), M)
+    rec = np.stack([np.linspace(0.1, 0.9, 12), np.full(12, 0.2)], axis=1)
+    shots = [solver.Shot(d, [[xs, 0.05]], rec, dt, 220, f0=8.0, t0=0.1) for xs in SOURCES]
+    obs = [sh.forward(c_true)[0] for sh in shots]
+
+    def objective(c):
+        J, g = 0.0, np.zeros(d.n_dofs)
+        for sh, o in zip(shots, obs):
+            Js, gs, _ = sh.misfit_gradient(c, o)
+            J += Js
+            g += gs
+        return J, g
+
+    if layout:
+        return d, M, c0, c_true, water, objective, dict(dt=dt, rec=rec, nt=220, f0=8.0, t0=0.1)
+    return d, M, c0, c_true, water, objective
+
+
+def test_inversion_reduces_the_misfit_and_respects_the_constraints():
+    from paper_2108_10946_amd.fwi import invert
+    d, M, c0, c_true, water, objective = water_case()
+    J0, _ = objective(c0)
+    res = invert(objective, c0, M, bounds=(1.0, 2.6), fixed=water, max_iter=8)
+    assert len(res.history) >= 3
+    assert all(b < a for a, b in zip([J0] + res.history, res.history))  # every accepted step reduces J
+    assert res.J < 0.3 * J0
+    assert np.all(res.c >= 1.0 - 1e-12) and np.all(res.c <= 2.6 + 1e-12)
+    assert np.array_equal(res.c[water], c0[water])  # the water layer never moves
+    # the update moves towards the true model where the anomaly is
+    x, z = d.dof_coords[:, 0], d.dof_coords[:, 1]
+    blob = np.exp(-((x - 0.5) ** 2 + (z - 0.55) ** 2) / 0.02) > 0.5
+    assert np.linalg.norm(res.c[blob] - c_true[blob]) < np.linalg.norm(c0[blob] - c_true[blob])
+
+
+def test_bounds_clip_the_start_and_bad_arguments_raise():
+    from paper_2108_10946_amd.fwi import invert
+    d, M, c0, c_true, water, objective = water_case()
+    res = invert(objective, c0, M, bounds=(1.0, 1.9), fixed=water, max_iter=2)
+    assert np.all(res.c[~water] <= 1.9 + 1e-12)
+    with pytest.raises(ValueError):
+        invert(objective, c0, M[:-1])
+    with pytest.raises(ValueError):
+        invert(objective, c0, M, bounds=(2.0, 1.0))
+    with pytest.raises(ValueError):
+        invert(objective, c0, M, fixed=np.ones(len(c0), dtype=bool))
