@@ -52,7 +52,10 @@ enum {
   KMV_EDEGREE = -3,  /* unsupported (dim, degree): tri 1..5, tet 1..3 */
   KMV_EMESH = -4,    /* invalid mesh: vertex index out of range, degenerate cell */
   KMV_EOUTSIDE = -5, /* a source or receiver lies outside every cell */
-  KMV_ECFL = -6,     /* dt above the Gershgorin bound 2/sqrt(rho(M^-1 K)) */
+  KMV_ECFL = -6,     /* reserved: solves do not check dt against c (that needs a
+                        spectral estimate of M^-1 K(c) per solve, see
+                        kmv_cfl_dt and kmv_spectral_radius); an unstable dt shows
+                        up as KMV_ENUMERIC from kmv_misfit_gradient */
   KMV_ENUMERIC = -7, /* non-finite value detected in a result */
   KMV_EDEVICE = -8,  /* HIP runtime error */
   KMV_EBUSY = -9,    /* serving: result not ready yet (not a failure) */
