@@ -290,11 +290,20 @@ def serving_bench(n_requests=48, t_scale=0.1, slots=6, load=0.7, seed=11):
                           eta=d["eta"], observed=o, forward_only=q["fwd"], f0=5.0, t0=0.2)
 
     dof_steps = sum(disc[q["key"]]["mesh"].n_dofs * q["nt"] for q in reqs)
+
+    def collect(srv, tickets, what):  # results in order, with a progress line every 10
+        out = []
+        for i, x in enumerate(tickets):
+            out.append(srv.result(x))
+            if (i + 1) % 10 == 0:
+                log(f"serving {what}: {i + 1}/{len(tickets)} done")
+        return out
+
     # saturation: every request at once
     srv = Server(max_slots=slots)
     t0 = time.perf_counter()
     tk = [submit(srv, q, "fp32") for q in reqs]
-    res_sat = [srv.result(x) for x in tk]
+    res_sat = collect(srv, tk, "saturation")
     t_sat = time.perf_counter() - t0
     srv.close()
     assert all(r["status"] == 0 for r in res_sat), [r.get("error") for r in res_sat if r["status"]]
@@ -312,7 +321,9 @@ def serving_bench(n_requests=48, t_scale=0.1, slots=6, load=0.7, seed=11):
         if wait > 0:
             time.sleep(wait)
         tk.append(submit(srv, q, "fp32"))
-    res = [srv.result(x) for x in tk]
+        if len(tk) % 20 == 0:
+            log(f"serving fp32: {len(tk)}/{n_requests} submitted")
+    res = collect(srv, tk, "fp32")
     srv.close()
     lat = np.array([r["t_done"] - r["t_submit"] for r in res])
     span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
@@ -340,6 +351,8 @@ def serving_bench(n_requests=48, t_scale=0.1, slots=6, load=0.7, seed=11):
         torch.cuda.synchronize()
         pr.close()
         lat64.append(time.perf_counter() - start - ta)
+        if len(lat64) % 10 == 0:
+            log(f"plain fp64: {len(lat64)}/{n_requests} done")
     lat64 = np.array(lat64)
     span64 = time.perf_counter() - start - arrivals[0]
     log(f"plain fp64: p50 {np.median(lat64):.3f}s p99 {np.percentile(lat64, 99):.3f}s, "
