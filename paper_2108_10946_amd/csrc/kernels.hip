@@ -77,12 +77,17 @@ __device__ __forceinline__ T gather_sum(uint32_t w, const T* x, const uint16_t* 
   return y;
 }
 
-// Minimum waves per SIMD asked of the register allocator: 4 (at most 128 VGPRs)
-// for the FP32 forward kernels whose natural allocation lands just above it, so
-// that four workgroups fit per CU when many are queued (several shots).
+// Minimum waves per SIMD asked of the register allocator, for forward kernels
+// whose natural allocation lands just above a step: FP32 KMV4 triangles and KMV2
+// tetrahedra 4 (at most 128 VGPRs), so that four workgroups fit per CU when many
+// are queued (several shots); FP64 KMV4 triangles 3 (at most 168 VGPRs), so that
+// one shot's workgroups are all resident.
 template <typename T, int DIM, int ND, bool ADJ>
 struct StepWaves {
-  static constexpr int kMin = sizeof(T) == 4 && !ADJ && ((DIM == 2 && ND == 18) || (DIM == 3 && ND == 15)) ? 4 : 1;
+  static constexpr int kMin =
+      ADJ ? 1
+          : sizeof(T) == 4 ? ((DIM == 2 && ND == 18) || (DIM == 3 && ND == 15) ? 4 : 1)
+                           : (DIM == 2 && ND == 18 ? 3 : 1);
 };
 
 template <typename T, int DIM, int ND, bool ADJ>
