@@ -38,9 +38,11 @@ __host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) / 16 * 
 // With ovl the slots start right after the level and overlay the c^2 [and u^m]
 // staging, which is dead once every thread has read its element's values (3D:
 // the slot arrays are the largest part, and LDS limits the resident workgroups).
+// With gst (2D adjoints whose occupancy registers limit, not LDS) the float64
+// gradient accumulators of the owned non-interior DOFs follow, at sg.
 struct StepLds {
-  size_t sx, gl, total;
-  __host__ __device__ StepLds(int LB, int cs, int nb, int glmax, bool adj, size_t ts, bool ovl) {
+  size_t sx, gl, sg, total;
+  __host__ __device__ StepLds(int LB, int cs, int nb, int glmax, bool adj, size_t ts, bool ovl, bool gst) {
     const size_t nslot = (size_t)nb * cs + 1;
     const size_t stage = (size_t)(adj ? 3 : 2) * LB * ts, slots = (adj ? 2 : 1) * nslot * ts;
     if (ovl) {
@@ -50,9 +52,20 @@ struct StepLds {
       sx = align16(stage);
       gl = sx + align16(slots);
     }
-    total = gl + align16((size_t)glmax * 2);
+    sg = gl + align16((size_t)glmax * 2);
+    total = sg + (gst ? align16((size_t)LB * 8) : 0);
   }
 };
+
+// Owned non-interior gradient accumulators staged in LDS (see StepLds): FP32 2D
+// adjoints of the elements where it costs no occupancy (KMV1, KMV2, and KMV4 with
+// its register cap below; KMV3 would drop from four waves per SIMD to three, and
+// the FP64 KMV4 adjoint from two workgroups per CU to one, by LDS).
+constexpr bool stage_grad(bool adj, int dim, int nd, size_t ts) {
+  return adj && dim == 2 && ts == 4 && (nd <= 7 || nd == 18);
+}
+template <typename T, bool ADJ, int DIM, int ND>
+constexpr bool kStageGrad = stage_grad(ADJ, DIM, ND, sizeof(T));
 
 // Items per thread whose global loads are issued together (latency hiding).
 template <typename T, bool ADJ = false, int ND = 18, int DIM = 2>
@@ -77,15 +90,15 @@ __device__ __forceinline__ T gather_sum(uint32_t w, const T* x, const uint16_t* 
   return y;
 }
 
-// Minimum waves per SIMD asked of the register allocator, for forward kernels
-// whose natural allocation lands just above a step: FP32 KMV4 triangles and KMV2
-// tetrahedra 4 (at most 128 VGPRs), so that four workgroups fit per CU when many
-// are queued (several shots); FP64 KMV4 triangles 3 (at most 168 VGPRs), so that
-// one shot's workgroups are all resident.
+// Minimum waves per SIMD asked of the register allocator, for kernels whose
+// natural allocation lands just above a step: FP32 KMV4 triangles and KMV2
+// tetrahedra forward 4 (at most 128 VGPRs), so that four workgroups fit per CU
+// when many are queued (several shots); FP64 KMV4 triangles forward and FP32 KMV4
+// triangles adjoint (with its staged accumulators) 3 (at most 168 VGPRs).
 template <typename T, int DIM, int ND, bool ADJ>
 struct StepWaves {
   static constexpr int kMin =
-      ADJ ? 1
+      ADJ ? (sizeof(T) == 4 && DIM == 2 && ND == 18 ? 3 : 1)
           : sizeof(T) == 4 ? ((DIM == 2 && ND == 18) || (DIM == 3 && ND == 15) ? 4 : 1)
                            : (DIM == 2 && ND == 18 ? 3 : 1);
 };
@@ -135,13 +148,15 @@ k_step(const StepArgs<T> A0) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int LB = A.nbl_max, CS = A.slot_stride;
   constexpr bool OVL = DIM == 3;  // slots overlay the c^2 [and u^m] staging
-  const StepLds lay(LB, CS, NB, A.glist_max, ADJ, sizeof(T), OVL);
+  constexpr bool GST = kStageGrad<T, ADJ, DIM, ND>;
+  const StepLds lay(LB, CS, NB, A.glist_max, ADJ, sizeof(T), OVL, GST);
   T* su = reinterpret_cast<T*>(smem_raw);  // level n of the non-interior DOFs
   T* sc = su + LB;                         // c^2
   T* sf = sc + LB;                         // forward state u^m (ADJ)
   T* sx = reinterpret_cast<T*>(smem_raw + lay.sx);  // K u - b per cell node
   T* sr = sx + (NB * CS + 1);                       // gradient pairing per cell node (ADJ)
   uint16_t* gl = reinterpret_cast<uint16_t*>(smem_raw + lay.gl);
+  double* sg = reinterpret_cast<double*>(smem_raw + lay.sg);  // GST: owned accumulators
   const int tid = threadIdx.x, bs = blockDim.x;
   const int c0 = A.cell_start[p], nc = A.cell_start[p + 1] - c0;
   const int own0 = A.own_start[p], bo0 = own0 + NI * nc, nbo = A.own_start[p + 1] - bo0;
@@ -221,12 +236,14 @@ k_step(const StepArgs<T> A0) {
   // owned non-interior DOFs: level, c^2 [, u^m] and the update operands
   constexpr int KO = Batch<T, ADJ, ND>::kOwned;
   T vu[KO], vc[KO], vf[ADJ ? KO : 1], pdu[KO], pg[KO], pb[KO];
+  double pga[GST ? KO : 1];  // their gradient accumulators (staged in LDS below)
 #pragma unroll
   for (int k = 0; k < KO; ++k) {
     const int gx = max(bo0 + min(tid + k * bs, nbo - 1), 0);
     vu[k] = A.u_in[gx];
     vc[k] = A.c2[gx];
     if (ADJ) vf[ADJ ? k : 0] = A.uf[gx];
+    if (GST) pga[GST ? k : 0] = A.gacc[gx];
     pdu[k] = A.du[gx];
     pg[k] = A.gamma[gx];
     pb[k] = bsrc[gx];
@@ -396,12 +413,14 @@ k_step(const StepArgs<T> A0) {
       su[i] = vu[k];
       sc[i] = vc[k];
       if (ADJ) sf[i] = vf[ADJ ? k : 0];
+      if (GST) sg[i] = pga[GST ? k : 0];
     }
   }
   for (int i = tid + KO * bs; i < nbo; i += bs) {
     su[i] = A.u_in[bo0 + i];
     sc[i] = A.c2[bo0 + i];
     if (ADJ) sf[i] = A.uf[bo0 + i];
+    if (GST) sg[i] = A.gacc[bo0 + i];
   }
   if (!OVL && tid == 0) {
     sx[NB * CS] = T(0);
@@ -557,7 +576,10 @@ k_step(const StepArgs<T> A0) {
         }
         A.du[gx] = dn;
         A.u_out[gx] = un + dn;
-        if (ADJ) A.gacc[gx] += (double)r;
+        if (GST)
+          A.gacc[gx] = sg[l] + (double)r;  // staged: no dependent load here
+        else if (ADJ)
+          A.gacc[gx] += (double)r;
       }
     } else {
       produce(l - nbo, y, r);
@@ -575,7 +597,10 @@ k_step(const StepArgs<T> A0) {
         const T dn = (damped ? A.beta[gx] : T(1)) * A.du[gx] - A.gamma[gx] * y;
         A.du[gx] = dn;
         A.u_out[gx] = su[l] + dn;
-        if (ADJ) A.gacc[gx] += (double)r;
+        if (GST)
+          A.gacc[gx] = sg[l] + (double)r;
+        else if (ADJ)
+          A.gacc[gx] += (double)r;
       }
     } else {
       produce(l - nbo, y, r);
@@ -762,8 +787,9 @@ void launch_ev(K kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, hip
 template <typename T, int DIM, int ND, bool ADJ>
 hipError_t launch_step_t(const StepArgs<T>& a, int np, int block, hipStream_t s, hipEvent_t e0,
                          hipEvent_t e1) {
-  const size_t lds =
-      StepLds(a.nbl_max, a.slot_stride, KmvTab<T, DIM, ND>::NB, a.glist_max, ADJ, sizeof(T), DIM == 3).total;
+  const size_t lds = StepLds(a.nbl_max, a.slot_stride, KmvTab<T, DIM, ND>::NB, a.glist_max, ADJ, sizeof(T),
+                             DIM == 3, kStageGrad<T, ADJ, DIM, ND>)
+                          .total;
   launch_ev(k_step<T, DIM, ND, ADJ>, dim3(np * a.n_shots), dim3(block), (uint32_t)lds, s, e0, e1, a);
   return hipGetLastError();
 }
@@ -788,9 +814,10 @@ hipError_t set_lds_t(int bytes) {
   }
 }  // namespace
 
-size_t step_lds_bytes(int dim, int nbl_max, int slot_stride, int nb, int glist_max, bool adjoint,
+size_t step_lds_bytes(int dim, int nd, int nbl_max, int slot_stride, int nb, int glist_max, bool adjoint,
                       size_t elem_size) {
-  return StepLds(nbl_max, slot_stride, nb, glist_max, adjoint, elem_size, dim == 3).total;
+  const bool gst = stage_grad(adjoint, dim, nd, elem_size);
+  return StepLds(nbl_max, slot_stride, nb, glist_max, adjoint, elem_size, dim == 3, gst).total;
 }
 
 template <typename T>

@@ -131,7 +131,7 @@ template <typename T>
 hipError_t launch_step(int dim, int nd, bool adjoint, const StepArgs<T>& a, int n_patches, int block,
                        hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Dynamic LDS bytes of one k_step workgroup.
-size_t step_lds_bytes(int dim, int nbl_max, int slot_stride, int nb, int glist_max, bool adjoint,
+size_t step_lds_bytes(int dim, int nd, int nbl_max, int slot_stride, int nb, int glist_max, bool adjoint,
                       size_t elem_size);
 template <typename T>
 hipError_t launch_finish(bool adjoint, const FinishArgs<T>& a, hipStream_t s, hipEvent_t e0 = nullptr,

@@ -825,7 +825,7 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
   p->nshot = n_shots;
   p->grad_every = grad_every;
   for (bool adjv : {false, true}) {
-    const size_t bytes = step_lds_bytes(m->dim, m->max_nbl, m->slot_stride, m->nb, m->max_glist, adjv, p->ts);
+    const size_t bytes = step_lds_bytes(m->dim, m->nd, m->max_nbl, m->slot_stride, m->nb, m->max_glist, adjv, p->ts);
     if (bytes > 160 * 1024) return Status{KMV_EINVAL, "patch LDS footprint above 160 KiB; use smaller patches"};
     if (bytes > 64 * 1024) {
       if (prec == KMV_FP64)
