@@ -557,9 +557,9 @@ def main():
                     help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); shots shard "
-              "across GPUs with one float64 all-reduce of the gradient, which this build does "
-              "not run", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); shots would shard "
+              "across GPUs with one float64 all-reduce of the gradient, which is not implemented",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
