@@ -74,8 +74,9 @@ struct Batch {
   // element vectors already fill the register file)
   static constexpr int kOwned = sizeof(T) == 4 ? (ND >= 30 ? 2 : 5) : 2;
   static constexpr int kWords = sizeof(T) == 4 ? 6 : 4;   // gather words in registers
-  // shared refs in the first batch (3D patches have several times more)
-  static constexpr int kShared = DIM == 3 && !ADJ ? 4 : 2;
+  // shared refs in the first batch (3D patches have several times more: a 128-cell
+  // KMV3 tetrahedron patch about six per thread)
+  static constexpr int kShared = DIM == 3 && !ADJ ? (ND == 32 ? 6 : 4) : 2;
   static constexpr int kList = 1;                         // 16-byte gather-list words
 };
 
