@@ -240,23 +240,30 @@ typedef struct {
   int64_t n_steps;        /* N_t */
   const double* c;        /* [n_dofs] P-wave speed (host, DOF order) */
   const double* eta;      /* [n_dofs] damping in 1/s, or NULL */
-  const double* xs;       /* [n_src*dim] source positions (Ricker, as kmv_set_sources) */
+  const double* xs;       /* [n_src*dim] source positions (Ricker, as kmv_set_sources;
+                             shot-major when n_shots > 1) */
   int n_src;
   double f0, t0, amp;
   const double* xr;       /* [n_rec*dim] receiver positions */
   int n_rec;
   int forward_only;       /* 1: traces only; 0: misfit, traces and gradient */
-  const void* observed;   /* [n_steps*n_rec] host, element type of the precision */
+  const void* observed;   /* [n_shots*n_steps*n_rec] host, element type of the precision */
+  int n_shots;            /* shots in the request (0 or 1 = one): they share everything but
+                             the sources, which are shot-major (n_src a multiple of
+                             n_shots), and run as one multi-shot problem (one launch per
+                             step for all of them, kmv_options.n_shots); J and grad are
+                             sums over the shots */
 } kmv_request;
 
 typedef struct {
   int status;             /* KMV_OK or the solve's error code (text: kmv_last_error) */
   double J;               /* misfit (0 for forward-only requests) */
-  const void* traces;     /* [n_steps*n_rec] host, element type of the precision */
+  const void* traces;     /* [n_shots*n_steps*n_rec] host, element type of the precision */
   const double* grad;     /* [n_dofs] host dJ/dc, or NULL for forward-only requests */
   int64_t n_steps, n_rec, n_dofs;
   double t_submit, t_admit, t_done;  /* seconds since the server was created */
   size_t device_bytes;    /* device memory reserved for the request while it ran */
+  int64_t n_shots;        /* the request's n_shots (at least 1) */
 } kmv_result;
 
 /* mem_budget: device bytes for requests (0 = 80% of the free memory).  Each

@@ -181,10 +181,13 @@ class Problem:
 
 
 class Server:
-    """Shot server on the current device: requests (one shot each) are admitted
-    in arrival order as slots and device memory free up, and run concurrently,
-    each on its own stream (see kmv_server_create).  Inputs are host arrays; the
-    results come back as host arrays."""
+    """Shot server on the current device: requests are admitted in arrival order
+    as slots and device memory free up, and run concurrently, each on its own
+    stream (see kmv_server_create).  A request is one shot (xs [n_src, dim]) or
+    several sharing the rest (xs [n_shots, n_src, dim], observed and traces
+    [n_shots, n_steps, n_rec], J and grad summed over the shots), which run as one
+    multi-shot problem.  Inputs are host arrays; the results come back as host
+    arrays."""
 
     def __init__(self, mem_budget=0, max_slots=4):
         self.handle = K.kmv_server_create(mem_budget, max_slots)

@@ -1,6 +1,7 @@
-// Shot server.  Requests (one shot each: mesh, wave speed, damping, sources,
-// receivers, time window, observed data) are copied on submission and queued in
-// arrival order.  Each of `slots` worker threads owns a HIP stream; a free worker
+// Shot server.  Requests (one or several shots: mesh, wave speed, damping,
+// sources, receivers, time window, observed data) are copied on submission and
+// queued in arrival order.  The shots of one request run as one multi-shot
+// problem.  Each of `slots` worker threads owns a HIP stream; a free worker
 // admits the request at the head of the queue as soon as its device memory fits
 // in what the running requests leave of the budget, solves it on its stream
 // (forward, or misfit + adjoint + gradient) and stores the results on the host.
@@ -29,9 +30,9 @@ Status run_job(Server* S, Job* j, hipStream_t st) {
   AllocStreamScope scope(st);
   const Mesh& m = *j->mesh;
   const size_t ts = j->prec == KMV_FP64 ? 8 : 4;
-  const size_t N = (size_t)m.n_dofs, rows = (size_t)j->nt * j->nrec;
+  const size_t N = (size_t)m.n_dofs, rows = (size_t)j->nt * j->nrec * j->nshot;
   Problem* p = nullptr;
-  Status s = problem_create(j->mesh, j->prec, j->dt, j->nt, 0, S->per_job_budget, 1, 1, &p);
+  Status s = problem_create(j->mesh, j->prec, j->dt, j->nt, 0, S->per_job_budget, j->nshot, 1, &p);
   if (s.code != KMV_OK) return s;
   std::unique_ptr<Problem> guard(p);
   void *c_dev = nullptr, *obs = nullptr, *tr = nullptr, *g = nullptr;
@@ -134,7 +135,7 @@ void worker(Server* S, int slot) {
 
 double Server::now() const { return seconds_since(epoch); }
 
-size_t job_device_bytes(const Mesh& m, int prec, int64_t nt, int nrec, size_t budget) {
+size_t job_device_bytes(const Mesh& m, int prec, int64_t nt, int nrec, size_t budget, int nshot) {
   const size_t ts = prec == KMV_FP64 ? 8 : 4;
   const size_t N = (size_t)m.n_dofs, ne = (size_t)m.n_cells, np = (size_t)m.n_patches;
   size_t b = 0;
@@ -144,10 +145,13 @@ size_t job_device_bytes(const Mesh& m, int prec, int64_t nt, int nrec, size_t bu
        (m.glist.size() + 8) * 2 + (np + 1) * 8;
   // coefficient vectors (and per-ref copies), sweeps, adjoint levels, gradient accumulator
   const size_t refs = std::max<size_t>(1, (size_t)m.n_shared_refs);
-  b += 4 * N * ts + 3 * refs * ts + 2 * (N + 6 * refs) * ts + 6 * refs * ts + 2 * (N + refs) * ts + N * 8 + 4096;
+  // (the per-shot ones n_shot times)
+  const size_t S = (size_t)std::max(1, nshot);
+  b += 4 * N * ts + 3 * refs * ts + S * (2 * (N + 6 * refs) * ts + 6 * refs * ts + 2 * (N + refs) * ts + N * 8) +
+       4096;
   // state storage (the plan the problem will take under `budget`): level vectors
-  // hold a copy per shared ref after the DOFs
-  const size_t vb = (N + refs) * ts;
+  // hold a copy per shared ref after the DOFs, one per shot
+  const size_t vb = (N + refs) * ts * S;
   if ((size_t)(nt + 1) * vb <= budget) {
     b += (size_t)(nt + 1) * vb;
   } else {
@@ -156,8 +160,8 @@ size_t job_device_bytes(const Mesh& m, int prec, int64_t nt, int nrec, size_t bu
     b += (size_t)(seg + 1) * vb + 2 * (size_t)nck * vb;
   }
   // traces, residual, wavelet, point tables; request buffers
-  const size_t rows = (size_t)nt * nrec;
-  b += 2 * rows * ts + (size_t)nt * ts + (size_t)(nrec + 8) * m.nd * 16;
+  const size_t rows = (size_t)nt * nrec * S;
+  b += 2 * rows * ts + (size_t)nt * ts + (size_t)(nrec + 8 * S) * m.nd * 16 + S * (np + 1) * 4;
   b += 2 * N * 8 + 2 * rows * ts;
   // allocation granularity
   return b + (b >> 4) + ((size_t)4 << 20);
@@ -203,6 +207,9 @@ Status server_submit(Server* S, Mesh* m, const kmv_request* q, uint64_t* ticket)
   if (!q->c || !q->xs || q->n_src <= 0 || !q->xr || q->n_rec <= 0)
     return Status{KMV_EINVAL, "wave speed, sources and receivers are required"};
   if (!q->forward_only && !q->observed) return Status{KMV_EINVAL, "observed data required"};
+  const int nshot = q->n_shots == 0 ? 1 : q->n_shots;
+  if (nshot < 1 || nshot > 1024) return Status{KMV_EINVAL, "n_shots must be in 1..1024"};
+  if (q->n_src % nshot != 0) return Status{KMV_EINVAL, "n_src must be a multiple of n_shots (shot-major)"};
   std::unique_ptr<Job> j(new Job());
   j->mesh = m;
   j->prec = q->precision;
@@ -211,6 +218,7 @@ Status server_submit(Server* S, Mesh* m, const kmv_request* q, uint64_t* ticket)
   j->nt = q->n_steps;
   j->nsrc = q->n_src;
   j->nrec = q->n_rec;
+  j->nshot = nshot;
   j->f0 = q->f0;
   j->t0 = q->t0;
   j->amp = q->amp;
@@ -221,10 +229,10 @@ Status server_submit(Server* S, Mesh* m, const kmv_request* q, uint64_t* ticket)
   j->xr.assign(q->xr, q->xr + (size_t)q->n_rec * m->dim);
   if (!j->forward_only) {
     const unsigned char* o = static_cast<const unsigned char*>(q->observed);
-    j->observed.assign(o, o + (size_t)q->n_steps * q->n_rec * ts);
+    j->observed.assign(o, o + (size_t)q->n_steps * q->n_rec * nshot * ts);
   }
   std::lock_guard<std::mutex> lk(S->mu);
-  j->need = job_device_bytes(*m, j->prec, j->nt, j->nrec, S->per_job_budget);
+  j->need = job_device_bytes(*m, j->prec, j->nt, j->nrec, S->per_job_budget, nshot);
   if (j->need > S->budget)
     return Status{KMV_ENOMEM, "request needs " + std::to_string(j->need) + " device bytes, budget is " +
                                   std::to_string(S->budget)};
@@ -246,6 +254,7 @@ void fill_result(const Job& j, kmv_result* out) {
   out->grad = j.grad.empty() ? nullptr : j.grad.data();
   out->n_steps = j.nt;
   out->n_rec = j.nrec;
+  out->n_shots = j.nshot;
   out->n_dofs = j.mesh->n_dofs;
   out->t_submit = j.t_submit;
   out->t_admit = j.t_admit;

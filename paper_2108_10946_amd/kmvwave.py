@@ -56,14 +56,14 @@ class kmv_request(C.Structure):
                 ("c", C.POINTER(C.c_double)), ("eta", C.POINTER(C.c_double)), ("xs", C.POINTER(C.c_double)),
                 ("n_src", C.c_int), ("f0", C.c_double), ("t0", C.c_double), ("amp", C.c_double),
                 ("xr", C.POINTER(C.c_double)), ("n_rec", C.c_int), ("forward_only", C.c_int),
-                ("observed", C.c_void_p)]
+                ("observed", C.c_void_p), ("n_shots", C.c_int)]
 
 
 class kmv_result(C.Structure):
     _fields_ = [("status", C.c_int), ("J", C.c_double), ("traces", C.c_void_p),
                 ("grad", C.POINTER(C.c_double)), ("n_steps", C.c_int64), ("n_rec", C.c_int64),
                 ("n_dofs", C.c_int64), ("t_submit", C.c_double), ("t_admit", C.c_double),
-                ("t_done", C.c_double), ("device_bytes", C.c_size_t)]
+                ("t_done", C.c_double), ("device_bytes", C.c_size_t), ("n_shots", C.c_int64)]
 
 
 _lib = None
@@ -315,35 +315,40 @@ def kmv_server_create(mem_budget=0, max_slots=4):
 
 def kmv_server_submit(s, mesh, precision, dt, n_steps, c, xs, xr, f0, t0, amp=1.0, eta=None,
                       observed=None, forward_only=False):
-    """Queue one shot.  Host inputs are copied before this returns."""
+    """Queue one request.  xs is [n_src, dim] for one shot or [n_shots, n_src, dim]
+    for several (observed then [n_shots, n_steps, n_rec]).  Host inputs are copied
+    before this returns."""
     c = np.ascontiguousarray(c, dtype=np.float64)
-    xs = np.ascontiguousarray(np.atleast_2d(xs), dtype=np.float64)
+    xs = np.asarray(xs, dtype=np.float64)
+    n_shots = xs.shape[0] if xs.ndim == 3 else 1
+    xs = np.ascontiguousarray(xs.reshape(-1, xs.shape[-1]) if xs.ndim == 3 else np.atleast_2d(xs))
     xr = np.ascontiguousarray(np.atleast_2d(xr), dtype=np.float64)
     eta = None if eta is None else np.ascontiguousarray(eta, dtype=np.float64)
     obs = None
     if not forward_only:
         obs = np.ascontiguousarray(observed, dtype=np.float64 if precision == KMV_FP64 else np.float32)
-        if obs.size != n_steps * len(xr):
-            raise ValueError("observed must hold n_steps * n_rec values")
+        if obs.size != n_shots * n_steps * len(xr):
+            raise ValueError("observed must hold n_shots * n_steps * n_rec values")
     req = kmv_request(mesh, precision, dt, n_steps, _dptr(c), None if eta is None else _dptr(eta), _dptr(xs),
                       len(xs), f0, t0, amp, _dptr(xr), len(xr), 1 if forward_only else 0,
-                      None if obs is None else obs.ctypes.data_as(C.c_void_p))
+                      None if obs is None else obs.ctypes.data_as(C.c_void_p), n_shots)
     t = C.c_uint64()
     _check(lib().kmv_server_submit(s, C.byref(req), C.byref(t)))
     return t.value
 
 
 def _result_dict(r, precision_hint=None):
-    out = dict(status=r.status, J=r.J, n_steps=r.n_steps, n_rec=r.n_rec, n_dofs=r.n_dofs,
+    out = dict(status=r.status, J=r.J, n_steps=r.n_steps, n_rec=r.n_rec, n_dofs=r.n_dofs, n_shots=r.n_shots,
                t_submit=r.t_submit, t_admit=r.t_admit, t_done=r.t_done, device_bytes=r.device_bytes,
                traces=None, grad=None)
     if r.status == KMV_OK:
-        n = r.n_steps * r.n_rec
+        n = r.n_shots * r.n_steps * r.n_rec
+        shape = (r.n_steps, r.n_rec) if r.n_shots == 1 else (r.n_shots, r.n_steps, r.n_rec)
         if r.traces:
             ct = C.c_double if precision_hint == KMV_FP64 else C.c_float
             buf = (ct * n).from_address(r.traces)
             out["traces"] = np.array(np.frombuffer(buf, dtype=np.float64 if ct is C.c_double else np.float32),
-                                     copy=True).reshape(r.n_steps, r.n_rec)
+                                     copy=True).reshape(shape)
         if r.grad:
             out["grad"] = np.array(np.ctypeslib.as_array(r.grad, shape=(r.n_dofs,)), copy=True)
     else:

@@ -174,3 +174,68 @@ def test_bad_request_reports_error():
             srv2.submit(**{**reqs[1], "observed": np.zeros(3), "forward_only": False})
         finally:
             srv2.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_multi_shot_request(prec):
+    """A request with three shots runs as one multi-shot problem: its traces are
+    bitwise those of the three one-shot requests, J and the gradient their sums up
+    to float64 rounding of the sum (1e-12 relative), and everything is bitwise what
+    the multi-shot Problem call gives.  FP64 also matches the oracle (1e-10)."""
+    from paper_2108_10946_amd import Mesh, Problem, Server
+    from paper_2108_10946_amd import kmvwave as K
+    coords, cells = configs.small_tri(8, seed=1)
+    k, nt, nrec = 3, 200, 7
+    d = Discretization(coords, cells, k)
+    c_true = d.nodal_values(lambda x, z: 1.5 + 0.4 * z + 0.1 * np.sin(6 * x))
+    c0 = d.nodal_values(lambda x, z: 1.5 + 0.4 * z)
+    eta = d.nodal_values(lambda x, z: sponge_eta(x, z, 0.0, 1.0, 0.8, 0.2, c_max=2.5))
+    dt = 0.8 * solver.cfl_dt_gershgorin(d.stiffness(c_true), d.lumped_mass())
+    xs = np.array([[[0.25, 0.1]], [[0.5, 0.12]], [[0.75, 0.1]]])
+    rec = np.stack([np.linspace(0.1, 0.9, nrec), np.full(nrec, 0.2)], axis=1)
+    J_or, g_or, tr_or, obs = 0.0, np.zeros(d.n_dofs), [], []
+    for s in range(3):
+        sh = solver.Shot(d, xs[s], rec, dt, nt, f0=8.0, t0=0.1)
+        dobs, _ = sh.forward(c_true, eta)
+        J, g, tr = sh.misfit_gradient(c0, dobs, eta)
+        J_or, g_or = J_or + J, g_or + g
+        tr_or.append(tr)
+        obs.append(dobs)
+    obs = np.stack(obs)
+    m = Mesh(coords, cells, k, patch_cells=13)
+    p = dof_map(m.dof_coords(), d.dof_coords)
+    q = dict(dt=dt, n_steps=nt, precision=prec, eta=eta[p], f0=8.0, t0=0.1)
+    say(f"serving: three-shot request {prec}")
+    srv = Server(max_slots=4)
+    t_multi = srv.submit(m, c0[p], xs, rec, observed=obs, **q)
+    t_single = [srv.submit(m, c0[p], xs[s], rec, observed=obs[s], **q) for s in range(3)]
+    r = srv.result(t_multi)
+    singles = [srv.result(t) for t in t_single]
+    c_h, xs_h, xr_h = np.ascontiguousarray(c0[p]), np.ascontiguousarray(xs.reshape(-1, 2)), np.ascontiguousarray(rec)
+    with pytest.raises(K.KMVError) as e:  # sources not a whole number per shot
+        req = K.kmv_request(m.handle, K.KMV_FP64, dt, nt, K._dptr(c_h), None, K._dptr(xs_h), 3, 8.0, 0.1, 1.0,
+                            K._dptr(xr_h), nrec, 1, None, 2)
+        t = K.C.c_uint64()
+        K._check(K.lib().kmv_server_submit(srv.handle, K.C.byref(req), K.C.byref(t)))
+    assert e.value.code == K.KMV_EINVAL
+    srv.close()
+    assert r["status"] == 0 and r["n_shots"] == 3 and r["traces"].shape == (3, nt, nrec)
+    for s in range(3):
+        assert singles[s]["n_shots"] == 1
+        assert np.array_equal(r["traces"][s], singles[s]["traces"])
+    assert abs(r["J"] - sum(x["J"] for x in singles)) < 1e-12 * r["J"]
+    assert rel_l2(r["grad"], sum(x["grad"] for x in singles)) < 1e-12
+    prob = Problem(m, dt, nt, precision=prec, n_shots=3)
+    prob.set_damping(eta[p])
+    prob.set_sources(xs, f0=8.0, t0=0.1)
+    prob.set_receivers(rec)
+    Jd, gd, trd = prob.misfit_gradient(torch.as_tensor(c0[p], device="cuda"),
+                                       torch.as_tensor(obs, dtype=prob.dtype, device="cuda"), keep_traces=True)
+    prob.close()
+    assert Jd == r["J"]
+    assert np.array_equal(gd.cpu().numpy(), r["grad"])
+    assert np.array_equal(trd.cpu().numpy(), r["traces"])
+    if prec == "fp64":
+        assert abs(r["J"] - J_or) < 1e-10 * J_or
+        assert rel_l2(r["traces"], np.stack(tr_or)) < 1e-10
+        assert rel_l2(r["grad"], g_or[p]) < 1e-10
