@@ -10,8 +10,9 @@ three-level recursions of the paper in float64.
 Modules
   elements  KMV reference elements (nodes, weights, nodal basis, gradients).
   fem       mesh geometry, DOF numbering, lumped mass, assembled stiffness,
-            point interpolation, gradient pairing.
-  solver    Ricker wavelet, CFL bounds, forward, adjoint, gradient, misfit.
+            point interpolation, gradient pairing, boundary mass.
+  solver    Ricker wavelet, CFL bounds, forward, adjoint, gradient, misfit,
+            absorbing boundary damping and its gradient term.
   green     closed-form 2D homogeneous solution used as an accuracy pin.
 
 Parity status: every function is pinned by tests in ``tests/test_oracle_*.py``

@@ -13,7 +13,11 @@ infrastructure only.  Plain float64 NumPy/SciPy, written from the definitions:
 * point interpolation / Dirac injection with weights phi_a(xi) in the containing
   cell (section "Receivers and sources");
 * gradient pairing sum_{(e,q)->i} w_q |det J_e| grad lam(x_eq).grad u(x_eq), the
-  integrand of eq. gradient3 at the quadrature nodes.
+  integrand of eq. gradient3 at the quadrature nodes;
+* boundary mass b_i = integral over the mesh boundary of phi_i, the row sums of the
+  boundary integral of c phi_i phi_j in the damping matrix M_{u,1} (appendix, with c
+  taken at node i), by Gauss quadrature of the trace of the cell basis on every
+  facet that belongs to one cell only.
 """
 from __future__ import annotations
 
@@ -139,6 +143,43 @@ class Discretization:
         cols = self.cell_dofs[cell].ravel()
         P = sps.coo_matrix((vals.ravel(), (rows, cols)), shape=(len(cell), self.n_dofs))
         return P.tocsr()
+
+    def boundary_mass(self, n_gauss=8):
+        """b_i = integral over the boundary of phi_i (zero off the boundary).
+
+        A facet (d vertices) on the boundary belongs to one cell; on it the cell's
+        basis is integrated with an n_gauss-point Gauss-Legendre rule on an edge, or
+        the collapsed (Duffy) n_gauss^2 product rule on a triangle."""
+        d = self.dim
+        x, w = np.polynomial.legendre.leggauss(n_gauss)
+        x, w = (x + 1.0) / 2.0, w / 2.0
+        if d == 2:   # facet barycentrics (1-t, t), weights summing to 1
+            fb = np.stack([1.0 - x, x], axis=1)
+            fw = w
+        else:        # (s, r) = (x_i, (1-x_i) x_j) covers the triangle; weights sum to 1
+            s = np.repeat(x, n_gauss)
+            r = (1.0 - s) * np.tile(x, n_gauss)
+            fb = np.stack([1.0 - s - r, s, r], axis=1)
+            fw = 2.0 * np.repeat(w, n_gauss) * np.tile(w, n_gauss) * (1.0 - s)
+        owners = {}
+        for e, cell in enumerate(self.cells):
+            for v in range(d + 1):
+                owners.setdefault(tuple(sorted(np.delete(cell, v))), []).append((e, v))
+        b = np.zeros(self.n_dofs)
+        for key, own in owners.items():
+            if len(own) != 1:
+                continue
+            e, v = own[0]
+            V = self.coords[np.delete(self.cells[e], v)]          # facet vertices [d, d]
+            if d == 2:
+                measure = np.linalg.norm(V[1] - V[0])
+            else:
+                measure = 0.5 * np.linalg.norm(np.cross(V[1] - V[0], V[2] - V[0]))
+            X = fb @ V                                             # physical points
+            xi = (X - self.coords[self.cells[e, 0]]) @ self.Jinv[e].T
+            vals, _ = self.elem.tabulate(xi)
+            np.add.at(b, self.cell_dofs[e], measure * (fw @ vals))
+        return b
 
     def nodal_values(self, fn):
         """Evaluate a function of point coordinates at the DOF coordinates."""

@@ -23,6 +23,17 @@ Plain float64 three-level recursions, written from the paper:
   kept every r steps and the pairing is taken only there, n = m with
   m = offset (mod r); the sum is scaled by r, so r = 1 is the exact gradient and
   r > 1 approximates it (a reading: the paper does not state the scale).
+* Absorbing boundary (the first-order condition du/dt + c du/dn = 0 on the outer
+  boundary, whose weak form adds the boundary integral of c phi_i phi_j to the
+  damping matrix M_{u,1} of the appendix): lumped by rows with c taken at node i it
+  is diag(c_i b_i), b_i = the boundary integral of phi_i, and the scheme above holds
+  with a = eta dt / 2 + dt c b / (2 M).  Because that damping depends on c, the
+  derivative of J gains a boundary term.  Writing the scheme as
+  M (u^{n+1} - 2u^n + u^{n-1})/dt^2 + D (u^{n+1} - u^{n-1})/(2dt) + K u^n = b^n with
+  D = diag(eta M + c b), the multiplier of its n-th row is -dt^2 lam^{n+1}, so
+      dJ/dc_i += (dt b_i / 2) sum_{n=0}^{N_t-1} lam_i^{n+1} (u_i^{n+1} - u_i^{n-1})
+               = (dt b_i / 2) sum_{n=1}^{N_t} lam_i^n (u_i^n - u_i^{n-2})
+  (u^{-1} = u^0 = 0).  It is taken at every step, also with gradient subsampling.
 * CFL bound (eq. spectral): dt <= 2 / sqrt(rho(M^{-1}K)), rho by Gershgorin
   discs, plus a seeded power iteration for the actual spectral radius.
 """
@@ -122,11 +133,12 @@ def adjoint(K, M, a, dt, P, y, record=None):
     return out
 
 
-def gradient(disc, c, K, M, a, dt, P, dobs, states, r=1, offset=0):
+def gradient(disc, c, K, M, a, dt, P, dobs, states, r=1, offset=0, bmass=None):
     """Misfit J, dJ/dc (Euclidean) and the traces d, from stored forward states
     u^0..u^nt.  The pairing at reverse step m is (lam^{m+1}, u^m), m = nt..1; the
     n = 0 term vanishes because u^0 = 0.  With r > 1 only the steps with
-    m % r == offset are paired and the sum is multiplied by r."""
+    m % r == offset are paired and the sum is multiplied by r.  bmass: the
+    boundary mass b when the absorbing boundary is on (its term is added)."""
     nt = dobs.shape[0]
     d = np.stack([P @ states[n] for n in range(1, nt + 1)])
     J = misfit(d, dobs)
@@ -137,8 +149,13 @@ def gradient(disc, c, K, M, a, dt, P, dobs, states, r=1, offset=0):
         if m % r == offset:
             acc[:] += disc.gradient_pairing(lam_mp1, states[m])
 
-    adjoint(K, M, a, dt, P, y, record=record)
+    lam = adjoint(K, M, a, dt, P, y, record=record)  # lam[m-1] = lam^m
     g = 2.0 * np.asarray(c) * dt * dt * r * acc
+    if bmass is not None:
+        bt = np.zeros(disc.n_dofs)
+        for n in range(1, nt + 1):
+            bt += lam[n - 1] * (states[n] - (states[n - 2] if n >= 2 else 0.0))
+        g = g + 0.5 * dt * np.asarray(bmass) * bt
     return J, g, d
 
 
@@ -158,20 +175,29 @@ class Shot:
             wavelet = ricker(np.arange(nt) * dt, f0, t0, amp)
         self.wavelet = np.asarray(wavelet, dtype=np.float64)
 
-    def forward(self, c, eta=None, keep_states=False):
+    def damping(self, c, M, eta, absorb):
+        """a = eta dt / 2, plus dt c b / (2 M) with the absorbing boundary."""
+        a = None if eta is None else np.asarray(eta) * self.dt / 2.0
+        if absorb:
+            ab = self.dt * np.asarray(c) * self.disc.boundary_mass() / (2.0 * M)
+            a = ab if a is None else a + ab
+        return a
+
+    def forward(self, c, eta=None, keep_states=False, absorb=False):
         disc = self.disc
         K = disc.stiffness(c)
         M = disc.lumped_mass()
-        a = None if eta is None else np.asarray(eta) * self.dt / 2.0
+        a = self.damping(c, M, eta, absorb)
         return forward(K, M, a, self.dt, self.nt, point_source_load(self.s_vec, self.wavelet),
                        P=self.P, keep_states=keep_states)
 
-    def misfit_gradient(self, c, dobs, eta=None, r=1, offset=0):
+    def misfit_gradient(self, c, dobs, eta=None, r=1, offset=0, absorb=False):
         disc = self.disc
         K = disc.stiffness(c)
         M = disc.lumped_mass()
-        a = None if eta is None else np.asarray(eta) * self.dt / 2.0
+        a = self.damping(c, M, eta, absorb)
         _, states = forward(K, M, a, self.dt, self.nt,
                             point_source_load(self.s_vec, self.wavelet), P=None,
                             keep_states=True)
-        return gradient(disc, c, K, M, a, self.dt, self.P, dobs, states, r=r, offset=offset)
+        return gradient(disc, c, K, M, a, self.dt, self.P, dobs, states, r=r, offset=offset,
+                        bmass=disc.boundary_mass() if absorb else None)
