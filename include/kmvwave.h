@@ -161,6 +161,18 @@ int kmv_spectral_radius(kmv_problem p, const void* c_dev, int iters, uint64_t se
 /* Damping eta [n_dofs] in 1/s (host, DOF order; NULL = none).  The step uses
  * a = eta*dt/2 as the pointwise tr(Psi_1) term of eq. forward3. */
 int kmv_set_damping(kmv_problem p, const double* eta);
+/* First-order absorbing boundary (the condition du/dt + c du/dn = 0 on the outer
+ * boundary of the forward problem; its weak form is the boundary integral of
+ * c phi_i phi_j in the damping matrix M_{u,1} of the appendix).  enable = 1 turns
+ * it on for every boundary facet of the mesh (facets of one cell only), 0 off (the
+ * default: homogeneous Neumann).  Lumped by rows with c at node i it adds
+ * dt c_i b_i / (2 M_i) to a_i, b_i = the boundary integral of phi_i, so the damping
+ * of the boundary DOFs follows the c of each solve, and kmv_misfit_gradient adds
+ * the matching term (dt b_i / 2) sum_n lambda_i^n (u_i^n - u_i^{n-2}) to dJ/dc_i
+ * (at every step, also with gradient_every > 1).  The gradient keeps u^n and
+ * lambda^n at the boundary DOFs of every level: 2 n_shots (n_steps+1) n_bnd
+ * elements of device memory.  Errors: KMV_EINVAL. */
+int kmv_set_absorbing_boundary(kmv_problem p, int enable);
 /* Point sources x_s [n_src*dim] firing together with a Ricker wavelet
  * w(t) = amp (1 - 2 pi^2 f0^2 (t-t0)^2) exp(-pi^2 f0^2 (t-t0)^2) sampled at
  * t_n = n dt; injected as w(t_n) phi_a(x_s) (section "Receivers and sources").

@@ -98,6 +98,11 @@ class Problem:
     def set_damping(self, eta):
         K.kmv_set_damping(self.handle, eta)
 
+    def set_absorbing_boundary(self, enable=True):
+        """First-order absorbing boundary on every boundary facet (du/dt + c du/dn = 0),
+        with its term in the gradient; off by default (homogeneous Neumann)."""
+        K.kmv_set_absorbing_boundary(self.handle, enable)
+
     def set_sources(self, xs, f0=5.0, t0=None, amp=1.0):
         xs = np.asarray(xs, dtype=np.float64)
         xs = xs.reshape(-1, xs.shape[-1]) if xs.ndim == 3 else np.atleast_2d(xs)  # [n_shots, n, dim] or flat

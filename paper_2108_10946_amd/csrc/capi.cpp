@@ -191,6 +191,14 @@ int kmv_set_damping(kmv_problem h, const double* eta) {
   });
 }
 
+int kmv_set_absorbing_boundary(kmv_problem h, int enable) {
+  return guarded([&]() {
+    if (!h) return fail(KMV_EINVAL, "problem is NULL");
+    if (enable != 0 && enable != 1) return fail(KMV_EINVAL, "enable must be 0 or 1");
+    return done(kmv::set_absorbing_boundary(h->p, enable == 1));
+  });
+}
+
 int kmv_set_sources(kmv_problem h, const double* xs, int n_src, double f0, double t0, double amp) {
   return guarded([&]() {
     if (!h) return fail(KMV_EINVAL, "problem is NULL");

@@ -735,4 +735,116 @@ bool validate_mesh(const Mesh& m, std::string& why) {
   return true;
 }
 
+namespace {
+// n-point Gauss-Legendre rule on [0, 1] (Newton on the three-term recurrence).
+void gauss01(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double t = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1, p1 = t;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2 * k - 1) * t * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (t * p1 - p0) / (t * t - 1);
+      const double step = p1 / dp;
+      t -= step;
+      if (std::fabs(step) < 1e-16) break;
+    }
+    x[i] = 0.5 * (1 - t);
+    w[i] = 1.0 / ((1 - t * t) * dp * dp);  // (2 / ((1-t^2) P_n'^2)) / 2
+  }
+}
+}  // namespace
+
+void boundary_weights(const Mesh& m, std::vector<int32_t>& dofs, std::vector<double>& b) {
+  const int dim = m.dim, nv = dim + 1, nd = m.nd, dd = dim * dim;
+  // every facet of every cell, as (sorted vertex ids, internal cell, local vertex left out)
+  struct F {
+    std::array<int32_t, 3> v;
+    int64_t cell;
+    int skip;
+  };
+  std::vector<F> fs;
+  fs.reserve((size_t)m.n_cells * nv);
+  for (int64_t e = 0; e < m.n_cells; ++e) {
+    const int32_t* cv = &m.cells_in[(size_t)m.cell_input[e] * nv];
+    for (int s = 0; s < nv; ++s) {
+      F f{{-1, -1, -1}, e, s};
+      int k = 0;
+      for (int a = 0; a < nv; ++a)
+        if (a != s) f.v[k++] = cv[a];
+      std::sort(f.v.begin(), f.v.begin() + dim);
+      fs.push_back(f);
+    }
+  }
+  std::sort(fs.begin(), fs.end(), [](const F& a, const F& c) { return a.v < c.v; });
+  // facet quadrature: points as barycentric weights of the facet's vertices, weights
+  // summing to 1 (times the facet measure below)
+  std::vector<double> gx, gw;
+  gauss01(8, gx, gw);
+  std::vector<std::array<double, 3>> qb;
+  std::vector<double> qw;
+  if (dim == 2) {
+    for (int i = 0; i < 8; ++i) {
+      qb.push_back({gx[i], 1 - gx[i], 0});
+      qw.push_back(gw[i]);
+    }
+  } else {  // triangle: t in (0,1) toward vertex 2, the remaining edge (1-t) split by s
+    for (int i = 0; i < 8; ++i)
+      for (int j = 0; j < 8; ++j) {
+        const double t = gx[i], s = gx[j];
+        qb.push_back({(1 - t) * (1 - s), (1 - t) * s, t});
+        qw.push_back(2 * gw[i] * gw[j] * (1 - t));
+      }
+  }
+  std::vector<double> acc(m.n_dofs, 0.0), phi(nd);
+  for (size_t i = 0; i < fs.size();) {
+    size_t j = i + 1;
+    while (j < fs.size() && fs[j].v == fs[i].v) ++j;
+    if (j - i == 1) {
+      const F& f = fs[i];
+      const double* X[3];
+      for (int a = 0; a < dim; ++a) X[a] = &m.coords[(size_t)f.v[a] * dim];
+      double meas;
+      if (dim == 2) {
+        meas = std::hypot(X[1][0] - X[0][0], X[1][1] - X[0][1]);
+      } else {
+        double u[3], v[3];
+        for (int r = 0; r < 3; ++r) {
+          u[r] = X[1][r] - X[0][r];
+          v[r] = X[2][r] - X[0][r];
+        }
+        meas = 0.5 * std::sqrt(std::pow(u[1] * v[2] - u[2] * v[1], 2) + std::pow(u[2] * v[0] - u[0] * v[2], 2) +
+                               std::pow(u[0] * v[1] - u[1] * v[0], 2));
+      }
+      const int64_t e = f.cell;
+      for (size_t q = 0; q < qw.size(); ++q) {
+        double x[3] = {0, 0, 0}, xi[3] = {0, 0, 0};
+        for (int a = 0; a < dim; ++a)
+          for (int r = 0; r < dim; ++r) x[r] += qb[q][a] * X[a][r];
+        for (int r = 0; r < dim; ++r)
+          for (int c = 0; c < dim; ++c) xi[r] += m.jinv[e * dd + r * dim + c] * (x[c] - m.x0[e * dim + c]);
+        m.el->eval(xi, phi.data());
+        for (int a = 0; a < nd; ++a) acc[m.cell_dofs[e * nd + a]] += meas * qw[q] * phi[a];
+      }
+    }
+    i = j;
+  }
+  // keep the DOFs on the boundary (the traces of the other nodes' basis functions
+  // vanish there, up to rounding)
+  double bmax = 0;
+  for (double v : acc) bmax = std::max(bmax, std::fabs(v));
+  dofs.clear();
+  b.clear();
+  for (int64_t i = 0; i < m.n_dofs; ++i)
+    if (std::fabs(acc[i]) > 1e-9 * bmax) {
+      dofs.push_back((int32_t)i);
+      b.push_back(acc[i]);
+    }
+}
+
 }  // namespace kmv

@@ -84,6 +84,13 @@ struct MeshError {
 Mesh* build_mesh(int dim, int degree, const double* coords, int64_t nv, const int32_t* cells,
                  int64_t ne, int patch_cells);
 
+// Boundary mass of the absorbing boundary term (the boundary integral of
+// c phi_i phi_j in the damping matrix M_{u,1} of the appendix, lumped by rows with c
+// at node i): b_i = integral over the mesh boundary of phi_i, for the DOFs where it
+// is not zero.  Facets (edges / triangles) that belong to one cell are the
+// boundary; on each, the cell's basis is integrated by Gauss quadrature.
+void boundary_weights(const Mesh& m, std::vector<int32_t>& dofs, std::vector<double>& b);
+
 // Row sums of |K(c)| divided by M (Gershgorin radii of M^-1 K).
 double gershgorin_rho(const Mesh& m, const double* c);
 

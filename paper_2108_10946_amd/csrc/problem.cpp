@@ -18,6 +18,7 @@
 #include <memory>
 
 #include "../../include/kmvwave.h"
+#include "boundary.hpp"
 #include "kernels.hpp"
 
 namespace kmv {
@@ -119,7 +120,11 @@ Status upload_coefficients(Problem* p) {
   const Mesh& m = *p->mesh;
   std::vector<double> gamma(m.n_dofs), beta;
   const double dt2 = p->dt * p->dt;
-  if (!p->eta.empty()) beta.resize(m.n_dofs);
+  // boundary DOFs carry c-dependent damping when the absorbing boundary is on
+  std::vector<int32_t> bix(p->absorb ? m.n_dofs : 0, -1);
+  for (int t = 0; p->absorb && t < p->nbd; ++t) bix[p->bnd_dof[t]] = t;
+  auto damped = [&](int64_t i) { return (!p->eta.empty() && p->eta[i] != 0.0) || (p->absorb && bix[i] >= 0); };
+  if (!p->eta.empty() || p->absorb) beta.resize(m.n_dofs);
   for (int64_t i = 0; i < m.n_dofs; ++i) {
     const double a = p->eta.empty() ? 0.0 : p->eta[i] * p->dt / 2.0;
     gamma[i] = dt2 / (m.mass[i] * (1.0 + a));
@@ -157,12 +162,33 @@ Status upload_coefficients(Problem* p) {
   if (!beta.empty()) {
     for (int64_t q = 0; q < m.n_patches; ++q) {
       for (int32_t i = m.patch_own_start[q]; i < m.patch_own_start[q + 1] && !flag[q]; ++i)
-        if (p->eta[i] != 0.0) flag[q] = 1;
+        if (damped(i)) flag[q] = 1;
       for (int32_t r = m.patch_sh_start[q]; r < m.patch_sh_start[q + 1] && !flag[q]; ++r)
-        if (p->eta[m.sh_idx[r]] != 0.0) flag[q] = 1;
+        if (damped(m.sh_idx[r])) flag[q] = 1;
     }
   }
   STTRY(upload_i(&p->d_damp_patch, flag));
+  if (p->absorb) {
+    std::vector<double> coef(3 * (size_t)p->nbd), hb(p->nbd);
+    for (int t = 0; t < p->nbd; ++t) {
+      const int32_t i = p->bnd_dof[t];
+      coef[3 * t] = p->eta.empty() ? 0.0 : p->eta[i] * p->dt / 2.0;
+      coef[3 * t + 1] = p->dt * p->bnd_b[t] / (2.0 * m.mass[i]);
+      coef[3 * t + 2] = dt2 / m.mass[i];
+      hb[t] = p->dt * p->bnd_b[t] / 2.0;
+    }
+    std::vector<int32_t> refs;
+    for (int64_t r = 0; r < m.n_shared_refs; ++r)
+      if (bix[m.sh_idx[r]] >= 0) {
+        refs.push_back((int32_t)r);
+        refs.push_back(bix[m.sh_idx[r]]);
+      }
+    p->nbr = (int)(refs.size() / 2);
+    if (refs.empty()) refs.assign(2, 0);
+    STTRY(upload_i(&p->d_bnd_coef, coef));
+    STTRY(upload_i(&p->d_bnd_hb, hb));
+    STTRY(upload_i(&p->d_bnd_ref, refs));
+  }
   return OK;
 }
 
@@ -441,8 +467,16 @@ Status zero_level(Problem* p, Sweep& S, T* u, int lvl_par, hipStream_t s) {
 // Forward launches n0..n1-1 from a complete level n0 (u in slot_of(n0), owned
 // increments in fwd.d, shared increments in fwd.dsh[n0&1]); ends with level n1
 // complete.  traces: rows n-1 = d^n.  save_ck: checkpoints at multiples of seg.
+// ub: boundary records, row n = u^n at the boundary DOFs (level n is complete
+// once launch n has run, level n1 after the final finish).
 template <typename T, typename F>
-Status run_forward(Problem* p, int64_t n0, int64_t n1, F slot_of, T* traces, bool save_ck, hipStream_t s) {
+Status run_forward(Problem* p, int64_t n0, int64_t n1, F slot_of, T* traces, bool save_ck, hipStream_t s,
+                   T* ub = nullptr) {
+  auto record = [&](int64_t n) -> Status {
+    HIPTRY(launch_gather_boundary<T>(slot_of(n), p->ls, p->nshot, p->nbd, p->d_bnd_dof, ub + n * p->nbd,
+                                     (p->nt + 1) * p->nbd, s));
+    return OK;
+  };
   const Mesh& m = *p->mesh;
   Sweep& S = p->fwd;
   const int64_t ns = p->nshot;
@@ -464,8 +498,10 @@ Status run_forward(Problem* p, int64_t n0, int64_t n1, F slot_of, T* traces, boo
     STTRY(step<T>(p, S, false, !fresh, slot_of(n), n > n0 ? slot_of(n - 1) : nullptr, slot_of(n + 1),
                   fwd_par(n), &p->src, (const T*)p->d_wavelet + n, 0, 0, T(1), nullptr, row, s));
     fresh = false;
+    if (ub) STTRY(record(n));
   }
   if (n1 > n0) STTRY(finish<T>(p, S, false, slot_of(n1 - 1), slot_of(n1), fwd_par(n1), s));
+  if (ub && n1 > n0) STTRY(record(n1));
   if (traces && n1 >= 1) {
     for (int64_t sh = 0; sh < ns; ++sh) {
       T* un = slot_of(n1) + sh * p->ls;
@@ -484,6 +520,9 @@ Status set_c2(Problem* p, const double* c, hipStream_t s) {
   const Mesh& m = *p->mesh;
   HIPTRY(launch_square<T>(c, (T*)p->d_c2, m.n_dofs, s));
   HIPTRY(launch_gather<T>((const T*)p->d_c2, p->d_sh_idx, (T*)p->d_c2_ref, p->nref, s));
+  if (p->absorb)
+    HIPTRY(launch_absorb_coef<T>(c, p->nbd, p->d_bnd_dof, p->d_bnd_coef, (T*)p->d_beta, (T*)p->d_gamma, p->nbr,
+                                 p->d_bnd_ref, (T*)p->d_beta_ref, (T*)p->d_gamma_ref, s));
   return OK;
 }
 
@@ -567,13 +606,32 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
   const int64_t r = p->grad_every;
   auto sub_slot = [p, r](int64_t n) { return n % r == 0 ? slot_ptr<T>(p, 2 + n / r) : slot_ptr<T>(p, n & 1); };
   STTRY(zero_level<T>(p, p->fwd, p->store_sub ? sub_slot(0) : slot_ptr<T>(p, 0), 0, s));
-  if (p->store_all) {
-    STTRY(run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n); }, traces, false, s));
-  } else if (p->store_sub) {
-    STTRY(run_forward<T>(p, 0, p->nt, sub_slot, traces, false, s));
-  } else {
-    STTRY(run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n & 1); }, traces, true, s));
+  // absorbing boundary: u^n and lambda^n at the boundary DOFs, every level
+  T *ub = nullptr, *lb = nullptr;
+  if (p->absorb && p->nbd > 0) {
+    const size_t rec = (size_t)p->nshot * (p->nt + 1) * p->nbd * sizeof(T);
+    if (p->bnd_rec_bytes != rec || !p->d_ub) {
+      STTRY(alloc(&p->d_ub, rec));
+      STTRY(alloc(&p->d_lb, rec));
+      p->bnd_rec_bytes = rec;
+    }
+    ub = (T*)p->d_ub;
+    lb = (T*)p->d_lb;
   }
+  if (p->store_all) {
+    STTRY(run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n); }, traces, false, s, ub));
+  } else if (p->store_sub) {
+    STTRY(run_forward<T>(p, 0, p->nt, sub_slot, traces, false, s, ub));
+  } else {
+    STTRY(run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n & 1); }, traces, true, s, ub));
+  }
+  // lambda^lvl is complete once reverse launch lvl-1 has run (lambda^1 after the end)
+  auto record_lam = [&](int64_t lvl) -> Status {
+    if (!lb) return OK;
+    HIPTRY(launch_gather_boundary<T>((const T*)p->d_lam[lvl & 1], p->ls, p->nshot, p->nbd, p->d_bnd_dof,
+                                     lb + lvl * p->nbd, (p->nt + 1) * p->nbd, s));
+    return OK;
+  };
   HIPTRY(launch_misfit<T>(traces, obs, (T*)p->d_resid, p->nt * p->rec.npts * p->nshot, p->d_red,
                           p->red_blocks, p->d_red + p->red_blocks, s));
   STTRY(adjoint_start<T>(p, s));
@@ -585,6 +643,7 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
     const bool g = mm % r == 0;
     STTRY(adjoint_launch<T>(p, mm, g, resid, g ? uf : nullptr, s));
     if (g && r > 1) STTRY(pair_finish<T>(p, adj_par(mm), s));
+    if (mm + 1 <= p->nt) STTRY(record_lam(mm + 1));
     return OK;
   };
   if (p->store_all) {
@@ -607,7 +666,14 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
     }
   }
   STTRY(adjoint_end<T>(p, r == 1, s));
+  STTRY(record_lam(1));
   HIPTRY(launch_finalize_grad(c, p->d_gacc, p->nshot, 2.0 * p->dt * p->dt * (double)r, grad, N, s));
+  if (lb) {
+    const int chunks = (int)std::min<int64_t>(kBndChunks, p->nt);
+    if (!p->d_bnd_part) STTRY(alloc((void**)&p->d_bnd_part, (size_t)kBndChunks * p->nbd * sizeof(double)));
+    HIPTRY(launch_absorb_grad<T>(ub, lb, p->nt, p->nbd, p->nshot, p->d_bnd_dof, p->d_bnd_hb, p->d_bnd_part,
+                                 chunks, grad, s));
+  }
   double hJ = 0;
   HIPTRY(hipMemcpyAsync(&hJ, p->d_red + p->red_blocks, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPTRY(hipStreamSynchronize(s));
@@ -762,7 +828,8 @@ Problem::~Problem() {
   for (void* q : {(void*)d_lmap, d_geom, (void*)d_cell_start, (void*)d_own_start, (void*)d_sh_start,
                   (void*)d_sh_idx, (void*)d_shp_ptr, (void*)d_shp_slot, (void*)d_ref_slots, (void*)d_gword,
                   (void*)d_glist, (void*)d_gword_off, (void*)d_glist_off, (void*)d_damp_patch, d_gamma, d_gdet, d_beta, d_c2, d_c2_ref, d_gamma_ref, d_beta_ref, d_minv_sqrt, d_lam[0], d_lam[1], (void*)d_gacc, (void*)d_red, d_slots,
-                  d_ck_u, d_ck_du, d_resid, d_traces_tmp, d_wavelet})
+                  d_ck_u, d_ck_du, d_resid, d_traces_tmp, d_wavelet, (void*)d_bnd_dof, (void*)d_bnd_ref,
+                  (void*)d_bnd_coef, (void*)d_bnd_hb, d_ub, d_lb, (void*)d_bnd_part})
     dfree(q);
   free_sweep(fwd);
   free_sweep(adj);
@@ -891,6 +958,19 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
   STTRY(alloc((void**)&p->d_red, (size_t)(p->red_blocks + 8) * 8));
   *out = guard.release();
   return OK;
+}
+
+Status set_absorbing_boundary(Problem* p, bool on) {
+  DeviceGuard dg(p->device);
+  if (on && p->bnd_dof.empty()) {
+    boundary_weights(*p->mesh, p->bnd_dof, p->bnd_b);
+    p->nbd = (int)p->bnd_dof.size();
+    STTRY(upload_i(&p->d_bnd_dof, p->bnd_dof.empty() ? std::vector<int32_t>{0} : p->bnd_dof));
+    dfree(p->d_bnd_part);
+    p->d_bnd_part = nullptr;
+  }
+  p->absorb = on;
+  return upload_coefficients(p);
 }
 
 Status set_damping(Problem* p, const double* eta) {

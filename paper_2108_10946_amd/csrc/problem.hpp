@@ -100,6 +100,19 @@ struct Problem {
   void* d_c2 = nullptr;
   void *d_c2_ref = nullptr, *d_gamma_ref = nullptr, *d_beta_ref = nullptr;  // [nref]
   void* d_minv_sqrt = nullptr;  // for the power iteration
+  // absorbing boundary term (off unless enabled): the boundary DOFs' damping
+  // a_i = eta_i dt/2 + dt c_i b_i/(2 M_i) is rebuilt from c at every solve
+  bool absorb = false;
+  std::vector<int32_t> bnd_dof;  // boundary DOFs (b_i != 0), ascending
+  std::vector<double> bnd_b;     // b_i = boundary integral of phi_i
+  int nbd = 0, nbr = 0;          // boundary DOFs, shared refs of boundary DOFs
+  int32_t* d_bnd_dof = nullptr;  // [nbd]
+  int32_t* d_bnd_ref = nullptr;  // [2*nbr] (shared ref, boundary index)
+  double* d_bnd_coef = nullptr;  // [3*nbd] (eta dt/2, dt b/(2M), dt^2/M)
+  double* d_bnd_hb = nullptr;    // [nbd] dt b / 2
+  void *d_ub = nullptr, *d_lb = nullptr;  // [n_shots][nt+1][nbd] u^n, lambda^n at the boundary DOFs
+  size_t bnd_rec_bytes = 0;
+  double* d_bnd_part = nullptr;  // [kBndChunks*nbd] ordered partial sums of the gradient term
   // sweeps
   Sweep fwd, adj;
   void* d_lam[2] = {nullptr, nullptr};
@@ -127,6 +140,7 @@ struct Problem {
 Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_every, size_t budget,
                       int n_shots, int64_t grad_every, Problem** out);
 Status set_damping(Problem* p, const double* eta);
+Status set_absorbing_boundary(Problem* p, bool on);
 Status set_sources(Problem* p, const double* xs, int nsrc, double f0, double t0, double amp);
 Status set_wavelet(Problem* p, const double* w);
 Status set_receivers(Problem* p, const double* xr, int nrec);

@@ -30,7 +30,7 @@ DECLARED = [
     "kmv_last_error", "kmv_element_tables", "kmv_mesh_create", "kmv_mesh_info",
     "kmv_mesh_dof_coords", "kmv_mesh_lumped_mass", "kmv_mesh_cell_dofs", "kmv_mesh_validate",
     "kmv_mesh_destroy",
-    "kmv_problem_create", "kmv_cfl_dt", "kmv_spectral_radius", "kmv_set_damping",
+    "kmv_problem_create", "kmv_cfl_dt", "kmv_spectral_radius", "kmv_set_damping", "kmv_set_absorbing_boundary",
     "kmv_set_sources", "kmv_set_source_wavelet", "kmv_set_receivers", "kmv_forward",
     "kmv_misfit_gradient", "kmv_adjoint", "kmv_stiffness_apply", "kmv_problem_info", "kmv_problem_num_shots",
     "kmv_profile_enable", "kmv_profile_read", "kmv_problem_destroy",
@@ -96,6 +96,7 @@ def lib():
         "kmv_cfl_dt": (C.c_int, [_P, _D, _D]),
         "kmv_spectral_radius": (C.c_int, [_P, _P, C.c_int, C.c_uint64, _D, _P]),
         "kmv_set_damping": (C.c_int, [_P, _D]),
+        "kmv_set_absorbing_boundary": (C.c_int, [_P, C.c_int]),
         "kmv_set_sources": (C.c_int, [_P, _D, C.c_int, C.c_double, C.c_double, C.c_double]),
         "kmv_set_source_wavelet": (C.c_int, [_P, _D]),
         "kmv_set_receivers": (C.c_int, [_P, _D, C.c_int]),
@@ -243,6 +244,10 @@ def kmv_spectral_radius(p, c_dev, iters=200, seed=0, stream=None):
     out = C.c_double()
     _check(lib().kmv_spectral_radius(p, _tptr(c_dev), iters, seed, C.byref(out), _stream(stream)))
     return out.value
+
+
+def kmv_set_absorbing_boundary(p, enable):
+    _check(lib().kmv_set_absorbing_boundary(p, 1 if enable else 0))
 
 
 def kmv_set_damping(p, eta):

@@ -1,0 +1,138 @@
+"""Absorbing boundary term (kmv_set_absorbing_boundary) against the oracle: the
+boundary DOFs' damping follows c at every solve, and the gradient carries the
+boundary term (dt b_i / 2) sum_n lambda_i^n (u_i^n - u_i^{n-2}).
+
+Tolerances as for every other parity case: FP64 1e-10 relative L2 on J, traces and
+gradient; FP32 1e-4 on the traces and 1e-3 on the gradient.  Cases: triangles
+k = 2 and 4 and tetrahedra k = 2, with small ragged patches (shared boundary DOFs
+everywhere), with the sponge on as well, two shots, checkpoints with recompute, and
+gradient subsampling (the boundary term is taken at every step)."""
+import numpy as np
+import pytest
+
+from gpu_util import say, dof_map, rel_l2
+from oracle.fem import Discretization
+from oracle import solver
+from synth import configs
+from synth.models import sponge_eta
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_10946_amd as kmv
+    kmv.lib()
+
+
+def cuda(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def case(kind, k, sponge, n_shots):
+    if kind == "tri":
+        coords, cells = configs.small_tri(7, seed=6)
+        d = Discretization(coords, cells, k)
+        x, z = d.dof_coords.T
+        c_true = 1.5 + 0.4 * z + 0.1 * np.sin(5 * x)
+        c0 = 1.5 + 0.4 * z
+        eta = sponge_eta(x, z, 0.0, 1.0, 0.8, 0.2, c_max=2.5) if sponge else None
+        xs = np.array([[[0.4, 0.3]], [[0.7, 0.5]]])[:n_shots]
+        xr = np.stack([np.linspace(0.1, 0.9, 7), np.full(7, 0.15)], axis=1)
+        f0, patch = 8.0, 9
+    else:
+        coords, cells = configs.small_tet(3, seed=6)
+        d = Discretization(coords, cells, k)
+        x, y, z = d.dof_coords.T
+        c_true = 1.5 + 0.3 * z + 0.1 * np.sin(4 * x)
+        c0 = 1.5 + 0.3 * z
+        eta = 3.0 * np.maximum(0.0, x - 0.75) ** 2 if sponge else None
+        xs = np.array([[[0.5, 0.5, 0.4]], [[0.3, 0.6, 0.5]]])[:n_shots]
+        xr = np.stack([np.linspace(0.2, 0.8, 5), np.full(5, 0.5), np.full(5, 0.2)], axis=1)
+        f0, patch = 6.0, 5
+    dt = 0.8 * solver.cfl_dt_gershgorin(d.stiffness(c_true), d.lumped_mass())
+    nt = int(np.ceil(0.9 / dt))  # long enough for the wave to reach every side and return
+    return coords, cells, d, c_true, c0, eta, xs, xr, f0, patch, dt, nt
+
+
+def oracle_sum(d, c_true, c0, eta, xs, xr, f0, dt, nt, r=1):
+    J, g, tr, obs = 0.0, np.zeros(d.n_dofs), [], []
+    for s in range(len(xs)):
+        sh = solver.Shot(d, xs[s], xr, dt, nt, f0=f0, t0=0.1)
+        dobs, _ = sh.forward(c_true, eta, absorb=True)
+        Js, gs, ts = sh.misfit_gradient(c0, dobs, eta, r=r, absorb=True)
+        J, g = J + Js, g + gs
+        tr.append(ts)
+        obs.append(dobs)
+    return J, g, np.stack(tr), np.stack(obs)
+
+
+CASES = [  # kind, k, sponge, shots, checkpoint_every, gradient_every, small patches
+    ("tri", 2, False, 1, 0, 1, False),
+    ("tri", 2, True, 1, 0, 1, True),
+    ("tri", 4, False, 2, 0, 1, True),
+    ("tri", 2, False, 1, 9, 1, True),
+    ("tri", 2, True, 2, 0, 3, False),
+    ("tet", 2, False, 1, 0, 1, True),
+    ("tet", 2, True, 2, 7, 1, False),
+]
+
+
+@pytest.mark.parametrize("kind,k,sponge,n_shots,ckpt,r,small", CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_absorbing_boundary_vs_oracle(kind, k, sponge, n_shots, ckpt, r, small, prec):
+    from paper_2108_10946_amd import Mesh, Problem
+    coords, cells, d, c_true, c0, eta, xs, xr, f0, patch, dt, nt = case(kind, k, sponge, n_shots)
+    J_or, g_or, tr_or, obs = oracle_sum(d, c_true, c0, eta, xs, xr, f0, dt, nt, r=r)
+    m = Mesh(coords, cells, k, patch_cells=patch if small else 0)
+    p = dof_map(m.dof_coords(), d.dof_coords)
+    say(f"absorbing boundary: {kind} k={k} sponge={sponge} shots={n_shots} ckpt={ckpt} r={r} "
+        f"small={small} {prec}")
+    prob = Problem(m, dt, nt, precision=prec, checkpoint_every=ckpt, n_shots=n_shots, gradient_every=r)
+    if eta is not None:
+        prob.set_damping(eta[p])
+    prob.set_absorbing_boundary(True)
+    prob.set_sources(xs if n_shots > 1 else xs[0], f0=f0, t0=0.1)
+    prob.set_receivers(xr)
+    o = cuda(obs if n_shots > 1 else obs[0], prob.dtype)
+    J, g, tr = prob.misfit_gradient(cuda(c0[p]), o, keep_traces=True)
+    fwd = prob.forward(cuda(c0[p]))
+    prob.close()
+    tr_ref = tr_or if n_shots > 1 else tr_or[0]
+    et, eg = rel_l2(tr.double().cpu().numpy(), tr_ref), rel_l2(g.cpu().numpy(), g_or[p])
+    say(f"  J {J:.9e} (oracle {J_or:.9e}) traces {et:.2e} gradient {eg:.2e}")
+    assert torch.equal(fwd, tr)  # the forward-only call runs the same steps
+    if prec == "fp64":
+        assert abs(J - J_or) < 1e-10 * J_or
+        assert et < 1e-10 and eg < 1e-10
+    else:
+        assert et < 1e-4 and eg < 1e-3
+
+
+def test_absorbing_boundary_off_again_is_neumann():
+    """Turning the term off restores the plain problem bitwise; on, it changes the
+    traces (the boundary reflections weaken)."""
+    from paper_2108_10946_amd import Mesh, Problem
+    coords, cells, d, c_true, c0, eta, xs, xr, f0, patch, dt, nt = case("tri", 3, True, 1)
+    m = Mesh(coords, cells, 3)
+    p = dof_map(m.dof_coords(), d.dof_coords)
+    say("absorbing boundary: on, then off")
+
+    def run(flags):
+        prob = Problem(m, dt, nt, precision="fp64")
+        prob.set_damping(eta[p])
+        for f in flags:
+            prob.set_absorbing_boundary(f)
+        prob.set_sources(xs[0], f0=f0, t0=0.1)
+        prob.set_receivers(xr)
+        out = prob.forward(cuda(c0[p])).cpu().numpy()
+        prob.close()
+        return out
+
+    plain, on, off = run([]), run([True]), run([True, False])
+    assert np.array_equal(plain, off)
+    assert rel_l2(on, plain) > 1e-3
