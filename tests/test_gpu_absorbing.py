@@ -4,7 +4,7 @@ boundary term (dt b_i / 2) sum_n lambda_i^n (u_i^n - u_i^{n-2}).
 
 Tolerances as for every other parity case: FP64 1e-10 relative L2 on J, traces and
 gradient; FP32 1e-4 on the traces and 1e-3 on the gradient.  Cases: triangles
-k = 2 and 4 and tetrahedra k = 2, with small ragged patches (shared boundary DOFs
+k = 2, 3 and 4 and tetrahedra k = 2 and 3, with small ragged patches (shared boundary DOFs
 everywhere), with the sponge on as well, two shots, checkpoints with recompute, and
 gradient subsampling (the boundary term is taken at every step)."""
 import numpy as np
@@ -77,8 +77,10 @@ CASES = [  # kind, k, sponge, shots, checkpoint_every, gradient_every, small pat
     ("tri", 4, False, 2, 0, 1, True),
     ("tri", 2, False, 1, 9, 1, True),
     ("tri", 2, True, 2, 0, 3, False),
+    ("tri", 3, True, 1, 0, 1, False),
     ("tet", 2, False, 1, 0, 1, True),
     ("tet", 2, True, 2, 7, 1, False),
+    ("tet", 3, False, 1, 0, 1, False),
 ]
 
 

@@ -7,7 +7,7 @@ wavelet with an early delay so that the window holds signal).  Over the
 whole window only properties that hold at any size are checked: the dot-product
 identity of the adjoint, and central differences of the multi-shot misfit along
 a smooth seeded direction, converging as h^2 (the 40-shot gradient workload,
-with fewer shots and a shorter window).  Tolerances as in the small-case parity tests."""
+with fewer shots and a shorter window), also with the absorbing boundary on.  Tolerances as in the small-case parity tests."""
 import numpy as np
 import pytest
 
@@ -162,3 +162,41 @@ def test_multishot_central_differences(c2, prec, hs, tol):
     assert errs[-1] < tol
     if len(errs) > 1:  # central differences converge as h^2 (16x per halving of h twice)
         assert errs[-1] < errs[0] / 8
+
+
+def test_absorbing_boundary_central_differences(c2):
+    """Absorbing boundary on (with the sponge), two shots in one problem, 1000 FP64
+    steps: the gradient, boundary term included, against central differences along
+    a direction concentrated on the top boundary next to the shots, where only the
+    boundary damping (no sponge) acts."""
+    from paper_2108_10946_amd import Problem
+    w, d, m, p = c2
+    nt = 1000
+    say("full size: absorbing boundary, 2-shot central differences fp64")
+    x = m.dof_coords()
+    eta = w.eta(x[:, 0], x[:, 1])
+    shots = np.array([2.0, 6.0])
+    c0 = w.vp(x[:, 0], x[:, 1])
+    bumps = sum(np.exp(-((x[:, 0] - xs - 0.1) ** 2 + (x[:, 1] - 0.12) ** 2) / 0.005) for xs in shots)
+    pr = Problem(m, DT, nt, precision="fp64", n_shots=2)
+    pr.set_damping(eta)
+    pr.set_absorbing_boundary(True)
+    pr.set_sources(np.array([[[xs, 0.01]] for xs in shots]), f0=w.f0, t0=0.1)
+    pr.set_receivers(w.receivers)
+    obs = pr.forward(cuda(c0 * (1.0 + 0.1 * bumps)))
+    dvec = sum(np.exp(-((x[:, 0] - xs + 0.2) ** 2 + x[:, 1] ** 2) / 0.01) for xs in shots)
+    dvec[eta > 0] = 0.0
+    dvec /= np.abs(dvec).max()
+    J, g, _ = pr.misfit_gradient(cuda(c0), obs)
+    an = float(g.cpu().numpy() @ dvec)
+    errs = []
+    for h in (4e-4, 1e-4):
+        Jp, _, _ = pr.misfit_gradient(cuda(c0 + h * dvec), obs)
+        Jm, _, _ = pr.misfit_gradient(cuda(c0 - h * dvec), obs)
+        fd = (Jp - Jm) / (2 * h)
+        errs.append(abs(fd - an) / abs(an))
+        say(f"  J {J:.6e} h {h:.0e} fd {fd:.9e} an {an:.9e} rel {errs[-1]:.2e}")
+    pr.close()
+    assert J > 1e-6
+    assert errs[-1] < 1e-6
+    assert errs[-1] < errs[0] / 8
