@@ -41,6 +41,17 @@ __global__ void __launch_bounds__(kBlock) k_gather_boundary(const T* __restrict_
 }
 
 template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gather_levels(const T* __restrict__ levels, int64_t level_stride,
+                                                          int64_t ls, int ns, int64_t nlev, int nbd,
+                                                          const int32_t* __restrict__ dof, T* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= (int64_t)ns * nlev * nbd) return;
+  const int64_t t = i % nbd, r = i / nbd;  // r = sh*nlev + n
+  const int64_t sh = r / nlev, n = r - sh * nlev;
+  out[i] = levels[n * level_stride + sh * ls + dof[t]];
+}
+
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_absorb_part(const T* __restrict__ ub, const T* __restrict__ lb, int64_t nt,
                                                         int nbd, int ns, int nchunk, double* __restrict__ part) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -91,6 +102,15 @@ hipError_t launch_gather_boundary(const T* lvl, int64_t ls, int ns, int nbd, con
 }
 
 template <typename T>
+hipError_t launch_gather_levels(const T* levels, int64_t level_stride, int64_t ls, int ns, int64_t nlev, int nbd,
+                                const int32_t* dof, T* out, hipStream_t s) {
+  if (nbd == 0 || ns == 0 || nlev == 0) return hipSuccess;
+  k_gather_levels<T><<<blocks((int64_t)ns * nlev * nbd), kBlock, 0, s>>>(levels, level_stride, ls, ns, nlev, nbd,
+                                                                         dof, out);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_absorb_grad(const T* ub, const T* lb, int64_t nt, int nbd, int ns, const int32_t* dof,
                               const double* hb, double* part, int nchunk, double* g, hipStream_t s) {
   if (nbd == 0 || nt < 1) return hipSuccess;
@@ -106,6 +126,8 @@ hipError_t launch_absorb_grad(const T* ub, const T* lb, int64_t nt, int nbd, int
                                             const int32_t*, T*, T*, hipStream_t);                              \
   template hipError_t launch_gather_boundary<T>(const T*, int64_t, int, int, const int32_t*, T*, int64_t,      \
                                                 hipStream_t);                                                  \
+  template hipError_t launch_gather_levels<T>(const T*, int64_t, int64_t, int, int64_t, int, const int32_t*, T*, \
+                                              hipStream_t);                                                    \
   template hipError_t launch_absorb_grad<T>(const T*, const T*, int64_t, int, int, const int32_t*,            \
                                             const double*, double*, int, double*, hipStream_t);
 KMV_BOUNDARY_INST(float)

@@ -29,6 +29,12 @@ template <typename T>
 hipError_t launch_gather_boundary(const T* lvl, int64_t ls, int ns, int nbd, const int32_t* dof, T* out,
                                   int64_t out_stride, hipStream_t s);
 
+// The same for every level at once when all levels are kept:
+// out[(sh*nlev + n)*nbd + t] = levels[n*level_stride + sh*ls + dof[t]], n < nlev.
+template <typename T>
+hipError_t launch_gather_levels(const T* levels, int64_t level_stride, int64_t ls, int ns, int64_t nlev, int nbd,
+                                const int32_t* dof, T* out, hipStream_t s);
+
 // g[dof[t]] += hb[t] * sum_sh sum_{n=1}^{nt} lb[sh][n][t] (ub[sh][n][t] - ub[sh][n-2][t])
 // with rows [sh][n] of nbd values, n = 0..nt (ub row 0 = u^0 = 0; u^{-1} = 0); the sum
 // over n is split in nchunk ordered partials (part: [nchunk*nbd] doubles), so the

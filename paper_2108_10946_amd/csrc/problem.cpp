@@ -618,8 +618,11 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
     ub = (T*)p->d_ub;
     lb = (T*)p->d_lb;
   }
-  if (p->store_all) {
-    STTRY(run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n); }, traces, false, s, ub));
+  if (p->store_all) {  // every level stays in its slot: one gather for all of them
+    STTRY(run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n); }, traces, false, s));
+    if (ub)
+      HIPTRY(launch_gather_levels<T>(slot_ptr<T>(p, 0), p->ls * p->nshot, p->ls, p->nshot, p->nt + 1, p->nbd,
+                                     p->d_bnd_dof, ub, s));
   } else if (p->store_sub) {
     STTRY(run_forward<T>(p, 0, p->nt, sub_slot, traces, false, s, ub));
   } else {
