@@ -99,7 +99,7 @@ WORKLOADS = ("layered_kmv4", "layered_tet_kmv3")
 
 
 def setup_workload(precision, budget_frac=0.75, window=0, workload="layered_kmv4", checkpoint_every=0,
-                   mesh_cache={}, problem=True, gradient_every=1):
+                   mesh_cache={}, problem=True, gradient_every=1, absorbing=False):
     import torch
     from paper_2108_10946_amd import Mesh, Problem
     from synth import configs
@@ -131,6 +131,8 @@ def setup_workload(precision, budget_frac=0.75, window=0, workload="layered_kmv4
     prob = Problem(m, dt, nt, precision=precision, mem_budget=budget, checkpoint_every=checkpoint_every,
                    gradient_every=gradient_every)
     prob.set_damping(eta)
+    if absorbing:
+        prob.set_absorbing_boundary(True)
     prob.set_sources(w.sources, f0=w.f0, t0=w.t0, amp=w.amp)
     prob.set_receivers(w.receivers)
     obs = prob.forward(c_obs)
@@ -139,11 +141,12 @@ def setup_workload(precision, budget_frac=0.75, window=0, workload="layered_kmv4
 
 
 def time_gpu(precision, steps, warmup, every, window=0, workload="layered_kmv4", checkpoint_every=0,
-             gradient_every=1):
+             gradient_every=1, absorbing=False):
     import torch
     from paper_2108_10946_amd import kmvwave as K
     w, m, prob, c, obs, dt, nt = setup_workload(precision, window=window, workload=workload,
-                                                checkpoint_every=checkpoint_every, gradient_every=gradient_every)
+                                                checkpoint_every=checkpoint_every, gradient_every=gradient_every,
+                                                absorbing=absorbing)
     K.kmv_profile_enable(prob.handle, every)
     for i in range(warmup):
         t = time.time()
@@ -574,6 +577,10 @@ def main():
     ap.add_argument("--multi-shot", type=int, default=8, help="shots per problem in the multi-shot leg")
     ap.add_argument("--subsample", type=int, default=10,
                     help="also time the paper's gradient subsampling with this ratio (1: skip)")
+    ap.add_argument("--no-absorbing", action="store_true",
+                    help="skip the leg with the absorbing boundary term on")
+    ap.add_argument("--absorbing-only", action="store_true",
+                    help="run only the absorbing-boundary leg (for a kernel-trace profile)")
     ap.add_argument("--multi-shot-only", action="store_true",
                     help="run only the multi-shot leg and print its object (profiling runs)")
     ap.add_argument("--serving-requests", type=int, default=48)
@@ -603,11 +610,29 @@ def main():
     import paper_2108_10946_amd as kmv
     kmv.lib()
 
+    def absorbing_leg(ref_sec=None):
+        a = time_gpu("fp32", args.steps, min(1, args.warmup), 0, absorbing=True)
+        out = {"value": round(a["n_dofs"] * a["nt"] / a["sec"], 1), "ms_per_step": round(a["sec"] * 1e3, 3),
+               "storage": ("all states kept in HBM" if a["checkpoint_every"] == 0
+                           else f"checkpoints every {a['checkpoint_every']} steps"),
+               "note": "first-order absorbing boundary (du/dt + c du/dn = 0) on every boundary facet, "
+                       "with its gradient term; observed data from the same boundary"}
+        if ref_sec:
+            out["overhead_vs_neumann"] = round(a["sec"] / ref_sec - 1.0, 4)
+        return out
+
+    if args.absorbing_only:
+        print(json.dumps({"absorbing_boundary": absorbing_leg()}), flush=True)
+        return
+
     res32 = time_gpu("fp32", args.steps, args.warmup, args.profile_every, args.window)
     rl = roofline(res32, 4)
     sub1 = None
     if not args.window and args.subsample > 1:
         sub1 = time_gpu("fp32", args.steps, min(1, args.warmup), 0, gradient_every=args.subsample)
+    absorb = None
+    if not args.window and not args.no_absorbing:
+        absorb = absorbing_leg(res32["sec"])
     res64 = None
     if not args.no_fp64:
         res64 = time_gpu("fp64", max(1, args.steps // 2), min(1, args.warmup), args.profile_every,
@@ -669,6 +694,8 @@ def main():
             "gradient_rel_l2_vs_exact": _rel(sub1["grad"], res32["grad"]),
             "note": "the paper's gradient subsampling (pairing and stored states every r-th step, "
                     "scaled by r); an approximation of the exact gradient that value is quoted on"}
+    if absorb:
+        out["absorbing_boundary"] = absorb
     if serving:
         out["p50_shot_latency_s"] = serving["fp32_server"]["p50_latency_s"]
         out["p99_shot_latency_s"] = serving["fp32_server"]["p99_latency_s"]
