@@ -265,6 +265,7 @@ typedef struct {
                              n_shots), and run as one multi-shot problem (one launch per
                              step for all of them, kmv_options.n_shots); J and grad are
                              sums over the shots */
+  int absorbing;          /* 1: absorbing boundary term on (kmv_set_absorbing_boundary) */
 } kmv_request;
 
 typedef struct {

@@ -847,4 +847,10 @@ void boundary_weights(const Mesh& m, std::vector<int32_t>& dofs, std::vector<dou
     }
 }
 
+void boundary_of(const Mesh& m, const std::vector<int32_t>** dofs, const std::vector<double>** b) {
+  std::call_once(m.bnd_once, [&m]() { boundary_weights(m, m.bnd_dof, m.bnd_b); });
+  *dofs = &m.bnd_dof;
+  *b = &m.bnd_b;
+}
+
 }  // namespace kmv

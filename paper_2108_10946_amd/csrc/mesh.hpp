@@ -1,6 +1,7 @@
 // Mesh preprocessing for the patch-scheduled GPU kernels (host side).
 #pragma once
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -72,6 +73,12 @@ struct Mesh {
   int grid_n[3] = {1, 1, 1};
   std::vector<int64_t> grid_ptr, grid_cells;
 
+  // boundary mass, computed on first use (see boundary_of); shared by the problems
+  // and server requests on this mesh
+  mutable std::once_flag bnd_once;
+  mutable std::vector<int32_t> bnd_dof;
+  mutable std::vector<double> bnd_b;
+
   // Find the cell containing x (barycentric >= -tol, lowest input id among ties).
   // Returns false if none.
   bool locate(const double* x, PointLoc& out) const;
@@ -90,6 +97,8 @@ Mesh* build_mesh(int dim, int degree, const double* coords, int64_t nv, const in
 // is not zero.  Facets (edges / triangles) that belong to one cell are the
 // boundary; on each, the cell's basis is integrated by Gauss quadrature.
 void boundary_weights(const Mesh& m, std::vector<int32_t>& dofs, std::vector<double>& b);
+// The mesh's boundary DOFs and b_i, computed once (thread-safe) and kept with it.
+void boundary_of(const Mesh& m, const std::vector<int32_t>** dofs, const std::vector<double>** b);
 
 // Row sums of |K(c)| divided by M (Gershgorin radii of M^-1 K).
 double gershgorin_rho(const Mesh& m, const double* c);

@@ -966,7 +966,11 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
 Status set_absorbing_boundary(Problem* p, bool on) {
   DeviceGuard dg(p->device);
   if (on && p->bnd_dof.empty()) {
-    boundary_weights(*p->mesh, p->bnd_dof, p->bnd_b);
+    const std::vector<int32_t>* d;
+    const std::vector<double>* b;
+    boundary_of(*p->mesh, &d, &b);
+    p->bnd_dof = *d;
+    p->bnd_b = *b;
     p->nbd = (int)p->bnd_dof.size();
     STTRY(upload_i(&p->d_bnd_dof, p->bnd_dof.empty() ? std::vector<int32_t>{0} : p->bnd_dof));
     dfree(p->d_bnd_part);

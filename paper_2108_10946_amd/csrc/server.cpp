@@ -48,6 +48,10 @@ Status run_job(Server* S, Job* j, hipStream_t st) {
       Status r = set_damping(p, j->eta.data());
       if (r.code != KMV_OK) return r;
     }
+    if (j->absorbing) {
+      Status r = set_absorbing_boundary(p, true);
+      if (r.code != KMV_OK) return r;
+    }
     Status r = set_sources(p, j->xs.data(), j->nsrc, j->f0, j->t0, j->amp);
     if (r.code != KMV_OK) return r;
     r = set_receivers(p, j->xr.data(), j->nrec);
@@ -135,7 +139,7 @@ void worker(Server* S, int slot) {
 
 double Server::now() const { return seconds_since(epoch); }
 
-size_t job_device_bytes(const Mesh& m, int prec, int64_t nt, int nrec, size_t budget, int nshot) {
+size_t job_device_bytes(const Mesh& m, int prec, int64_t nt, int nrec, size_t budget, int nshot, int64_t n_bnd) {
   const size_t ts = prec == KMV_FP64 ? 8 : 4;
   const size_t N = (size_t)m.n_dofs, ne = (size_t)m.n_cells, np = (size_t)m.n_patches;
   size_t b = 0;
@@ -163,6 +167,8 @@ size_t job_device_bytes(const Mesh& m, int prec, int64_t nt, int nrec, size_t bu
   const size_t rows = (size_t)nt * nrec * S;
   b += 2 * rows * ts + (size_t)nt * ts + (size_t)(nrec + 8 * S) * m.nd * 16 + S * (np + 1) * 4;
   b += 2 * N * 8 + 2 * rows * ts;
+  // absorbing boundary (n_bnd >= 0): coefficient tables, u and lambda records, partial sums
+  if (n_bnd >= 0) b += (size_t)n_bnd * (2 * S * (nt + 1) * ts + 4 * 8 + 4 + 64 * 8) + 2 * N * ts + 4096;
   // allocation granularity
   return b + (b >> 4) + ((size_t)4 << 20);
 }
@@ -210,6 +216,7 @@ Status server_submit(Server* S, Mesh* m, const kmv_request* q, uint64_t* ticket)
   const int nshot = q->n_shots == 0 ? 1 : q->n_shots;
   if (nshot < 1 || nshot > 1024) return Status{KMV_EINVAL, "n_shots must be in 1..1024"};
   if (q->n_src % nshot != 0) return Status{KMV_EINVAL, "n_src must be a multiple of n_shots (shot-major)"};
+  if (q->absorbing != 0 && q->absorbing != 1) return Status{KMV_EINVAL, "absorbing must be 0 or 1"};
   std::unique_ptr<Job> j(new Job());
   j->mesh = m;
   j->prec = q->precision;
@@ -219,6 +226,7 @@ Status server_submit(Server* S, Mesh* m, const kmv_request* q, uint64_t* ticket)
   j->nsrc = q->n_src;
   j->nrec = q->n_rec;
   j->nshot = nshot;
+  j->absorbing = q->absorbing;
   j->f0 = q->f0;
   j->t0 = q->t0;
   j->amp = q->amp;
@@ -232,7 +240,14 @@ Status server_submit(Server* S, Mesh* m, const kmv_request* q, uint64_t* ticket)
     j->observed.assign(o, o + (size_t)q->n_steps * q->n_rec * nshot * ts);
   }
   std::lock_guard<std::mutex> lk(S->mu);
-  j->need = job_device_bytes(*m, j->prec, j->nt, j->nrec, S->per_job_budget, nshot);
+  int64_t n_bnd = -1;
+  if (j->absorbing) {
+    const std::vector<int32_t>* d;
+    const std::vector<double>* bw;
+    boundary_of(*m, &d, &bw);
+    n_bnd = (int64_t)d->size();
+  }
+  j->need = job_device_bytes(*m, j->prec, j->nt, j->nrec, S->per_job_budget, nshot, n_bnd);
   if (j->need > S->budget)
     return Status{KMV_ENOMEM, "request needs " + std::to_string(j->need) + " device bytes, budget is " +
                                   std::to_string(S->budget)};

@@ -24,7 +24,7 @@ struct Job {
   uint64_t ticket = 0;
   // request
   Mesh* mesh = nullptr;
-  int prec = 0, forward_only = 0, nsrc = 0, nrec = 0, nshot = 1;
+  int prec = 0, forward_only = 0, nsrc = 0, nrec = 0, nshot = 1, absorbing = 0;
   double dt = 0, f0 = 0, t0 = 0, amp = 0;
   int64_t nt = 0;
   std::vector<double> c, eta, xs, xr;
@@ -69,6 +69,7 @@ void server_destroy(Server* s);
 // Upper bound of the device bytes a problem of this size holds (mesh tables,
 // vectors, the state storage plan under `budget`, traces) plus the request's
 // own buffers.
-size_t job_device_bytes(const Mesh& m, int prec, int64_t nt, int nrec, size_t budget, int nshot = 1);
+size_t job_device_bytes(const Mesh& m, int prec, int64_t nt, int nrec, size_t budget, int nshot = 1,
+                        int64_t n_bnd = -1);
 
 }  // namespace kmv

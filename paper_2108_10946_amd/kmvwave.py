@@ -56,7 +56,7 @@ class kmv_request(C.Structure):
                 ("c", C.POINTER(C.c_double)), ("eta", C.POINTER(C.c_double)), ("xs", C.POINTER(C.c_double)),
                 ("n_src", C.c_int), ("f0", C.c_double), ("t0", C.c_double), ("amp", C.c_double),
                 ("xr", C.POINTER(C.c_double)), ("n_rec", C.c_int), ("forward_only", C.c_int),
-                ("observed", C.c_void_p), ("n_shots", C.c_int)]
+                ("observed", C.c_void_p), ("n_shots", C.c_int), ("absorbing", C.c_int)]
 
 
 class kmv_result(C.Structure):
@@ -319,7 +319,7 @@ def kmv_server_create(mem_budget=0, max_slots=4):
 
 
 def kmv_server_submit(s, mesh, precision, dt, n_steps, c, xs, xr, f0, t0, amp=1.0, eta=None,
-                      observed=None, forward_only=False):
+                      observed=None, forward_only=False, absorbing=False):
     """Queue one request.  xs is [n_src, dim] for one shot or [n_shots, n_src, dim]
     for several (observed then [n_shots, n_steps, n_rec]).  Host inputs are copied
     before this returns."""
@@ -336,7 +336,7 @@ def kmv_server_submit(s, mesh, precision, dt, n_steps, c, xs, xr, f0, t0, amp=1.
             raise ValueError("observed must hold n_shots * n_steps * n_rec values")
     req = kmv_request(mesh, precision, dt, n_steps, _dptr(c), None if eta is None else _dptr(eta), _dptr(xs),
                       len(xs), f0, t0, amp, _dptr(xr), len(xr), 1 if forward_only else 0,
-                      None if obs is None else obs.ctypes.data_as(C.c_void_p), n_shots)
+                      None if obs is None else obs.ctypes.data_as(C.c_void_p), n_shots, 1 if absorbing else 0)
     t = C.c_uint64()
     _check(lib().kmv_server_submit(s, C.byref(req), C.byref(t)))
     return t.value

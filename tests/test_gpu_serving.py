@@ -239,3 +239,42 @@ def test_multi_shot_request(prec):
         assert abs(r["J"] - J_or) < 1e-10 * J_or
         assert rel_l2(r["traces"], np.stack(tr_or)) < 1e-10
         assert rel_l2(r["grad"], g_or[p]) < 1e-10
+
+
+def test_absorbing_request_matches_problem_api_and_oracle():
+    """A request with the absorbing boundary on equals the Problem call with it on
+    (bitwise) and the oracle (FP64, 1e-10); its memory estimate covers the records."""
+    from paper_2108_10946_amd import Mesh, Problem, Server
+    coords, cells = configs.small_tri(8, seed=1)
+    k, nt = 2, 240
+    d = Discretization(coords, cells, k)
+    c_true = d.nodal_values(lambda x, z: 1.5 + 0.4 * z + 0.1 * np.sin(6 * x))
+    c0 = d.nodal_values(lambda x, z: 1.5 + 0.4 * z)
+    dt = 0.8 * solver.cfl_dt_gershgorin(d.stiffness(c_true), d.lumped_mass())
+    src, rec = np.array([[0.5, 0.2]]), np.stack([np.linspace(0.1, 0.9, 6), np.full(6, 0.1)], axis=1)
+    sh = solver.Shot(d, src, rec, dt, nt, f0=8.0, t0=0.1)
+    dobs, _ = sh.forward(c_true, absorb=True)
+    J, g, tr = sh.misfit_gradient(c0, dobs, absorb=True)
+    m = Mesh(coords, cells, k)
+    p = dof_map(m.dof_coords(), d.dof_coords)
+    say("serving: absorbing-boundary request vs Problem and oracle")
+    srv = Server(max_slots=2)
+    t_on = srv.submit(m, c0[p], src, rec, dt, nt, precision="fp64", observed=dobs, f0=8.0, t0=0.1, absorbing=True)
+    t_off = srv.submit(m, c0[p], src, rec, dt, nt, precision="fp64", observed=dobs, f0=8.0, t0=0.1)
+    r, r_off = srv.result(t_on), srv.result(t_off)
+    srv.close()
+    assert r["status"] == 0 and r_off["status"] == 0
+    assert r["device_bytes"] > r_off["device_bytes"]
+    assert abs(r["J"] - J) < 1e-10 * J
+    assert rel_l2(r["traces"], tr) < 1e-10
+    assert rel_l2(r["grad"], g[p]) < 1e-10
+    prob = Problem(m, dt, nt, precision="fp64")
+    prob.set_absorbing_boundary(True)
+    prob.set_sources(src, f0=8.0, t0=0.1)
+    prob.set_receivers(rec)
+    cuda = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    Jd, gd, trd = prob.misfit_gradient(cuda(c0[p]), cuda(dobs), keep_traces=True)
+    prob.close()
+    assert Jd == r["J"]
+    assert np.array_equal(gd.cpu().numpy(), r["grad"])
+    assert np.array_equal(trd.cpu().numpy(), r["traces"])
