@@ -11,7 +11,11 @@ of c phi_i phi_j in the damping matrix M_{u,1} of the appendix).
   by central differences of the oracle's own J (not by its formula); the same
   check without the boundary term must fail, so the term is what makes it pass.
 * Energy: with no sponge and the source off, the discrete energy is conserved
-  without the term and decays with it."""
+  without the term and decays with it.
+* Reflection: a plane pulse meeting the boundary head-on is reflected whole by the
+  Neumann boundary and almost not at all with the term (the first-order condition
+  is exact at normal incidence); a damping off by a factor alpha would reflect
+  |1 - alpha| / (1 + alpha), 1/3 for alpha = 2 or 1/2."""
 import numpy as np
 import pytest
 
@@ -119,3 +123,25 @@ def test_boundary_term_dissipates_energy(kind):
     assert np.ptp(E[False]) < 1e-9 * E[False][0]
     assert np.all(np.diff(E[True]) <= 1e-12 * E[True][0])
     assert E[True][-1] < 0.5 * E[True][0]
+
+
+def test_boundary_term_absorbs_a_normally_incident_plane_wave():
+    coords, cells = configs.structured_tri(40, 40, 0.0, 2.0, 0.0, 2.0)
+    d = Discretization(coords, cells, 2)
+    x, z = d.dof_coords.T
+    c = np.full(d.n_dofs, 1.5)
+    K, M = d.stiffness(c), d.lumped_mass()
+    dt = 0.8 * solver.cfl_dt_gershgorin(K, M)
+    pulse = lambda xx: np.exp(-((xx - 1.2) / 0.08) ** 2)
+    u0, um1 = pulse(x), pulse(x + 1.5 * dt)  # u(x, t) = pulse(x - c t), moving to x = 2
+    nt = int(np.ceil(1.0 / dt))              # out to x = 2 and back to x ~ 1.3
+    band = (np.abs(z - 1.0) < 0.3) & (x < 1.6)  # away from the grazing top and bottom sides
+
+    def reflected(alpha):
+        a = None if alpha == 0 else alpha * dt * c * d.boundary_mass() / (2.0 * M)
+        _, st = solver.forward(K, M, a, dt, nt, lambda n: None, u0=u0, um1=um1, keep_states=True)
+        return np.abs(st[-1][band]).max()
+
+    assert reflected(0) > 0.95          # Neumann: the pulse comes back whole
+    assert reflected(1.0) < 0.08        # the boundary term: almost nothing comes back
+    assert reflected(2.0) > 0.2 and reflected(0.5) > 0.2  # a wrong scale reflects ~1/3
