@@ -977,6 +977,12 @@ Status set_absorbing_boundary(Problem* p, bool on) {
     p->d_bnd_part = nullptr;
   }
   p->absorb = on;
+  if (!on) {  // the records are kept only while the term is on
+    dfree(p->d_ub);
+    dfree(p->d_lb);
+    p->d_ub = p->d_lb = nullptr;
+    p->bnd_rec_bytes = 0;
+  }
   return upload_coefficients(p);
 }
 

@@ -138,3 +138,32 @@ def test_absorbing_boundary_off_again_is_neumann():
     plain, on, off = run([]), run([True]), run([True, False])
     assert np.array_equal(plain, off)
     assert rel_l2(on, plain) > 1e-3
+
+
+@pytest.mark.parametrize("kind,k", [("tri", 3), ("tet", 2)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_absorbing_boundary_adjoint_dot_product(kind, k, prec):
+    """kmv_adjoint with the term on is the transpose of the forward:
+    <y, P u(w)> = dt^2 sum_n w_n s . lambda^{n+1}(y), with the boundary damping
+    rebuilt from the same c in both solves (FP64 1e-12, FP32 1e-5)."""
+    from paper_2108_10946_amd import Mesh, Problem
+    coords, cells, d, c_true, c0, eta, xs, xr, f0, patch, dt, nt = case(kind, k, True, 1)
+    m = Mesh(coords, cells, k, patch_cells=patch)
+    p = dof_map(m.dof_coords(), d.dof_coords)
+    say(f"absorbing boundary: dot product {kind} k={k} {prec}")
+    prob = Problem(m, dt, nt, precision=prec)
+    prob.set_damping(eta[p])
+    prob.set_absorbing_boundary(True)
+    prob.set_sources(xs[0], f0=f0, t0=0.1)
+    rng = np.random.default_rng(11)
+    w = rng.standard_normal(nt)
+    prob.set_source_wavelet(w)
+    prob.set_receivers(xr)
+    c = cuda(c0[p])
+    tr_f = prob.forward(c).double().cpu().numpy()
+    y = rng.standard_normal((nt, len(xr)))
+    _, st = prob.adjoint(c, cuda(y, prob.dtype), src_trace=True)
+    prob.close()
+    lhs = np.sum(y * tr_f)
+    rhs = dt * dt * np.sum(w * st.double().cpu().numpy()[:, 0])
+    assert abs(lhs - rhs) < (1e-12 if prec == "fp64" else 1e-5) * abs(lhs)
