@@ -52,6 +52,18 @@ __global__ void __launch_bounds__(kBlock) k_gather_levels(const T* __restrict__ 
 }
 
 template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gather_ring(const T* __restrict__ ring, int K, int64_t slot_stride,
+                                                        int64_t ls, int ns, int64_t n0, int cnt, int nbd,
+                                                        const int32_t* __restrict__ dof, T* __restrict__ out,
+                                                        int64_t out_stride) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= (int64_t)ns * cnt * nbd) return;
+  const int64_t t = i % nbd, r = i / nbd;  // r = sh*cnt + j
+  const int64_t sh = r / cnt, n = n0 + (r - sh * cnt);
+  out[sh * out_stride + n * nbd + t] = ring[(n % K) * slot_stride + sh * ls + dof[t]];
+}
+
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_absorb_part(const T* __restrict__ ub, const T* __restrict__ lb, int64_t nt,
                                                         int nbd, int ns, int nchunk, double* __restrict__ part) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -111,6 +123,15 @@ hipError_t launch_gather_levels(const T* levels, int64_t level_stride, int64_t l
 }
 
 template <typename T>
+hipError_t launch_gather_ring(const T* ring, int K, int64_t slot_stride, int64_t ls, int ns, int64_t n0, int cnt,
+                              int nbd, const int32_t* dof, T* out, int64_t out_stride, hipStream_t s) {
+  if (nbd == 0 || ns == 0 || cnt <= 0) return hipSuccess;
+  k_gather_ring<T><<<blocks((int64_t)ns * cnt * nbd), kBlock, 0, s>>>(ring, K, slot_stride, ls, ns, n0, cnt, nbd,
+                                                                      dof, out, out_stride);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_absorb_grad(const T* ub, const T* lb, int64_t nt, int nbd, int ns, const int32_t* dof,
                               const double* hb, double* part, int nchunk, double* g, hipStream_t s) {
   if (nbd == 0 || nt < 1) return hipSuccess;
@@ -128,6 +149,8 @@ hipError_t launch_absorb_grad(const T* ub, const T* lb, int64_t nt, int nbd, int
                                                 hipStream_t);                                                  \
   template hipError_t launch_gather_levels<T>(const T*, int64_t, int64_t, int, int64_t, int, const int32_t*, T*, \
                                               hipStream_t);                                                    \
+  template hipError_t launch_gather_ring<T>(const T*, int, int64_t, int64_t, int, int64_t, int, int,          \
+                                            const int32_t*, T*, int64_t, hipStream_t);                         \
   template hipError_t launch_absorb_grad<T>(const T*, const T*, int64_t, int, int, const int32_t*,            \
                                             const double*, double*, int, double*, hipStream_t);
 KMV_BOUNDARY_INST(float)

@@ -16,6 +16,8 @@ namespace kmv {
 
 // Ordered partial sums over time of the gradient term (one chunk of steps each).
 constexpr int kBndChunks = 64;
+// Adjoint levels kept in the ring while the term is on.
+constexpr int kLamRing = 8;
 
 // beta, gamma of the boundary DOFs (and their per-ref copies) from c:
 // coef[3t..3t+2] = (eta_i dt/2, dt b_i/(2 M_i), dt^2/M_i) of boundary DOF t = dof[t];
@@ -34,6 +36,13 @@ hipError_t launch_gather_boundary(const T* lvl, int64_t ls, int ns, int nbd, con
 template <typename T>
 hipError_t launch_gather_levels(const T* levels, int64_t level_stride, int64_t ls, int ns, int64_t nlev, int nbd,
                                 const int32_t* dof, T* out, hipStream_t s);
+
+// Levels n0 .. n0+cnt-1 of a ring of K levels (level n in slot n % K, slots
+// slot_stride apart, shots ls apart within a slot):
+// out[sh*out_stride + n*nbd + t] = ring[(n % K)*slot_stride + sh*ls + dof[t]].
+template <typename T>
+hipError_t launch_gather_ring(const T* ring, int K, int64_t slot_stride, int64_t ls, int ns, int64_t n0, int cnt,
+                              int nbd, const int32_t* dof, T* out, int64_t out_stride, hipStream_t s);
 
 // g[dof[t]] += hb[t] * sum_sh sum_{n=1}^{nt} lb[sh][n][t] (ub[sh][n][t] - ub[sh][n-2][t])
 // with rows [sh][n] of nbd values, n = 0..nt (ub row 0 = u^0 = 0; u^{-1} = 0); the sum

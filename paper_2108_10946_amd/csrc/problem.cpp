@@ -572,27 +572,35 @@ Status plan_storage(Problem* p) {
   return ensure_slots(p, seg + 1);
 }
 
-// One reverse launch m (lambda^{m+1} -> lambda^m); uf = u^m when grad.
+// Adjoint level lvl's vector: the two buffers by parity, or slot lvl % lam_k of the ring.
+template <typename T>
+T* lam_ptr(Problem* p, int64_t lvl) {
+  if (p->lam_k > 2) return (T*)p->d_lam_ring + (lvl % p->lam_k) * p->ls * p->nshot;
+  return (T*)p->d_lam[lvl & 1];
+}
+
+// One reverse launch m (lambda^{m+1} -> lambda^m, finishing level m+1 from level m+2);
+// uf = u^m when grad.
 template <typename T>
 Status adjoint_launch(Problem* p, int64_t m, bool grad, const T* adj_rows, const T* uf, hipStream_t s) {
   const double inv_dt2 = 1.0 / (p->dt * p->dt);
-  T* lam_in = (T*)p->d_lam[(m + 1) & 1];
-  T* lam_out = (T*)p->d_lam[m & 1];
-  return step<T>(p, p->adj, grad, m != p->nt, lam_in, lam_out, lam_out, adj_par(m), &p->rec,
-                 adj_rows + (m - 1) * p->rec.npts, 1, p->nt * p->rec.npts, (T)inv_dt2, uf, nullptr, s);
+  return step<T>(p, p->adj, grad, m != p->nt, lam_ptr<T>(p, m + 1), lam_ptr<T>(p, m + 2), lam_ptr<T>(p, m),
+                 adj_par(m), &p->rec, adj_rows + (m - 1) * p->rec.npts, 1, p->nt * p->rec.npts, (T)inv_dt2, uf,
+                 nullptr, s);
 }
 
 template <typename T>
 Status adjoint_start(Problem* p, hipStream_t s) {
-  STTRY(zero_level<T>(p, p->adj, (T*)p->d_lam[(p->nt + 1) & 1], (int)((p->nt + 1) & 1), s));
-  HIPTRY(launch_fill<T>((T*)p->d_lam[p->nt & 1], T(0), p->ls * p->nshot, s));
+  STTRY(zero_level<T>(p, p->adj, lam_ptr<T>(p, p->nt + 1), (int)((p->nt + 1) & 1), s));
+  HIPTRY(launch_fill<T>(lam_ptr<T>(p, p->nt), T(0), p->ls * p->nshot, s));
+  if (p->lam_k > 2) HIPTRY(launch_fill<T>(lam_ptr<T>(p, p->nt + 2), T(0), p->ls * p->nshot, s));
   return OK;
 }
 
 // After launch 1: finish lambda^1 (level 1) from level 2 and launch 1's partials.
 template <typename T>
 Status adjoint_end(Problem* p, bool grad, hipStream_t s) {
-  return finish<T>(p, p->adj, grad, (const T*)p->d_lam[0], (T*)p->d_lam[1], adj_par(0), s);
+  return finish<T>(p, p->adj, grad, lam_ptr<T>(p, 2), lam_ptr<T>(p, 1), adj_par(0), s);
 }
 
 template <typename T>
@@ -628,11 +636,19 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
   } else {
     STTRY(run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n & 1); }, traces, true, s, ub));
   }
-  // lambda^lvl is complete once reverse launch lvl-1 has run (lambda^1 after the end)
-  auto record_lam = [&](int64_t lvl) -> Status {
-    if (!lb) return OK;
-    HIPTRY(launch_gather_boundary<T>((const T*)p->d_lam[lvl & 1], p->ls, p->nshot, p->nbd, p->d_bnd_dof,
-                                     lb + lvl * p->nbd, (p->nt + 1) * p->nbd, s));
+  // lambda^lvl is complete once reverse launch lvl-1 has run (lambda^1 after the end).
+  // The ring keeps lam_k levels, so complete levels lo..top are recorded in one launch
+  // just before the oldest of them would be overwritten.
+  if (lb && p->lam_k != kLamRing) {
+    STTRY(alloc(&p->d_lam_ring, (size_t)kLamRing * p->ls * p->nshot * sizeof(T)));
+    p->lam_k = kLamRing;
+  }
+  int64_t lam_top = p->nt;  // highest level not yet recorded
+  auto record_lam = [&](int64_t lo) -> Status {  // levels lo..lam_top are complete
+    if (!lb || lo > lam_top) return OK;
+    HIPTRY(launch_gather_ring<T>(lam_ptr<T>(p, 0), p->lam_k, p->ls * p->nshot, p->ls, p->nshot, lo,
+                                 (int)(lam_top - lo + 1), p->nbd, p->d_bnd_dof, lb, (p->nt + 1) * p->nbd, s));
+    lam_top = lo - 1;
     return OK;
   };
   HIPTRY(launch_misfit<T>(traces, obs, (T*)p->d_resid, p->nt * p->rec.npts * p->nshot, p->d_red,
@@ -646,7 +662,8 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
     const bool g = mm % r == 0;
     STTRY(adjoint_launch<T>(p, mm, g, resid, g ? uf : nullptr, s));
     if (g && r > 1) STTRY(pair_finish<T>(p, adj_par(mm), s));
-    if (mm + 1 <= p->nt) STTRY(record_lam(mm + 1));
+    // the next launch overwrites level mm + lam_k - 1
+    if (lb && (lam_top >= mm + kLamRing - 1 || mm == 1)) STTRY(record_lam(mm + 1));
     return OK;
   };
   if (p->store_all) {
@@ -696,7 +713,7 @@ Status adjoint_t(Problem* p, const double* c, const T* adj, T* lambda_out, T* sr
   // shot sh samples its own sources: points [sh*nps, (sh+1)*nps) of the table
   const int nps = p->src.npts / p->nshot;
   auto record = [&](int64_t lvl) -> Status {  // level lvl is complete: row lvl-1
-    const T* lam = (const T*)p->d_lam[lvl & 1];
+    const T* lam = lam_ptr<T>(p, lvl);
     if (lambda_out) HIPTRY(hipMemcpyAsync(lambda_out + (lvl - 1) * N, lam, vb, hipMemcpyDeviceToDevice, s));
     if (src_trace)
       for (int sh = 0; sh < p->nshot; ++sh) {
@@ -830,7 +847,7 @@ Status alloc_sweep(Sweep& S, const Mesh& m, size_t ts, bool with_r, int nshot) {
 Problem::~Problem() {
   for (void* q : {(void*)d_lmap, d_geom, (void*)d_cell_start, (void*)d_own_start, (void*)d_sh_start,
                   (void*)d_sh_idx, (void*)d_shp_ptr, (void*)d_shp_slot, (void*)d_ref_slots, (void*)d_gword,
-                  (void*)d_glist, (void*)d_gword_off, (void*)d_glist_off, (void*)d_damp_patch, d_gamma, d_gdet, d_beta, d_c2, d_c2_ref, d_gamma_ref, d_beta_ref, d_minv_sqrt, d_lam[0], d_lam[1], (void*)d_gacc, (void*)d_red, d_slots,
+                  (void*)d_glist, (void*)d_gword_off, (void*)d_glist_off, (void*)d_damp_patch, d_gamma, d_gdet, d_beta, d_c2, d_c2_ref, d_gamma_ref, d_beta_ref, d_minv_sqrt, d_lam[0], d_lam[1], d_lam_ring, (void*)d_gacc, (void*)d_red, d_slots,
                   d_ck_u, d_ck_du, d_resid, d_traces_tmp, d_wavelet, (void*)d_bnd_dof, (void*)d_bnd_ref,
                   (void*)d_bnd_coef, (void*)d_bnd_hb, d_ub, d_lb, (void*)d_bnd_part})
     dfree(q);

@@ -116,6 +116,10 @@ struct Problem {
   // sweeps
   Sweep fwd, adj;
   void* d_lam[2] = {nullptr, nullptr};
+  // With the absorbing boundary's records the adjoint levels rotate through a ring of
+  // lam_k levels instead (lam_k - 1 complete levels recorded per gather launch).
+  void* d_lam_ring = nullptr;
+  int lam_k = 2;
   double* d_gacc = nullptr;
   double* d_red = nullptr;      // reduction scratch
   int red_blocks = 256;

@@ -10,6 +10,8 @@
 // is bitwise the one the request gets alone.
 #include "server.hpp"
 
+#include "boundary.hpp"
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -168,7 +170,10 @@ size_t job_device_bytes(const Mesh& m, int prec, int64_t nt, int nrec, size_t bu
   b += 2 * rows * ts + (size_t)nt * ts + (size_t)(nrec + 8 * S) * m.nd * 16 + S * (np + 1) * 4;
   b += 2 * N * 8 + 2 * rows * ts;
   // absorbing boundary (n_bnd >= 0): coefficient tables, u and lambda records, partial sums
-  if (n_bnd >= 0) b += (size_t)n_bnd * (2 * S * (nt + 1) * ts + 4 * 8 + 4 + 64 * 8) + 2 * N * ts + 4096;
+  // and the ring of adjoint levels those records are taken from
+  if (n_bnd >= 0)
+    b += (size_t)n_bnd * (2 * S * (nt + 1) * ts + 4 * 8 + 4 + kBndChunks * 8) + 2 * N * ts +
+         (size_t)kLamRing * (N + refs) * ts * S + 4096;
   // allocation granularity
   return b + (b >> 4) + ((size_t)4 << 20);
 }
