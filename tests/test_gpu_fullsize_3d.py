@@ -5,7 +5,9 @@ accumulation, checkpointed reverse sweep.
 
 The oracle cannot assemble this operator in reasonable time, so full-size checks
 are properties that hold at any size: the dot-product identity of the adjoint
-and central differences of the misfit along a smooth seeded direction.  Oracle
+and central differences of the misfit along a smooth seeded direction, also with
+the absorbing boundary term on (its damping acts at the top surface next to the
+source from the first steps).  Oracle
 parity of the same kernels in 3D runs on small tetrahedral meshes
 (test_gpu_parity.py)."""
 import numpy as np
@@ -99,4 +101,44 @@ def test_checkpointed_gradient_central_differences_3d(c5):
     fd = (float(fwi_misfit(cuda(c + h * d), prob, obs)) - float(fwi_misfit(cuda(c - h * d), prob, obs))) / (2 * h)
     say(f"  J {float(J):.6e} fd {fd:.6e} an {an:.6e} rel {abs(fd - an) / abs(an):.2e}")
     assert prob.info()["checkpoint_every"] == 25
+    assert abs(fd - an) < 1e-2 * abs(an)
+
+
+def test_absorbing_boundary_3d(c5):
+    """Absorbing boundary on, FP32 fields, checkpoints every 25 steps: the adjoint's
+    dot-product identity, and the gradient (boundary term included) against central
+    differences along a direction concentrated at the top surface near the source."""
+    from paper_2108_10946_amd import Problem
+    w, m, x, c, eta, dt = c5
+    nt, h = 300, 1e-3
+    say("3D full size: absorbing boundary, dot product and central differences, FP32")
+    prob = Problem(m, dt, nt, precision="fp32", checkpoint_every=25)
+    prob.set_damping(eta)
+    prob.set_absorbing_boundary(True)
+    prob.set_sources(w.sources, f0=w.f0, t0=0.05)
+    rng = np.random.default_rng(23)
+    wav = rng.standard_normal(nt)
+    prob.set_source_wavelet(wav)
+    prob.set_receivers(w.receivers)
+    cd = cuda(c)
+    tr = prob.forward(cd).double().cpu().numpy()
+    y = rng.standard_normal((nt, len(w.receivers)))
+    _, st = prob.adjoint(cd, cuda(y, prob.dtype), src_trace=True)
+    lhs = np.sum(y * tr)
+    rhs = dt * dt * np.sum(wav * st.double().cpu().numpy()[:, 0])
+    say(f"  dot: lhs {lhs:.9e} rhs {rhs:.9e} rel {abs(lhs - rhs) / abs(lhs):.2e}")
+    assert abs(lhs - rhs) < 1e-5 * abs(lhs)
+    prob.set_sources(w.sources, f0=w.f0, t0=0.05)  # back to the Ricker wavelet
+    bump = np.exp(-((x[:, 0] - 2.0) ** 2 + (x[:, 1] - 2.0) ** 2 + (x[:, 2] - 0.15) ** 2) / 0.01)
+    obs = prob.forward(cuda(c * (1.0 + 0.1 * bump)))
+    d = np.exp(-((x[:, 0] - 2.1) ** 2 + (x[:, 1] - 1.9) ** 2 + x[:, 2] ** 2) / 0.02)
+    d[eta > 0] = 0.0
+    d /= np.abs(d).max()
+    J, g, _ = prob.misfit_gradient(cd, obs)
+    an = float(g.cpu().numpy() @ d)
+    Jp, _, _ = prob.misfit_gradient(cuda(c + h * d), obs)
+    Jm, _, _ = prob.misfit_gradient(cuda(c - h * d), obs)
+    fd = (Jp - Jm) / (2 * h)
+    say(f"  J {J:.6e} fd {fd:.6e} an {an:.6e} rel {abs(fd - an) / abs(an):.2e}")
+    prob.close()
     assert abs(fd - an) < 1e-2 * abs(an)
