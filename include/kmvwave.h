@@ -181,8 +181,15 @@ int kmv_set_absorbing_boundary(kmv_problem p, int enable);
  * Errors: KMV_EOUTSIDE, KMV_EINVAL. */
 int kmv_set_sources(kmv_problem p, const double* xs, int n_src, double f0, double t0,
                     double amp);
-/* Replace the wavelet by w[n_steps] (host). */
+/* Replace the wavelet by w[n_steps] (host), the same for every shot.
+ * Errors: KMV_EINVAL (NULL), KMV_ESTATE (no sources set yet). */
 int kmv_set_source_wavelet(kmv_problem p, const double* w);
+/* One wavelet per shot: w[n_shots*n_steps] (host, shot-major), shot s firing
+ * w[s*n_steps + n] at t_n = n dt.  The paper fires every shot with the same Ricker
+ * wavelet; this is for shots that differ in their signature (or polarity) within
+ * one multi-shot problem.  kmv_set_sources or kmv_set_source_wavelet go back to one
+ * shared wavelet.  Errors: KMV_EINVAL (NULL), KMV_ESTATE (no sources set yet). */
+int kmv_set_source_wavelets(kmv_problem p, const double* w);
 /* Receivers x_r [n_rec*dim]: d^n_j = sum_a phi_a(x_j) u^n_{g(e_j,a)}.
  * Errors: KMV_EOUTSIDE. */
 int kmv_set_receivers(kmv_problem p, const double* xr, int n_rec);

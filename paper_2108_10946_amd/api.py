@@ -110,7 +110,16 @@ class Problem:
         self.n_src = len(xs)
 
     def set_source_wavelet(self, w):
-        K.kmv_set_source_wavelet(self.handle, w)
+        """w: [n_steps] for every shot, or [n_shots, n_steps], one wavelet per shot."""
+        w = np.asarray(w, dtype=np.float64)
+        if w.ndim not in (1, 2) or w.shape[-1] != self.n_steps:
+            raise ValueError(f"wavelet must be [n_steps] or [n_shots, n_steps] with n_steps = {self.n_steps}")
+        if w.ndim == 2:
+            if w.shape[0] != self.n_shots:
+                raise ValueError(f"per-shot wavelets need {self.n_shots} rows, got {w.shape[0]}")
+            K.kmv_set_source_wavelets(self.handle, w)
+        else:
+            K.kmv_set_source_wavelet(self.handle, w)
 
     def set_receivers(self, xr):
         xr = np.atleast_2d(np.asarray(xr, dtype=np.float64))

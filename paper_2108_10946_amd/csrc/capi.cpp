@@ -206,6 +206,14 @@ int kmv_set_sources(kmv_problem h, const double* xs, int n_src, double f0, doubl
   });
 }
 
+int kmv_set_source_wavelets(kmv_problem h, const double* w) {
+  return guarded([&]() {
+    if (!h || !w) return fail(KMV_EINVAL, "NULL argument");
+    if (!h->p->has_src) return fail(KMV_ESTATE, "set the source points first");
+    return done(kmv::set_wavelets(h->p, w));
+  });
+}
+
 int kmv_set_source_wavelet(kmv_problem h, const double* w) {
   return guarded([&]() {
     if (!h || !w) return fail(KMV_EINVAL, "NULL argument");

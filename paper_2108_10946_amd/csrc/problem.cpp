@@ -496,7 +496,8 @@ Status run_forward(Problem* p, int64_t n0, int64_t n1, F slot_of, T* traces, boo
     }
     T* row = (traces && n >= 1) ? traces + (n - 1) * p->rec.npts : nullptr;
     STTRY(step<T>(p, S, false, !fresh, slot_of(n), n > n0 ? slot_of(n - 1) : nullptr, slot_of(n + 1),
-                  fwd_par(n), &p->src, (const T*)p->d_wavelet + n, 0, 0, T(1), nullptr, row, s));
+                  fwd_par(n), &p->src, (const T*)p->d_wavelet + n, 0, p->wavelet_per_shot ? p->nt : 0, T(1),
+                  nullptr, row, s));
     fresh = false;
     if (ub) STTRY(record(n));
   }
@@ -1018,6 +1019,16 @@ Status set_damping(Problem* p, const double* eta) {
 Status set_wavelet(Problem* p, const double* w) {
   DeviceGuard dg(p->device);
   p->wavelet.assign(w, w + p->nt);
+  p->wavelet_per_shot = false;
+  return upload_real(&p->d_wavelet, p->wavelet, p->prec);
+}
+
+// One wavelet per shot, shot-major [n_shots][nt]: the forward launch offsets the
+// amplitude pointer by shot * nt, as it offsets the other per-shot buffers.
+Status set_wavelets(Problem* p, const double* w) {
+  DeviceGuard dg(p->device);
+  p->wavelet.assign(w, w + p->nt * p->nshot);
+  p->wavelet_per_shot = true;
   return upload_real(&p->d_wavelet, p->wavelet, p->prec);
 }
 

@@ -135,7 +135,8 @@ struct Problem {
   // sources / receivers
   bool has_src = false;
   PointTables src, rec;
-  void* d_wavelet = nullptr;    // [nt]
+  void* d_wavelet = nullptr;    // [nt], or [n_shots][nt] when wavelet_per_shot
+  bool wavelet_per_shot = false;
   std::vector<double> wavelet;
 
   ~Problem();
@@ -147,6 +148,7 @@ Status set_damping(Problem* p, const double* eta);
 Status set_absorbing_boundary(Problem* p, bool on);
 Status set_sources(Problem* p, const double* xs, int nsrc, double f0, double t0, double amp);
 Status set_wavelet(Problem* p, const double* w);
+Status set_wavelets(Problem* p, const double* w);
 Status set_receivers(Problem* p, const double* xr, int nrec);
 Status forward(Problem* p, const double* c_dev, void* traces_dev, hipStream_t s);
 Status misfit_gradient(Problem* p, const double* c_dev, const void* obs_dev, double* J,

@@ -31,7 +31,7 @@ DECLARED = [
     "kmv_mesh_dof_coords", "kmv_mesh_lumped_mass", "kmv_mesh_cell_dofs", "kmv_mesh_validate",
     "kmv_mesh_destroy",
     "kmv_problem_create", "kmv_cfl_dt", "kmv_spectral_radius", "kmv_set_damping", "kmv_set_absorbing_boundary",
-    "kmv_set_sources", "kmv_set_source_wavelet", "kmv_set_receivers", "kmv_forward",
+    "kmv_set_sources", "kmv_set_source_wavelet", "kmv_set_source_wavelets", "kmv_set_receivers", "kmv_forward",
     "kmv_misfit_gradient", "kmv_adjoint", "kmv_stiffness_apply", "kmv_problem_info", "kmv_problem_num_shots",
     "kmv_profile_enable", "kmv_profile_read", "kmv_problem_destroy",
     "kmv_server_create", "kmv_server_submit", "kmv_server_poll", "kmv_server_wait",
@@ -99,6 +99,7 @@ def lib():
         "kmv_set_absorbing_boundary": (C.c_int, [_P, C.c_int]),
         "kmv_set_sources": (C.c_int, [_P, _D, C.c_int, C.c_double, C.c_double, C.c_double]),
         "kmv_set_source_wavelet": (C.c_int, [_P, _D]),
+        "kmv_set_source_wavelets": (C.c_int, [_P, _D]),
         "kmv_set_receivers": (C.c_int, [_P, _D, C.c_int]),
         "kmv_forward": (C.c_int, [_P, _P, _P, _P]),
         "kmv_misfit_gradient": (C.c_int, [_P, _P, _P, _D, _P, _P, _P]),
@@ -266,6 +267,11 @@ def kmv_set_sources(p, xs, f0, t0, amp=1.0):
 def kmv_set_source_wavelet(p, w):
     w = np.ascontiguousarray(w, dtype=np.float64)
     _check(lib().kmv_set_source_wavelet(p, _dptr(w)))
+
+
+def kmv_set_source_wavelets(p, w):
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    _check(lib().kmv_set_source_wavelets(p, _dptr(w)))
 
 
 def kmv_set_receivers(p, xr):

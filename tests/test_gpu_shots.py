@@ -184,3 +184,50 @@ def test_shots_argument_errors():
     with pytest.raises(K.KMVError) as e:
         Problem(m, dt, nt, precision="fp32", n_shots=2000)
     assert e.value.code == K.KMV_EINVAL
+
+
+@pytest.mark.parametrize("kind", ["tri", "tet"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_per_shot_wavelets(kind, prec):
+    """kmv_set_source_wavelets: each shot fires its own wavelet (here Ricker pulses
+    of different delay, frequency and polarity).  Each shot's traces are bitwise those
+    of a one-shot problem given that wavelet; J and the gradient are the sums (1e-12)."""
+    m, c_true, c0, eta, dt, nt, f0, xs, xr = case(kind)
+    S = len(xs)
+    t = np.arange(nt) * dt
+    rng = np.random.default_rng(29)
+    waves = []
+    for s in range(S):
+        f, t0, sgn = f0 * rng.uniform(0.8, 1.2), rng.uniform(0.08, 0.14), rng.choice([-1.0, 1.0])
+        a = (np.pi * f * (t - t0)) ** 2
+        waves.append(sgn * (1 - 2 * a) * np.exp(-a))
+    waves = np.stack(waves)
+    say(f"shots: per-shot wavelets {kind} {prec} S={S}")
+    pb = problem(m, dt, nt, prec, eta, f0, xs, xr)
+    pb.set_source_wavelet(waves)
+    obs = pb.forward(cuda(c_true))
+    Jb, gb, trb = pb.misfit_gradient(cuda(c0), obs, keep_traces=True)
+    Js, gs = [], []
+    for s in range(S):
+        p1 = problem(m, dt, nt, prec, eta, f0, xs[s], xr)
+        p1.set_source_wavelet(waves[s])
+        o1 = p1.forward(cuda(c_true))
+        assert torch.equal(o1, obs[s]), f"forward traces of shot {s} differ from its one-shot problem"
+        J1, g1, tr1 = p1.misfit_gradient(cuda(c0), o1, keep_traces=True)
+        assert torch.equal(tr1, trb[s]), f"misfit traces of shot {s} differ"
+        Js.append(J1)
+        gs.append(g1.cpu().numpy())
+        p1.close()
+    # a shared wavelet again: every shot fires waves[0]
+    pb.set_source_wavelet(waves[0])
+    o_shared = pb.forward(cuda(c_true))
+    p0 = problem(m, dt, nt, prec, eta, f0, xs[1], xr)
+    p0.set_source_wavelet(waves[0])
+    assert torch.equal(p0.forward(cuda(c_true)), o_shared[1])
+    p0.close()
+    with pytest.raises(ValueError):
+        pb.set_source_wavelet(waves[:, :-1])
+    pb.close()
+    gsum = np.sum(gs, axis=0)
+    assert abs(Jb - sum(Js)) <= 1e-12 * sum(Js)
+    assert rel_l2(gb.cpu().numpy(), gsum) < 1e-12
