@@ -12,7 +12,7 @@ from synth import configs
 SOURCES = (0.25, 0.5, 0.75)  # x of the three surface shots (z = 0.05 km)
 
 
-def water_case(layout=False):
+def water_case(layout=False, absorb=False):
     coords, cells = configs.small_tri(6, seed=4)
     d = Discretization(coords, cells, 2)
     x, z = d.dof_coords[:, 0], d.dof_coords[:, 1]
@@ -23,12 +23,12 @@ def water_case(layout=False):
     dt = 0.8 * solver.cfl_dt_gershgorin(d.stiffness(c_true), M)
     rec = np.stack([np.linspace(0.1, 0.9, 12), np.full(12, 0.2)], axis=1)
     shots = [solver.Shot(d, [[xs, 0.05]], rec, dt, 220, f0=8.0, t0=0.1) for xs in SOURCES]
-    obs = [sh.forward(c_true)[0] for sh in shots]
+    obs = [sh.forward(c_true, absorb=absorb)[0] for sh in shots]
 
     def objective(c):
         J, g = 0.0, np.zeros(d.n_dofs)
         for sh, o in zip(shots, obs):
-            Js, gs, _ = sh.misfit_gradient(c, o)
+            Js, gs, _ = sh.misfit_gradient(c, o, absorb=absorb)
             J += Js
             g += gs
         return J, g

@@ -2,7 +2,8 @@
 library's FP64 misfit and gradient and by the oracle's gives the same iterates
 (misfit history and final model to 1e-9 relative: both objectives agree to
 ~1e-12, and the optimiser is deterministic), and an FP32-driven run reduces the
-misfit as much to within a few percent."""
+misfit as much to within a few percent.  The FP64 comparison also runs with the
+absorbing boundary on, as the paper's inversions do."""
 import numpy as np
 import pytest
 
@@ -21,16 +22,18 @@ def need_gpu():
     kmv.lib()
 
 
-def library_case(prec):
+def library_case(prec, absorb=False):
     from test_fwi_host import water_case, SOURCES
     from synth import configs
     from paper_2108_10946_amd import Mesh, Problem
     from paper_2108_10946_amd.fwi import library_objective
-    d, M, c0, c_true, water, oracle_objective, lay = water_case(layout=True)
+    d, M, c0, c_true, water, oracle_objective, lay = water_case(layout=True, absorb=absorb)
     coords, cells = configs.small_tri(6, seed=4)
     m = Mesh(coords, cells, 2)
     p = dof_map(m.dof_coords(), d.dof_coords)
     prob = Problem(m, lay["dt"], lay["nt"], precision=prec, n_shots=len(SOURCES))
+    if absorb:
+        prob.set_absorbing_boundary(True)
     prob.set_sources(np.array([[[xs, 0.05]] for xs in SOURCES]), f0=lay["f0"], t0=lay["t0"])
     prob.set_receivers(lay["rec"])
     obs = prob.forward(torch.as_tensor(c_true[p], dtype=torch.float64, device="cuda"))
@@ -44,10 +47,11 @@ def library_case(prec):
     return M[p], c0[p], water[p], library_objective([prob], [obs]), oracle_in_library_order, prob
 
 
-def test_fp64_inversion_matches_the_oracle_driven_run():
+@pytest.mark.parametrize("absorb", [False, True])
+def test_fp64_inversion_matches_the_oracle_driven_run(absorb):
     from paper_2108_10946_amd.fwi import invert
-    M, c0, water, lib_obj, or_obj, prob = library_case("fp64")
-    say("fwi: 4 L-BFGS iterations, FP64 library vs oracle")
+    M, c0, water, lib_obj, or_obj, prob = library_case("fp64", absorb)
+    say(f"fwi: 4 L-BFGS iterations, FP64 library vs oracle, absorbing boundary {absorb}")
     a = invert(lib_obj, c0, M, bounds=(1.0, 2.6), fixed=water, max_iter=4)
     b = invert(or_obj, c0, M, bounds=(1.0, 2.6), fixed=water, max_iter=4)
     prob.close()
