@@ -99,6 +99,12 @@ int kmv_mesh_info(kmv_mesh m, int64_t* n_dofs, int64_t* n_cells, int* n_nodes,
 int kmv_mesh_dof_coords(kmv_mesh m, double* out);
 /* Lumped mass [n_dofs] in DOF order (appendix, M_u with the KMV rule). */
 int kmv_mesh_lumped_mass(kmv_mesh m, double* out);
+/* Boundary mass [n_dofs] in DOF order: b_i = the integral over the mesh boundary
+ * (facets of one cell only) of phi_i, the row sums of the boundary integral of
+ * phi_i phi_j in the damping matrix M_{u,1} of the appendix; zero off the boundary.
+ * The absorbing boundary term (kmv_set_absorbing_boundary) damps DOF i with c_i b_i.
+ * Computed once per mesh and kept.  Host only.  Errors: KMV_EINVAL. */
+int kmv_mesh_boundary_mass(kmv_mesh m, double* out);
 /* Global DOF of every node of every input cell: out[cell*n_nodes + a], input cell
  * order, reference node order of kmv_element_tables. */
 int kmv_mesh_cell_dofs(kmv_mesh m, int64_t* out);

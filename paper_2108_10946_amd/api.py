@@ -33,6 +33,10 @@ class Mesh:
     def lumped_mass(self):
         return K.kmv_mesh_lumped_mass(self.handle)
 
+    def boundary_mass(self):
+        """b_i = integral of phi_i over the mesh boundary (the absorbing term's weights)."""
+        return K.kmv_mesh_boundary_mass(self.handle)
+
     def cell_dofs(self):
         return K.kmv_mesh_cell_dofs(self.handle)
 

@@ -110,6 +110,18 @@ int kmv_mesh_lumped_mass(kmv_mesh h, double* out) {
   return KMV_OK;
 }
 
+int kmv_mesh_boundary_mass(kmv_mesh h, double* out) {
+  return guarded([&]() {
+    if (!h || !out) return fail(KMV_EINVAL, "NULL argument");
+    const std::vector<int32_t>* d;
+    const std::vector<double>* b;
+    kmv::boundary_of(*h->m, &d, &b);
+    std::memset(out, 0, h->m->n_dofs * sizeof(double));
+    for (size_t t = 0; t < d->size(); ++t) out[(*d)[t]] = (*b)[t];
+    return (int)KMV_OK;
+  });
+}
+
 int kmv_mesh_cell_dofs(kmv_mesh h, int64_t* out) {
   if (!h || !out) return fail(KMV_EINVAL, "NULL argument");
   const kmv::Mesh& m = *h->m;

@@ -28,7 +28,7 @@ ERROR_NAMES = {0: "KMV_OK", -1: "KMV_EINVAL", -2: "KMV_ENOMEM", -3: "KMV_EDEGREE
 # every symbol include/kmvwave.h declares
 DECLARED = [
     "kmv_last_error", "kmv_element_tables", "kmv_mesh_create", "kmv_mesh_info",
-    "kmv_mesh_dof_coords", "kmv_mesh_lumped_mass", "kmv_mesh_cell_dofs", "kmv_mesh_validate",
+    "kmv_mesh_dof_coords", "kmv_mesh_lumped_mass", "kmv_mesh_boundary_mass", "kmv_mesh_cell_dofs", "kmv_mesh_validate",
     "kmv_mesh_destroy",
     "kmv_problem_create", "kmv_cfl_dt", "kmv_spectral_radius", "kmv_set_damping", "kmv_set_absorbing_boundary",
     "kmv_set_sources", "kmv_set_source_wavelet", "kmv_set_source_wavelets", "kmv_set_receivers", "kmv_forward",
@@ -89,6 +89,7 @@ def lib():
                                     C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
         "kmv_mesh_dof_coords": (C.c_int, [_P, _D]),
         "kmv_mesh_lumped_mass": (C.c_int, [_P, _D]),
+        "kmv_mesh_boundary_mass": (C.c_int, [_P, _D]),
         "kmv_mesh_cell_dofs": (C.c_int, [_P, C.POINTER(C.c_int64)]),
         "kmv_mesh_validate": (C.c_int, [_P]),
         "kmv_mesh_destroy": (C.c_int, [_P]),
@@ -195,6 +196,12 @@ def kmv_mesh_dof_coords(m, dim):
 def kmv_mesh_lumped_mass(m):
     out = np.zeros(kmv_mesh_info(m)["n_dofs"])
     _check(lib().kmv_mesh_lumped_mass(m, _dptr(out)))
+    return out
+
+
+def kmv_mesh_boundary_mass(m):
+    out = np.zeros(kmv_mesh_info(m)["n_dofs"])
+    _check(lib().kmv_mesh_boundary_mass(m, _dptr(out)))
     return out
 
 

@@ -1,7 +1,7 @@
 """CPU tests of the HIP library's host side through the C ABI (no GPU calls):
 the library loads and exports every declared symbol, its element tables, DOF
-numbering, lumped mass and Gershgorin bound agree with the oracle's independent
-construction, and its scheduling invariants and error codes hold."""
+numbering, lumped mass, boundary mass and Gershgorin bound agree with the oracle's
+independent construction, and its scheduling invariants and error codes hold."""
 import os
 import re
 
@@ -93,6 +93,11 @@ def test_mesh_matches_oracle(kind, k, patch):
     p = match(x, d.dof_coords)
     # lumped mass per DOF
     assert np.allclose(m.lumped_mass(), d.lumped_mass()[p], rtol=1e-13, atol=0)
+    # boundary mass per DOF (different quadratures of the same facet integrals; the
+    # library keeps only DOFs whose value is above rounding, so compare with a floor)
+    b_or, b = d.boundary_mass()[p], m.boundary_mass()
+    assert np.allclose(b, b_or, rtol=0, atol=(1e-11 if k == 5 else 1e-13) * np.abs(b_or).max())
+    assert np.count_nonzero(b) >= np.count_nonzero(np.abs(b_or) > 1e-9 * np.abs(b_or).max())
     # cell -> DOF map agrees through the coordinate matching
     cd = m.cell_dofs()
     e = kmv_element(2 if kind == "tri" else 3, k)
