@@ -176,8 +176,10 @@ int kmv_set_damping(kmv_problem p, const double* eta);
  * of the boundary DOFs follows the c of each solve, and kmv_misfit_gradient adds
  * the matching term (dt b_i / 2) sum_n lambda_i^n (u_i^n - u_i^{n-2}) to dJ/dc_i
  * (at every step, also with gradient_every > 1).  The gradient keeps u^n and
- * lambda^n at the boundary DOFs of every level: 2 n_shots (n_steps+1) n_bnd
- * elements of device memory.  Errors: KMV_EINVAL. */
+ * lambda^n at the boundary DOFs of every level, 2 n_shots (n_steps+1) n_bnd
+ * elements of device memory, and takes them from a ring of 8 adjoint levels
+ * (8 n_shots level vectors) instead of 2; both are allocated on the first gradient
+ * with the term on.  Errors: KMV_EINVAL. */
 int kmv_set_absorbing_boundary(kmv_problem p, int enable);
 /* Point sources x_s [n_src*dim] firing together with a Ricker wavelet
  * w(t) = amp (1 - 2 pi^2 f0^2 (t-t0)^2) exp(-pi^2 f0^2 (t-t0)^2) sampled at
