@@ -3,8 +3,8 @@ boundary DOFs' damping follows c at every solve, and the gradient carries the
 boundary term (dt b_i / 2) sum_n lambda_i^n (u_i^n - u_i^{n-2}).
 
 Tolerances as for every other parity case: FP64 1e-10 relative L2 on J, traces and
-gradient; FP32 1e-4 on the traces and 1e-3 on the gradient.  Cases: triangles
-k = 2, 3 and 4 and tetrahedra k = 2 and 3, with small ragged patches (shared boundary DOFs
+gradient; FP32 1e-4 on the traces and 1e-3 on the gradient.  Cases: every element
+(triangles k = 1..5, tetrahedra k = 1..3), with small ragged patches (shared boundary DOFs
 everywhere), with the sponge on as well, two shots, checkpoints with recompute, and
 gradient subsampling (the boundary term is taken at every step)."""
 import numpy as np
@@ -81,6 +81,9 @@ CASES = [  # kind, k, sponge, shots, checkpoint_every, gradient_every, small pat
     ("tet", 2, False, 1, 0, 1, True),
     ("tet", 2, True, 2, 7, 1, False),
     ("tet", 3, False, 1, 0, 1, False),
+    ("tri", 1, False, 1, 0, 1, True),
+    ("tri", 5, True, 1, 0, 1, False),
+    ("tet", 1, False, 1, 0, 1, True),
 ]
 
 
