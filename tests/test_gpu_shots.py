@@ -231,3 +231,43 @@ def test_per_shot_wavelets(kind, prec):
     gsum = np.sum(gs, axis=0)
     assert abs(Jb - sum(Js)) <= 1e-12 * sum(Js)
     assert rel_l2(gb.cpu().numpy(), gsum) < 1e-12
+
+
+def test_per_shot_wavelets_vs_oracle():
+    """FP64, two shots with seeded random wavelets of their own, against the oracle
+    run shot by shot with the same wavelets: J, traces and gradient to 1e-10."""
+    from oracle.fem import Discretization
+    from oracle import solver
+    from paper_2108_10946_amd import Mesh, Problem
+    from gpu_util import dof_map
+    coords, cells = configs.small_tri(7, seed=8)
+    k = 2
+    d = Discretization(coords, cells, k)
+    c_true = d.nodal_values(lambda x, z: 1.5 + 0.4 * z + 0.1 * np.sin(5 * x))
+    c0 = d.nodal_values(lambda x, z: 1.5 + 0.4 * z)
+    dt = 0.8 * solver.cfl_dt_gershgorin(d.stiffness(c_true), d.lumped_mass())
+    nt = 150
+    rng = np.random.default_rng(31)
+    waves = rng.standard_normal((2, nt))
+    xs = np.array([[[0.3, 0.2]], [[0.7, 0.4]]])
+    xr = np.stack([np.linspace(0.1, 0.9, 6), np.full(6, 0.15)], axis=1)
+    J_or, g_or, tr_or, obs = 0.0, np.zeros(d.n_dofs), [], []
+    for s in range(2):
+        sh = solver.Shot(d, xs[s], xr, dt, nt, wavelet=waves[s])
+        dobs, _ = sh.forward(c_true)
+        J, g, tr = sh.misfit_gradient(c0, dobs)
+        J_or, g_or = J_or + J, g_or + g
+        tr_or.append(tr)
+        obs.append(dobs)
+    m = Mesh(coords, cells, k, patch_cells=11)
+    p = dof_map(m.dof_coords(), d.dof_coords)
+    say("shots: per-shot wavelets vs oracle, fp64")
+    prob = Problem(m, dt, nt, precision="fp64", n_shots=2)
+    prob.set_sources(xs, f0=8.0)
+    prob.set_source_wavelet(waves)
+    prob.set_receivers(xr)
+    J, g, tr = prob.misfit_gradient(cuda(c0[p]), cuda(np.stack(obs)), keep_traces=True)
+    prob.close()
+    assert abs(J - J_or) < 1e-10 * J_or
+    assert rel_l2(tr.cpu().numpy(), np.stack(tr_or)) < 1e-10
+    assert rel_l2(g.cpu().numpy(), g_or[p]) < 1e-10
