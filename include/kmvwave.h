@@ -281,6 +281,9 @@ typedef struct {
                              step for all of them, kmv_options.n_shots); J and grad are
                              sums over the shots */
   int absorbing;          /* 1: absorbing boundary term on (kmv_set_absorbing_boundary) */
+  const double* wavelets; /* [n_shots*n_steps] host, shot-major: shot s fires its own
+                             wavelet (as kmv_set_source_wavelets; f0, t0 and amp are then
+                             unused), or NULL: the Ricker wavelet of f0, t0, amp for all */
 } kmv_request;
 
 typedef struct {

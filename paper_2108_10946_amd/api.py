@@ -213,11 +213,12 @@ class Server:
         self._keep = {}  # meshes of pending requests stay alive
 
     def submit(self, mesh: Mesh, c, xs, xr, dt, n_steps, precision="fp32", eta=None, observed=None,
-               forward_only=False, f0=5.0, t0=None, amp=1.0, absorbing=False):
+               forward_only=False, f0=5.0, t0=None, amp=1.0, absorbing=False, wavelets=None):
+        """wavelets: None (Ricker of f0, t0, amp) or [n_shots, n_steps], one per shot."""
         prec = K.KMV_FP64 if precision == "fp64" else K.KMV_FP32
         t = K.kmv_server_submit(self.handle, mesh.handle, prec, dt, n_steps, c, xs, xr, f0,
                                 1.0 / f0 if t0 is None else t0, amp, eta=eta, observed=observed,
-                                forward_only=forward_only, absorbing=absorbing)
+                                forward_only=forward_only, absorbing=absorbing, wavelets=wavelets)
         self._prec[t] = prec
         self._keep[t] = mesh
         return t

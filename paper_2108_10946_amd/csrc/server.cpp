@@ -56,6 +56,10 @@ Status run_job(Server* S, Job* j, hipStream_t st) {
     }
     Status r = set_sources(p, j->xs.data(), j->nsrc, j->f0, j->t0, j->amp);
     if (r.code != KMV_OK) return r;
+    if (!j->wavelets.empty()) {
+      r = set_wavelets(p, j->wavelets.data());
+      if (r.code != KMV_OK) return r;
+    }
     r = set_receivers(p, j->xr.data(), j->nrec);
     if (r.code != KMV_OK) return r;
     hipError_t e;
@@ -167,7 +171,7 @@ size_t job_device_bytes(const Mesh& m, int prec, int64_t nt, int nrec, size_t bu
   }
   // traces, residual, wavelet, point tables; request buffers
   const size_t rows = (size_t)nt * nrec * S;
-  b += 2 * rows * ts + (size_t)nt * ts + (size_t)(nrec + 8 * S) * m.nd * 16 + S * (np + 1) * 4;
+  b += 2 * rows * ts + (size_t)nt * S * ts + (size_t)(nrec + 8 * S) * m.nd * 16 + S * (np + 1) * 4;
   b += 2 * N * 8 + 2 * rows * ts;
   // absorbing boundary (n_bnd >= 0): coefficient tables, u and lambda records, partial sums
   // and the ring of adjoint levels those records are taken from
@@ -240,6 +244,7 @@ Status server_submit(Server* S, Mesh* m, const kmv_request* q, uint64_t* ticket)
   if (q->eta) j->eta.assign(q->eta, q->eta + N);
   j->xs.assign(q->xs, q->xs + (size_t)q->n_src * m->dim);
   j->xr.assign(q->xr, q->xr + (size_t)q->n_rec * m->dim);
+  if (q->wavelets) j->wavelets.assign(q->wavelets, q->wavelets + (size_t)nshot * q->n_steps);
   if (!j->forward_only) {
     const unsigned char* o = static_cast<const unsigned char*>(q->observed);
     j->observed.assign(o, o + (size_t)q->n_steps * q->n_rec * nshot * ts);

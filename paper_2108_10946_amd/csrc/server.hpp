@@ -28,6 +28,7 @@ struct Job {
   double dt = 0, f0 = 0, t0 = 0, amp = 0;
   int64_t nt = 0;
   std::vector<double> c, eta, xs, xr;
+  std::vector<double> wavelets;  // [nshot * nt], or empty: the Ricker of f0, t0, amp
   std::vector<unsigned char> observed;
   size_t need = 0;  // device bytes reserved while it runs
   // result

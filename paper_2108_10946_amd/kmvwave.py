@@ -56,7 +56,8 @@ class kmv_request(C.Structure):
                 ("c", C.POINTER(C.c_double)), ("eta", C.POINTER(C.c_double)), ("xs", C.POINTER(C.c_double)),
                 ("n_src", C.c_int), ("f0", C.c_double), ("t0", C.c_double), ("amp", C.c_double),
                 ("xr", C.POINTER(C.c_double)), ("n_rec", C.c_int), ("forward_only", C.c_int),
-                ("observed", C.c_void_p), ("n_shots", C.c_int), ("absorbing", C.c_int)]
+                ("observed", C.c_void_p), ("n_shots", C.c_int), ("absorbing", C.c_int),
+                ("wavelets", C.POINTER(C.c_double))]
 
 
 class kmv_result(C.Structure):
@@ -332,10 +333,11 @@ def kmv_server_create(mem_budget=0, max_slots=4):
 
 
 def kmv_server_submit(s, mesh, precision, dt, n_steps, c, xs, xr, f0, t0, amp=1.0, eta=None,
-                      observed=None, forward_only=False, absorbing=False):
+                      observed=None, forward_only=False, absorbing=False, wavelets=None):
     """Queue one request.  xs is [n_src, dim] for one shot or [n_shots, n_src, dim]
-    for several (observed then [n_shots, n_steps, n_rec]).  Host inputs are copied
-    before this returns."""
+    for several (observed then [n_shots, n_steps, n_rec]).  wavelets: None (the
+    Ricker wavelet of f0, t0, amp for every shot) or [n_shots, n_steps], one per
+    shot.  Host inputs are copied before this returns."""
     c = np.ascontiguousarray(c, dtype=np.float64)
     xs = np.asarray(xs, dtype=np.float64)
     n_shots = xs.shape[0] if xs.ndim == 3 else 1
@@ -347,9 +349,14 @@ def kmv_server_submit(s, mesh, precision, dt, n_steps, c, xs, xr, f0, t0, amp=1.
         obs = np.ascontiguousarray(observed, dtype=np.float64 if precision == KMV_FP64 else np.float32)
         if obs.size != n_shots * n_steps * len(xr):
             raise ValueError("observed must hold n_shots * n_steps * n_rec values")
+    if wavelets is not None:
+        wavelets = np.ascontiguousarray(wavelets, dtype=np.float64)
+        if wavelets.size != n_shots * n_steps:
+            raise ValueError("wavelets must hold n_shots * n_steps values")
     req = kmv_request(mesh, precision, dt, n_steps, _dptr(c), None if eta is None else _dptr(eta), _dptr(xs),
                       len(xs), f0, t0, amp, _dptr(xr), len(xr), 1 if forward_only else 0,
-                      None if obs is None else obs.ctypes.data_as(C.c_void_p), n_shots, 1 if absorbing else 0)
+                      None if obs is None else obs.ctypes.data_as(C.c_void_p), n_shots, 1 if absorbing else 0,
+                      None if wavelets is None else _dptr(wavelets))
     t = C.c_uint64()
     _check(lib().kmv_server_submit(s, C.byref(req), C.byref(t)))
     return t.value
