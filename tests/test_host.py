@@ -123,3 +123,12 @@ def test_large_graded_mesh_invariants():
     M = m.lumped_mass()
     area = 9.5 * 3.75
     assert abs(M.sum() - area) < 1e-10 * area
+
+
+def test_server_request_checks_wavelet_size():
+    """The binding refuses a per-shot wavelet array that does not hold n_shots * n_steps
+    values, before it builds the request (no server or GPU is needed to reach it)."""
+    xs = np.zeros((2, 1, 2))
+    with pytest.raises(ValueError, match="wavelets"):
+        K.kmv_server_submit(None, None, K.KMV_FP32, 1e-3, 10, np.ones(4), xs, np.zeros((1, 2)), 5.0, 0.2,
+                            forward_only=True, wavelets=np.zeros(10))
