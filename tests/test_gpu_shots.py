@@ -271,3 +271,43 @@ def test_per_shot_wavelets_vs_oracle():
     assert abs(J - J_or) < 1e-10 * J_or
     assert rel_l2(tr.cpu().numpy(), np.stack(tr_or)) < 1e-10
     assert rel_l2(g.cpu().numpy(), g_or[p]) < 1e-10
+
+
+def test_maximum_shot_count():
+    """1024 shots, the most one problem takes, on a small mesh of 7-cell patches: the
+    work-item mapping then deals n_patches * 1024 workgroups over the XCDs.  Sampled
+    shots' traces are bitwise those of one-shot problems.  The observed data equal the
+    computed traces except at the sampled shots, so every other shot's residual, and
+    its gradient term, is exactly zero: J and the gradient are then the sampled shots'
+    sums (1e-12 relative, the float64 order of the sum)."""
+    from paper_2108_10946_amd import Mesh
+    coords, cells = configs.small_tri(4, seed=3)
+    m = Mesh(coords, cells, 2, patch_cells=7)
+    x = m.dof_coords()
+    c = 1.5 + 0.5 * x[:, 1]
+    S, nt, f0 = 1024, 40, 8.0
+    xs = np.stack([[[0.05 + 0.9 * s / (S - 1), 0.5]] for s in range(S)])
+    xr = np.array([[0.3, 0.3], [0.6, 0.45], [0.55, 0.8]])
+    dt = 0.5 * m.cfl_dt(c)
+    say(f"shots: maximum shot count S={S}")
+    pb = problem(m, dt, nt, "fp32", None, f0, xs, xr)
+    cg = torch.as_tensor(c, dtype=torch.float64, device="cuda")
+    tr = pb.forward(cg).cpu().numpy()
+    assert tr.shape == (S, nt, len(xr))
+    sample = [0, 1, 7, 8, 9, 511, 1016, 1023]
+    rng = np.random.default_rng(3)
+    obs = tr.copy()
+    for s in sample:
+        obs[s] += rng.standard_normal((nt, len(xr))).astype(np.float32) * 1e-3
+    J, g, _ = pb.misfit_gradient(cg, torch.as_tensor(obs, device="cuda"), keep_traces=True)
+    g = g.cpu().numpy()
+    pb.close()
+    J1, g1 = 0.0, np.zeros_like(g)
+    for s in sample:
+        p1 = problem(m, dt, nt, "fp32", None, f0, xs[s], xr)
+        assert np.array_equal(p1.forward(cg).cpu().numpy(), tr[s])
+        Js, gs, _ = p1.misfit_gradient(cg, torch.as_tensor(obs[s], device="cuda"), keep_traces=True)
+        J1, g1 = J1 + Js, g1 + gs.cpu().numpy()
+        p1.close()
+    assert J1 > 0 and abs(J - J1) < 1e-12 * J1
+    assert rel_l2(g, g1) < 1e-12
