@@ -74,3 +74,43 @@ def test_short_sweeps(k, nt, ck, r, prec):
         assert np.all(gg == 0.0)
     else:
         assert rel_l2(gg, g[p]) < tol_g
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_points_on_vertices_and_shared_edges(prec):
+    """A source on an interior vertex and receivers on vertices and on the midpoints
+    of interior edges: each lies in several cells, and either cell gives the same
+    value of the continuous field, so the library and the oracle agree whichever
+    cell each one picks (FP64 1e-10; FP32 1e-4 traces, 1e-3 gradient)."""
+    from paper_2108_10946_amd import Mesh, Problem
+    coords, cells = configs.small_tri(6, seed=4)
+    k, nt = 3, 150
+    d = Discretization(coords, cells, k)
+    c0 = d.nodal_values(lambda x, z: 1.5 + 0.4 * z)
+    dt = 0.8 * solver.cfl_dt_gershgorin(d.stiffness(c0), d.lumped_mass())
+    # interior vertices: used by the most cells
+    use = np.bincount(cells.ravel(), minlength=len(coords))
+    inner = np.argsort(-use, kind="stable")[:4]
+    src = coords[inner[:1]]
+    e = sorted({(min(a, b), max(a, b)) for a, b in cells[:, :2]})
+    shared = [(a, b) for (a, b) in e if sum(1 for c in cells if a in c and b in c) == 2][:3]
+    rec = np.vstack([coords[inner[1:]], [(coords[a] + coords[b]) / 2 for a, b in shared]])
+    rng = np.random.default_rng(11)
+    w = rng.standard_normal(nt)
+    dobs = rng.standard_normal((nt, len(rec))) * 1e-3
+    sh = solver.Shot(d, src, rec, dt, nt, wavelet=w)
+    J, g, tr = sh.misfit_gradient(c0, dobs)
+    m = Mesh(coords, cells, k, patch_cells=7)
+    p = dof_map(m.dof_coords(), d.dof_coords)
+    say(f"points on vertices and shared edges {prec}")
+    prob = Problem(m, dt, nt, precision=prec)
+    prob.set_sources(src, f0=8.0, t0=0.1)
+    prob.set_source_wavelet(w)
+    prob.set_receivers(rec)
+    cuda = lambda a, t=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=t, device="cuda")
+    Jg, gg, trg = prob.misfit_gradient(cuda(c0[p]), cuda(dobs, prob.dtype), keep_traces=True)
+    prob.close()
+    tol_t, tol_g = (1e-10, 1e-10) if prec == "fp64" else (1e-4, 1e-3)
+    assert rel_l2(trg.double().cpu().numpy(), tr) < tol_t
+    assert rel_l2(gg.cpu().numpy(), g[p]) < tol_g
+    assert abs(Jg - J) < (1e-10 if prec == "fp64" else 1e-3) * J
