@@ -76,24 +76,31 @@ def test_short_sweeps(k, nt, ck, r, prec):
         assert rel_l2(gg, g[p]) < tol_g
 
 
+@pytest.mark.parametrize("kind", ["tri", "tet"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_points_on_vertices_and_shared_edges(prec):
-    """A source on an interior vertex and receivers on vertices and on the midpoints
-    of interior edges: each lies in several cells, and either cell gives the same
-    value of the continuous field, so the library and the oracle agree whichever
-    cell each one picks (FP64 1e-10; FP32 1e-4 traces, 1e-3 gradient)."""
+def test_points_on_vertices_and_shared_edges(prec, kind):
+    """A source on the vertex with the most cells, receivers on other such vertices and
+    on midpoints of edges shared by two or more cells (in the tetrahedral mesh these
+    edges lie on the domain boundary): each point lies in several cells, and every one
+    of them gives the same value of the continuous field, so the library and the
+    oracle agree whichever cell each picks (FP64 1e-10; FP32 1e-4 traces, 1e-3
+    gradient)."""
     from paper_2108_10946_amd import Mesh, Problem
-    coords, cells = configs.small_tri(6, seed=4)
-    k, nt = 3, 150
+    if kind == "tri":
+        coords, cells = configs.small_tri(6, seed=4)
+        k, nt = 3, 150
+    else:
+        coords, cells = configs.small_tet(3, seed=5)
+        k, nt = 2, 100
     d = Discretization(coords, cells, k)
-    c0 = d.nodal_values(lambda x, z: 1.5 + 0.4 * z)
+    c0 = d.nodal_values(lambda *x: 1.5 + 0.4 * x[-1])
     dt = 0.8 * solver.cfl_dt_gershgorin(d.stiffness(c0), d.lumped_mass())
     # interior vertices: used by the most cells
     use = np.bincount(cells.ravel(), minlength=len(coords))
     inner = np.argsort(-use, kind="stable")[:4]
     src = coords[inner[:1]]
     e = sorted({(min(a, b), max(a, b)) for a, b in cells[:, :2]})
-    shared = [(a, b) for (a, b) in e if sum(1 for c in cells if a in c and b in c) == 2][:3]
+    shared = [(a, b) for (a, b) in e if sum(1 for c in cells if a in c and b in c) >= 2][:3]
     rec = np.vstack([coords[inner[1:]], [(coords[a] + coords[b]) / 2 for a, b in shared]])
     rng = np.random.default_rng(11)
     w = rng.standard_normal(nt)
