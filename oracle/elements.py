@@ -12,9 +12,10 @@ section on higher-order mass-lumped elements):
 Readings taken here where the paper is silent:
   * spaces: tri P1; P2+b; P3+b*P1; P4+b*P2; P5+b*P4 (b = l0*l1*l2);
     tet P1; P2+{b_F}+b_T; P3+{b_F*P1(F)}+b_T*P1;
-  * weights are the rule exact for polynomials of degree k+k'-2 (k' the top degree
-    of the space): 1,3,5,7,10 on triangles, 1,3,5 on tetrahedra; KMV2tet, whose
-    degree-3 system leaves a one-parameter family, also integrates b_T exactly;
+  * weights are the nodal rule exact for polynomials of degree 2k-1: 1, 3, 5, 7 on
+    triangles of degree 1..4 and 1, 3, 5 on tetrahedra; the degree-5 triangle's rule
+    is exact to degree 10.  KMV2tet, whose degree-3 system leaves a one-parameter
+    family, also integrates b_T exactly;
   * KMV4tri and KMV5tri nodes are not printed: they are the solution of the moment
     system with orbit structures {v, m, e, 3, 3} and {v, e, e, 3, 3, 3, 6}, found by
     Newton from the starting values below (degree-5 triangle: identity with the

@@ -2,8 +2,9 @@
 // nodes = orbits of the reference simplex (coordinates printed in figures
 // fig:2dels / fig:3dels for KMV2tri, KMV3tri, KMV2tet, KMV3tet; degree-4 and
 // degree-5 triangles solved for from the moment equations), weights = the nodal
-// quadrature rule exact to degree k + k' - 2 (k' the top degree of the space),
-// basis = Lagrange basis of the enriched space at the nodes, all in long double.
+// quadrature rule exact to degree 2k - 1 (1, 3, 5, 7 on triangles of degree 1..4,
+// 1, 3, 5 on tetrahedra; 10 for the degree-5 triangle), basis = Lagrange basis of
+// the enriched space at the nodes, all in long double.
 #include "element.hpp"
 
 #include <algorithm>

@@ -215,3 +215,43 @@ def test_mms_convergence():
             exact = T ** 2 * phi
             errs.append(np.sqrt(np.sum(M * (st[-1] - exact) ** 2) / np.sum(M * exact ** 2)))
         assert errs[1] < errs[0] / 2 ** k
+
+
+@pytest.mark.parametrize("f0,t0,amp", [(5.0, 0.2, 1.0), (8.0, 0.1, 2.5), (12.5, 0.3, -0.7)])
+def test_ricker_wavelet_pins(f0, t0, amp):
+    """The oracle's wavelet against what fixes the Ricker wavelet independently of its
+    formula: the peak frequency f0 of its amplitude spectrum (section on the forward
+    wave simulation: the source is a Ricker wavelet of a given peak frequency), its
+    value amp at the delay t0, its zero crossings at t0 +- 1/(sqrt(2) pi f0), its
+    symmetry about t0, its zero mean, and its spectrum against the closed-form Fourier
+    transform of the second derivative of a Gaussian."""
+    dt = 1e-4
+    n = int(round(4.0 / dt))
+    t = t0 + (np.arange(n) - n // 2) * dt              # 4 s centred on t0: the whole wavelet
+    w = solver.ricker(t, f0, t0, amp)
+    # value at the delay and zero crossings
+    assert solver.ricker(np.array([t0]), f0, t0, amp)[0] == pytest.approx(amp, rel=1e-15)
+    tz = 1.0 / (np.sqrt(2.0) * np.pi * f0)
+    z = solver.ricker(np.array([t0 - tz, t0 + tz]), f0, t0, amp)
+    assert np.abs(z).max() < 1e-14 * abs(amp)
+    # sign change across each zero (so they are crossings, not touch points)
+    for s in (-1.0, 1.0):
+        a, b = solver.ricker(np.array([t0 + s * tz * 0.99, t0 + s * tz * 1.01]), f0, t0, amp)
+        assert a * b < 0
+    # symmetry about t0
+    tau = np.linspace(0.0, 0.5, 101)
+    assert np.abs(solver.ricker(t0 + tau, f0, t0, amp) - solver.ricker(t0 - tau, f0, t0, amp)).max() \
+        < 1e-15 * abs(amp)
+    # zero mean (the wavelet is a second derivative of a Gaussian)
+    assert abs(np.sum(w) * dt) < 1e-10 * abs(amp)
+    # amplitude spectrum: peak at f0 within the frequency resolution of a padded FFT
+    nfft = 1 << 20
+    W = np.abs(np.fft.rfft(w, nfft)) * dt
+    f = np.fft.rfftfreq(nfft, dt)
+    df = f[1]
+    assert abs(f[np.argmax(W)] - f0) <= df
+    # closed form |W(f)| = |amp| 2 f^2 / (sqrt(pi) f0^3) exp(-f^2/f0^2) (the Fourier
+    # transform of -(1/(2 pi^2 f0^2)) d^2/dt^2 exp(-pi^2 f0^2 t^2), times amp)
+    ref = abs(amp) * 2.0 * f ** 2 / (np.sqrt(np.pi) * f0 ** 3) * np.exp(-(f / f0) ** 2)
+    band = f < 4 * f0
+    assert np.abs(W[band] - ref[band]).max() < 1e-6 * ref.max()
