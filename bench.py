@@ -79,9 +79,12 @@ def algorithmic_flops(variant, n_cells, dim, degree):
     return per_cell * n_cells
 
 
-def traffic_from_profiles(variant, hash_, path=None):
-    """HBM bytes per launch of a kernel variant from the committed counter summary,
-    or None when there is none or it was taken on another version of kernels.hip."""
+def traffic_from_profiles(variant, hash_, precision="fp32", path=None):
+    """HBM bytes per launch of a kernel variant in one precision ("fp32" or "fp64")
+    from the committed counter summary, or None when there is no record for that
+    variant and precision, or it was taken on another version of kernels.hip.  The
+    record's kernel name must also be the instance of that precision
+    (k_step<float, ...> or k_step<double, ...>)."""
     path = path or os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -89,8 +92,13 @@ def traffic_from_profiles(variant, hash_, path=None):
         d = json.load(open(path))
     except Exception:
         return None
-    rec = d.get(variant)
-    if not rec or d.get("kernels_hip_sha") != hash_:
+    if d.get("kernels_hip_sha") != hash_:
+        return None
+    rec = (d.get(precision) or {}).get(variant)
+    if not rec:
+        return None
+    ctype = {"fp32": "float", "fp64": "double"}.get(precision)
+    if ctype is None or f"k_step<{ctype}," not in rec.get("kernel", "").replace(" ", ""):
         return None
     return rec.get("bytes_per_launch")
 
@@ -185,7 +193,8 @@ def roofline(res, ts, dim=2, shots=1):
         achieved = b / (p["mean_ms"] * 1e-3) / 1e9
         r = {"kernel": f"k_step ({variant.split('_')[1]})", "bound": "hbm", "achieved": round(achieved, 1),
              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-             "traffic": traffic_from_profiles(variant, hash_) if shots == 1 else None,
+             "traffic": (traffic_from_profiles(variant, hash_, "fp32" if ts == 4 else "fp64")
+                         if shots == 1 else None),
              "algorithmic_bytes": int(b),
              "mean_launch_us": round(p["mean_ms"] * 1e3, 3), "launches": p["launches"],
              "timed_launches": p["timed"], "total_ms": total}
@@ -226,6 +235,25 @@ def _oracle_sample(n_sample, quiet=False):
     return d.n_dofs, n_sample, sec
 
 
+def host_cpu():
+    """The host the oracle ran on: logical CPUs the OS reports, the CPUs this process
+    may run on, and the processor model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = None
+    return {"os_cpu_count": os.cpu_count(), "cpus_allowed": allowed, "cpu_model": model}
+
+
 def _oracle_sample_quiet(n_sample):
     return _oracle_sample(n_sample, quiet=True)
 
@@ -239,7 +267,8 @@ def cpu_baseline(n_sample=120, processes=None):
     log(f"oracle: {n} steps fwd+adj+grad in {sec:.1f}s -> {value:.3g} DOF-timesteps/s")
     out = {"value": round(value, 1), "unit": "DOF-timesteps/s", "cores": 1, "kind": "oracle",
            "sample": f"layered_kmv4 mesh (N={N}), first {n} steps of forward + "
-                     f"adjoint + gradient, FP64 assembled CSR, one thread; {sec:.1f}s"}
+                     f"adjoint + gradient, FP64 assembled CSR, one thread; {sec:.1f}s",
+           "host": host_cpu()}
     procs = processes if processes is not None else min(16, os.cpu_count() or 1)
     if procs > 1:
         import multiprocessing as mp

@@ -21,22 +21,65 @@ def test_more_than_one_gpu_is_refused():
 
 def test_traffic_lookup_follows_the_kernel_source_hash(tmp_path):
     rec = {"kernels_hip_sha": "abc123", "fetch_scale": 2.0, "write_scale": 1.0,
-           "patch_forward": {"kernel": "k", "fetch_kib": 1.0, "write_kib": 2.0, "bytes_per_launch": 12345},
-           "patch_adjoint": {"kernel": "k", "fetch_kib": 1.0, "write_kib": 2.0, "bytes_per_launch": 67890}}
+           "fp32": {"patch_forward": {"kernel": "void kmv::k_step<float, 2, 18, false>(kmv::StepArgs<float>)",
+                                      "fetch_kib": 1.0, "write_kib": 2.0, "bytes_per_launch": 12345},
+                    "patch_adjoint": {"kernel": "void kmv::k_step<float, 2, 18, true>(kmv::StepArgs<float>)",
+                                      "fetch_kib": 1.0, "write_kib": 2.0, "bytes_per_launch": 67890}}}
     p = tmp_path / "traffic.json"
     p.write_text(json.dumps(rec))
-    assert bench.traffic_from_profiles("patch_forward", "abc123", str(p)) == 12345
-    assert bench.traffic_from_profiles("patch_adjoint", "abc123", str(p)) == 67890
-    assert bench.traffic_from_profiles("patch_forward", "other", str(p)) is None
-    assert bench.traffic_from_profiles("missing", "abc123", str(p)) is None
-    assert bench.traffic_from_profiles("patch_forward", "abc123", str(tmp_path / "none.json")) is None
+    assert bench.traffic_from_profiles("patch_forward", "abc123", "fp32", str(p)) == 12345
+    assert bench.traffic_from_profiles("patch_adjoint", "abc123", "fp32", str(p)) == 67890
+    assert bench.traffic_from_profiles("patch_forward", "other", "fp32", str(p)) is None
+    assert bench.traffic_from_profiles("missing", "abc123", "fp32", str(p)) is None
+    assert bench.traffic_from_profiles("patch_forward", "abc123", "fp32", str(tmp_path / "none.json")) is None
 
 
-def test_committed_traffic_summary_has_both_variants():
+def test_fp64_roofline_never_takes_fp32_traffic(tmp_path):
+    """Counter bytes are per precision: an FP64 lookup finds nothing when only FP32
+    counters were taken, and a record filed under fp64 whose kernel is the float
+    instance is refused too."""
+    fwd32 = {"kernel": "void kmv::k_step<float, 2, 18, false>(kmv::StepArgs<float>)",
+             "fetch_kib": 1.0, "write_kib": 2.0, "bytes_per_launch": 111}
+    p = tmp_path / "traffic.json"
+    p.write_text(json.dumps({"kernels_hip_sha": "h", "fp32": {"patch_forward": fwd32}}))
+    assert bench.traffic_from_profiles("patch_forward", "h", "fp32", str(p)) == 111
+    assert bench.traffic_from_profiles("patch_forward", "h", "fp64", str(p)) is None
+    p.write_text(json.dumps({"kernels_hip_sha": "h", "fp64": {"patch_forward": fwd32}}))
+    assert bench.traffic_from_profiles("patch_forward", "h", "fp64", str(p)) is None
+    fwd64 = dict(fwd32, kernel="void kmv::k_step<double, 2, 18, false>(kmv::StepArgs<double>)",
+                 bytes_per_launch=222)
+    p.write_text(json.dumps({"kernels_hip_sha": "h", "fp32": {"patch_forward": fwd32},
+                             "fp64": {"patch_forward": fwd64}}))
+    assert bench.traffic_from_profiles("patch_forward", "h", "fp64", str(p)) == 222
+    assert bench.traffic_from_profiles("patch_forward", "h", "fp32", str(p)) == 111
+    # the roofline of an FP64 result asks for the fp64 record
+    res = {"n_dofs": 1000, "n_cells": 300,
+           "prof": {"patch_forward": {"timed": 1, "launches": 1, "mean_ms": 0.01},
+                    "patch_adjoint": {"timed": 0, "launches": 0, "mean_ms": 0.0}}}
+    orig = bench.traffic_from_profiles
+    seen = []
+    try:
+        bench.traffic_from_profiles = lambda v, h, prec="fp32", path=None: seen.append(prec)
+        bench.roofline(res, 8)
+        bench.roofline(dict(res), 4)
+    finally:
+        bench.traffic_from_profiles = orig
+    assert seen == ["fp64", "fp32"]
+
+
+def test_committed_traffic_summary_is_per_precision():
     d = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
     assert len(d["kernels_hip_sha"]) == 16
-    for v in ("patch_forward", "patch_adjoint"):
-        assert d[v]["bytes_per_launch"] > 0
+    for prec, ctype in (("fp32", "float"), ("fp64", "double")):
+        for v, rec in (d.get(prec) or {}).items():
+            assert rec["bytes_per_launch"] > 0
+            assert f"k_step<{ctype}," in rec["kernel"].replace(" ", "")
+
+
+def test_host_cpu_is_stated():
+    h = bench.host_cpu()
+    assert h["os_cpu_count"] == os.cpu_count()
+    assert h["cpus_allowed"] is None or 1 <= h["cpus_allowed"] <= os.cpu_count()
 
 
 def test_algorithmic_bytes():
