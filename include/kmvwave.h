@@ -52,11 +52,13 @@ enum {
   KMV_EDEGREE = -3,  /* unsupported (dim, degree): tri 1..5, tet 1..3 */
   KMV_EMESH = -4,    /* invalid mesh: vertex index out of range, degenerate cell */
   KMV_EOUTSIDE = -5, /* a source or receiver lies outside every cell */
-  KMV_ECFL = -6,     /* reserved: solves do not check dt against c (that needs a
-                        spectral estimate of M^-1 K(c) per solve, see
-                        kmv_cfl_dt and kmv_spectral_radius); an unstable dt shows
-                        up as KMV_ENUMERIC from kmv_misfit_gradient */
-  KMV_ENUMERIC = -7, /* non-finite value detected in a result */
+  KMV_ECFL = -6,     /* a solve left the floating-point range and dt exceeds the
+                        Gershgorin step bound 2/sqrt(rho) of eq. spectral for its
+                        wave speed (kmv_cfl_dt): the step is the likely cause.  The
+                        bound is conservative, so a larger dt is not refused up
+                        front; only a solve that blows up reports it */
+  KMV_ENUMERIC = -7, /* a solve produced a NaN or infinity with dt within that bound
+                        (non-finite inputs), or a result is not finite */
   KMV_EDEVICE = -8,  /* HIP runtime error */
   KMV_EBUSY = -9,    /* serving: result not ready yet (not a failure) */
   KMV_ESTATE = -10   /* call out of order (e.g. no sources set) */
@@ -119,6 +121,19 @@ int kmv_cfl_dt(kmv_mesh m, const double* c_host, double* dt_max);
  * and every lumped mass is positive.  Host only.
  * Returns KMV_OK or KMV_EMESH with the first violation in kmv_last_error(). */
 int kmv_mesh_validate(kmv_mesh m);
+/* Scheduling figures of the mesh's patches, for tests and tuning (host only):
+ *   max_patch_cells   most cells in one patch (one GPU thread per cell, so the
+ *                     step kernel's workgroup is this rounded up to whole
+ *                     wavefronts of 64);
+ *   max_shared_refs   most shared refs in one patch: DOFs the patch shares with
+ *                     other patches, each finished in every touching patch from
+ *                     the previous step's partial sums;
+ *   first_batch_refs  shared refs a workgroup finishes in its first batch of
+ *                     loads for the forward (adjoint = 0) or adjoint (1) step; a
+ *                     patch with more finishes the rest in a second loop.
+ * Any output may be NULL.  Errors: KMV_EINVAL. */
+int kmv_mesh_patch_stats(kmv_mesh m, int adjoint, int64_t* max_patch_cells, int64_t* max_shared_refs,
+                         int64_t* first_batch_refs);
 int kmv_mesh_destroy(kmv_mesh m);
 
 /* ------------------------------------------------------------------- problem */
@@ -204,7 +219,8 @@ int kmv_set_receivers(kmv_problem p, const double* xr, int n_rec);
 
 /* Forward solve (eqs. Leapfrog/forward3).  c_dev: double [n_dofs] wavespeed (DOF
  * order).  traces_dev: [n_shots*n_steps*n_rec] of the problem's type, row n-1 of
- * a shot = d^n.  Asynchronous on stream. */
+ * a shot = d^n.  Asynchronous on stream; a blow-up is reported by
+ * kmv_problem_status. */
 int kmv_forward(kmv_problem p, const void* c_dev, void* traces_dev, void* stream);
 /* Misfit and gradient: forward with stored or checkpointed states, J (eq.
  * l2error, no dt), adjoint sweep (eq. acoustic_pml_FEM_adj) fused with the
@@ -216,6 +232,24 @@ int kmv_forward(kmv_problem p, const void* c_dev, void* traces_dev, void* stream
  * before return. */
 int kmv_misfit_gradient(kmv_problem p, const void* c_dev, const void* observed_dev,
                         double* J_out, double* grad_dev, void* traces_dev, void* stream);
+/* As kmv_misfit_gradient, but adding to what the caller holds: *J_acc += J and
+ * grad_acc[i] += dJ/dc_i, so that several problems (other shots, other
+ * acquisitions on the same mesh and wave speed) are summed in place on the device,
+ * in call order.  Synchronises.  Errors: as kmv_misfit_gradient. */
+int kmv_misfit_gradient_accumulate(kmv_problem p, const void* c_dev, const void* observed_dev,
+                                   double* J_acc, double* grad_acc, void* traces_dev, void* stream);
+/* Misfit only (eq. l2error, no dt): the forward solve and the float64 reduction of
+ * J, without stored states or the adjoint sweep (a line-search or finite-difference
+ * probe).  J is bitwise the J of kmv_misfit_gradient for the same inputs.
+ * traces_dev optional as there.  Synchronises.  Errors: as kmv_misfit_gradient. */
+int kmv_misfit(kmv_problem p, const void* c_dev, const void* observed_dev, double* J_out, void* traces_dev,
+               void* stream);
+/* Non-finite sentinel of the most recent solve.  Every solve scans its wavefield
+ * every 128 levels of each sweep, and its last level, for NaN or infinity.
+ * kmv_misfit_gradient and kmv_misfit report a trip themselves; kmv_forward and
+ * kmv_adjoint are asynchronous, so this call synchronises the stream and reports
+ * theirs: KMV_ECFL or KMV_ENUMERIC (see the codes), else KMV_OK. */
+int kmv_problem_status(kmv_problem p, void* stream);
 /* Adjoint of the forward map for arbitrary receiver data y: lambda from the
  * transposed scheme, (1+a) lambda^m = 2 lambda^{m+1} - dt^2 M^-1 K lambda^{m+1}
  * - (1-a) lambda^{m+2} + M^-1 P^T y^m, m = N_t..1 (eq. acoustic_pml_FEM_adj).

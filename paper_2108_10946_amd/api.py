@@ -47,6 +47,11 @@ class Mesh:
     def validate(self):
         K.kmv_mesh_validate(self.handle)
 
+    def patch_stats(self, adjoint=False):
+        """Most cells and shared refs in one patch, and the refs the step kernel
+        finishes in its first batch (kmv_mesh_patch_stats)."""
+        return K.kmv_mesh_patch_stats(self.handle, adjoint)
+
     def nodal_values(self, fn):
         x = self.dof_coords()
         return fn(*[x[:, r] for r in range(self.dim)])
@@ -162,6 +167,36 @@ class Problem:
         tr = torch.empty_like(obs) if keep_traces else None
         J = K.kmv_misfit_gradient(self.handle, c, obs, g, tr)
         return J, g, tr
+
+    def misfit(self, c, observed, keep_traces=False):
+        """J only (forward solve + float64 misfit, no adjoint sweep)."""
+        torch = _torch()
+        c = self._c(c)
+        obs = self._observed(observed)
+        tr = torch.empty_like(obs) if keep_traces else None
+        J = K.kmv_misfit(self.handle, c, obs, tr)
+        return (J, tr) if keep_traces else J
+
+    def misfit_gradient_accumulate(self, c, observed, J_acc, grad_acc):
+        """J_acc + J, and grad_acc (float64 CUDA tensor) += dJ/dc in the library."""
+        torch = _torch()
+        c = self._c(c)
+        obs = self._observed(observed)
+        if not (isinstance(grad_acc, torch.Tensor) and grad_acc.is_cuda and grad_acc.dtype == torch.float64
+                and grad_acc.numel() == self.mesh.n_dofs and grad_acc.is_contiguous()):
+            raise TypeError("grad_acc must be a contiguous float64 CUDA tensor of n_dofs values")
+        return K.kmv_misfit_gradient_accumulate(self.handle, c, obs, float(J_acc), grad_acc)
+
+    def status(self):
+        """Synchronise and raise KMVError (KMV_ECFL / KMV_ENUMERIC) if the most recent
+        solve went non-finite (kmv_problem_status)."""
+        K.kmv_problem_status(self.handle)
+
+    def _observed(self, observed):
+        obs = observed.to(dtype=self.dtype).contiguous()
+        if tuple(obs.shape) != self._shape(self.n_rec):
+            raise ValueError("observed must be " + str(list(self._shape(self.n_rec))))
+        return obs
 
     def adjoint(self, c, adj, keep_lambda=False, src_trace=False):
         torch = _torch()

@@ -1,5 +1,6 @@
 // extern "C" boundary: argument checks, status codes, thread-local error text.
 // No C++ exception crosses this file.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -8,6 +9,7 @@
 
 #include "../../include/kmvwave.h"
 #include "element.hpp"
+#include "kernels.hpp"
 #include "mesh.hpp"
 #include "problem.hpp"
 #include "server.hpp"
@@ -188,6 +190,22 @@ int kmv_mesh_validate(kmv_mesh h) {
   });
 }
 
+int kmv_mesh_patch_stats(kmv_mesh h, int adjoint, int64_t* max_patch_cells, int64_t* max_shared_refs,
+                         int64_t* first_batch_refs) {
+  return guarded([&]() {
+    if (!h) return fail(KMV_EINVAL, "mesh is NULL");
+    const kmv::Mesh& m = *h->m;
+    int64_t most = 0;
+    for (int64_t q = 0; q < m.n_patches; ++q)
+      most = std::max<int64_t>(most, m.patch_sh_start[q + 1] - m.patch_sh_start[q]);
+    if (max_patch_cells) *max_patch_cells = m.max_patch_cells;
+    if (max_shared_refs) *max_shared_refs = most;
+    if (first_batch_refs)
+      *first_batch_refs = kmv::step_first_batch_refs(m.dim, m.nd, adjoint != 0, kmv::step_block(m.max_patch_cells));
+    return (int)KMV_OK;
+  });
+}
+
 int kmv_spectral_radius(kmv_problem h, const void* c_dev, int iters, uint64_t seed, double* rho,
                         void* stream) {
   return guarded([&]() {
@@ -254,6 +272,30 @@ int kmv_misfit_gradient(kmv_problem h, const void* c_dev, const void* observed_d
     if (!h) return fail(KMV_EINVAL, "problem is NULL");
     return done(kmv::misfit_gradient(h->p, (const double*)c_dev, observed_dev, J_out, grad_dev, traces_dev,
                                      (hipStream_t)stream));
+  });
+}
+
+int kmv_misfit_gradient_accumulate(kmv_problem h, const void* c_dev, const void* observed_dev, double* J_acc,
+                                   double* grad_acc, void* traces_dev, void* stream) {
+  return guarded([&]() {
+    if (!h) return fail(KMV_EINVAL, "problem is NULL");
+    return done(kmv::misfit_gradient(h->p, (const double*)c_dev, observed_dev, J_acc, grad_acc, traces_dev,
+                                     (hipStream_t)stream, true));
+  });
+}
+
+int kmv_misfit(kmv_problem h, const void* c_dev, const void* observed_dev, double* J_out, void* traces_dev,
+               void* stream) {
+  return guarded([&]() {
+    if (!h) return fail(KMV_EINVAL, "problem is NULL");
+    return done(kmv::misfit(h->p, (const double*)c_dev, observed_dev, J_out, traces_dev, (hipStream_t)stream));
+  });
+}
+
+int kmv_problem_status(kmv_problem h, void* stream) {
+  return guarded([&]() {
+    if (!h) return fail(KMV_EINVAL, "problem is NULL");
+    return done(kmv::solve_status(h->p, (hipStream_t)stream));
   });
 }
 

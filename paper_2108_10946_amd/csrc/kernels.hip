@@ -24,6 +24,8 @@
 //     du <- beta du - gamma (K u - b), u <- u + du.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "kmv_tables.inc"
 
@@ -67,6 +69,11 @@ constexpr bool stage_grad(bool adj, int dim, int nd, size_t ts) {
 template <typename T, bool ADJ, int DIM, int ND>
 constexpr bool kStageGrad = stage_grad(ADJ, DIM, ND, sizeof(T));
 
+// Shared refs per thread finished in the first batch of k_step (3D patches have
+// several times more than 2D ones: a 128-cell KMV3 tetrahedron patch about six per
+// thread); the rest go through the loop over the remaining refs, two per pass.
+constexpr int first_batch_shared(int dim, int nd, bool adj) { return dim == 3 && !adj ? (nd == 32 ? 6 : 4) : 2; }
+
 // Items per thread whose global loads are issued together (latency hiding).
 template <typename T, bool ADJ = false, int ND = 18, int DIM = 2>
 struct Batch {
@@ -74,11 +81,15 @@ struct Batch {
   // element vectors already fill the register file)
   static constexpr int kOwned = sizeof(T) == 4 ? (ND >= 30 ? 2 : 5) : 2;
   static constexpr int kWords = sizeof(T) == 4 ? 6 : 4;   // gather words in registers
-  // shared refs in the first batch (3D patches have several times more: a 128-cell
-  // KMV3 tetrahedron patch about six per thread)
-  static constexpr int kShared = DIM == 3 && !ADJ ? (ND == 32 ? 6 : 4) : 2;
+  static constexpr int kShared = first_batch_shared(DIM, ND, ADJ);
   static constexpr int kList = 1;                         // 16-byte gather-list words
 };
+
+int step_first_batch_refs(int dim, int nd, bool adjoint, int block) {
+  return first_batch_shared(dim, nd, adjoint) * block;
+}
+
+int step_block(int max_patch_cells) { return max_patch_cells <= 64 ? 64 : (max_patch_cells + 63) / 64 * 64; }
 
 // Sum of the cell-node contributions of one local DOF, in its fixed slot order.
 template <typename T>
@@ -737,12 +748,25 @@ __global__ void __launch_bounds__(256) k_reduce_parts(const double* __restrict__
 }
 
 __global__ void k_finalize_grad(const double* __restrict__ c, const double* __restrict__ gacc, int ns,
-                                double scale, double* __restrict__ g, int64_t n) {
+                                double scale, double* __restrict__ g, int64_t n, int accumulate) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double a = gacc[i];
   for (int s = 1; s < ns; ++s) a += gacc[s * n + i];
-  g[i] = scale * c[i] * a;
+  const double v = scale * c[i] * a;
+  g[i] = accumulate ? g[i] + v : v;
+}
+
+// Sentinel for a solve that has left the floating-point range (an unstable step, or
+// non-finite inputs): any NaN or infinity among the checked values raises the flag.
+template <typename T>
+__global__ void __launch_bounds__(256) k_check_finite(const T* __restrict__ x, int64_t n, int64_t stride,
+                                                      int* __restrict__ flag) {
+  const T* xv = x + (int64_t)blockIdx.y * stride;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !__builtin_isfinite(xv[i]);
+  if (bad) *flag = 1;
 }
 
 template <typename T>
@@ -876,6 +900,7 @@ hipError_t launch_fill(T* x, T v, int64_t n, hipStream_t s) {
 }
 
 hipError_t launch_fill_f64(double* x, double v, int64_t n, hipStream_t s) { return launch_fill<double>(x, v, n, s); }
+hipError_t launch_fill_i32(int* x, int v, int64_t n, hipStream_t s) { return launch_fill<int>(x, v, n, s); }
 
 template <typename T>
 hipError_t launch_misfit(const T* d, const T* obs, T* resid, int64_t n, double* scratch, int nblocks,
@@ -888,9 +913,17 @@ hipError_t launch_misfit(const T* d, const T* obs, T* resid, int64_t n, double* 
 }
 
 hipError_t launch_finalize_grad(const double* c, const double* gacc, int n_shots, double scale, double* g,
-                                int64_t n, hipStream_t s) {
+                                int64_t n, hipStream_t s, bool accumulate) {
   hipLaunchKernelGGL(k_finalize_grad, dim3(blocks_for(n, 256)), dim3(256), 0, s, c, gacc, n_shots, scale, g,
-                     n);
+                     n, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_check_finite(const T* x, int64_t n, int64_t stride, int nvec, int* flag, hipStream_t s) {
+  if (n <= 0 || nvec <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)std::min<int64_t>(blocks_for(n, 256), 512);
+  hipLaunchKernelGGL((k_check_finite<T>), dim3(nb, (unsigned)nvec), dim3(256), 0, s, x, n, stride, flag);
   return hipGetLastError();
 }
 
@@ -931,7 +964,8 @@ hipError_t launch_normalize(T* v, const T* w, const double* dot_ww, int64_t n, h
                                        hipStream_t);                                                  \
   template hipError_t launch_scale<T>(const T*, const T*, T*, int64_t, hipStream_t);                  \
   template hipError_t launch_dot<T>(const T*, const T*, int64_t, double*, int, double*, hipStream_t); \
-  template hipError_t launch_normalize<T>(T*, const T*, const double*, int64_t, hipStream_t);
+  template hipError_t launch_normalize<T>(T*, const T*, const double*, int64_t, hipStream_t);          \
+  template hipError_t launch_check_finite<T>(const T*, int64_t, int64_t, int, int*, hipStream_t);
 KMV_INST(float)
 KMV_INST(double)
 

@@ -130,6 +130,12 @@ struct FinishArgs {
 template <typename T>
 hipError_t launch_step(int dim, int nd, bool adjoint, const StepArgs<T>& a, int n_patches, int block,
                        hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// Threads per workgroup of k_step for patches of up to max_patch_cells cells (one
+// thread per cell, whole wavefronts).
+int step_block(int max_patch_cells);
+// Shared refs a k_step workgroup of `block` threads finishes in its first batch of
+// loads; a patch with more goes through the loop over the remaining refs.
+int step_first_batch_refs(int dim, int nd, bool adjoint, int block);
 // Dynamic LDS bytes of one k_step workgroup.
 size_t step_lds_bytes(int dim, int nd, int nbl_max, int slot_stride, int nb, int glist_max, bool adjoint,
                       size_t elem_size);
@@ -144,13 +150,19 @@ hipError_t launch_square(const double* c, T* c2, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_fill(T* x, T v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double* x, double v, int64_t n, hipStream_t s);
+hipError_t launch_fill_i32(int* x, int v, int64_t n, hipStream_t s);
 // r = obs - d (element type T), J = 1/2 sum r^2 in float64 (fixed order) at *J_out.
 template <typename T>
 hipError_t launch_misfit(const T* d, const T* obs, T* resid, int64_t n, double* scratch,
                          int nblocks, double* J_out, hipStream_t s);
-// g = scale * c * sum_s gacc[s*n + i], shots summed in order
+// g = scale * c * sum_s gacc[s*n + i], shots summed in order; with accumulate the
+// result is added to g instead of replacing it
 hipError_t launch_finalize_grad(const double* c, const double* gacc, int n_shots, double scale, double* g,
-                                int64_t n, hipStream_t s);
+                                int64_t n, hipStream_t s, bool accumulate = false);
+// Non-finite sentinel: sets *flag = 1 if any of x[v*stride + i], i < n, v < nvec is
+// NaN or infinite (flag untouched otherwise).
+template <typename T>
+hipError_t launch_check_finite(const T* x, int64_t n, int64_t stride, int nvec, int* flag, hipStream_t s);
 // out[r] = x[idx[r]], r < n (per-ref copies of a DOF vector)
 template <typename T>
 hipError_t launch_gather(const T* x, const int32_t* idx, T* out, int64_t n, hipStream_t s);

@@ -464,6 +464,42 @@ Status zero_level(Problem* p, Sweep& S, T* u, int lvl_par, hipStream_t s) {
   return OK;
 }
 
+// Non-finite sentinel: every kCheckEvery-th level of each sweep (and the last) is
+// scanned for NaN or infinity; an unstable step grows without bound, so a scan of
+// every 128th level finds it long before the end of a typical window.
+constexpr int64_t kCheckEvery = 128;
+
+template <typename T>
+Status check_level(Problem* p, const T* lvl, hipStream_t s) {
+  HIPTRY(launch_check_finite<T>(lvl, p->mesh->n_dofs, p->ls, p->nshot, p->d_flag, s));
+  return OK;
+}
+
+Status clear_flag(Problem* p, hipStream_t s) {
+  HIPTRY(launch_fill_i32(p->d_flag, 0, 1, s));
+  return OK;
+}
+
+// The sentinel tripped (or J is not finite): classify by the step bound of eq.
+// spectral for the solve's wave speed (sqrt of the c^2 the kernels used).
+template <typename T>
+Status classify_nonfinite(Problem* p, hipStream_t s) {
+  const Mesh& m = *p->mesh;
+  std::vector<T> c2(m.n_dofs);
+  HIPTRY(hipMemcpyAsync(c2.data(), p->d_c2, m.n_dofs * sizeof(T), hipMemcpyDeviceToHost, s));
+  HIPTRY(hipStreamSynchronize(s));
+  std::vector<double> c(m.n_dofs);
+  for (int64_t i = 0; i < m.n_dofs; ++i) c[i] = std::sqrt((double)c2[i]);
+  const double rho = gershgorin_rho(m, c.data());
+  const double dtg = 2.0 / std::sqrt(rho);
+  if (p->dt > dtg)
+    return Status{KMV_ECFL, "the solve left the floating-point range and dt = " + std::to_string(p->dt) +
+                                " s exceeds the Gershgorin step bound " + std::to_string(dtg) +
+                                " s of this wave speed (eq. spectral)"};
+  return Status{KMV_ENUMERIC, "the solve produced a non-finite value (dt is within the Gershgorin step "
+                              "bound; check the wave speed, damping and source inputs)"};
+}
+
 // Forward launches n0..n1-1 from a complete level n0 (u in slot_of(n0), owned
 // increments in fwd.d, shared increments in fwd.dsh[n0&1]); ends with level n1
 // complete.  traces: rows n-1 = d^n.  save_ck: checkpoints at multiples of seg.
@@ -500,8 +536,10 @@ Status run_forward(Problem* p, int64_t n0, int64_t n1, F slot_of, T* traces, boo
                   nullptr, row, s));
     fresh = false;
     if (ub) STTRY(record(n));
+    if (n % kCheckEvery == 0) STTRY(check_level<T>(p, slot_of(n), s));  // level n is complete
   }
   if (n1 > n0) STTRY(finish<T>(p, S, false, slot_of(n1 - 1), slot_of(n1), fwd_par(n1), s));
+  if (n1 > n0) STTRY(check_level<T>(p, slot_of(n1), s));
   if (ub && n1 > n0) STTRY(record(n1));
   if (traces && n1 >= 1) {
     for (int64_t sh = 0; sh < ns; ++sh) {
@@ -530,6 +568,7 @@ Status set_c2(Problem* p, const double* c, hipStream_t s) {
 template <typename T>
 Status forward_t(Problem* p, const double* c, T* traces, hipStream_t s) {
   STTRY(ensure_slots(p, 2));
+  STTRY(clear_flag(p, s));
   STTRY(set_c2<T>(p, c, s));
   STTRY(zero_level<T>(p, p->fwd, slot_ptr<T>(p, 0), 0, s));
   return run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n & 1); }, traces, false, s);
@@ -606,11 +645,12 @@ Status adjoint_end(Problem* p, bool grad, hipStream_t s) {
 
 template <typename T>
 Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, double* grad, T* traces_out,
-                         hipStream_t s) {
+                         hipStream_t s, bool accumulate) {
   const Mesh& m = *p->mesh;
   const int64_t N = m.n_dofs;
   STTRY(plan_storage(p));
   T* traces = traces_out ? traces_out : (T*)p->d_traces_tmp;
+  STTRY(clear_flag(p, s));
   STTRY(set_c2<T>(p, c, s));
   const int64_t r = p->grad_every;
   auto sub_slot = [p, r](int64_t n) { return n % r == 0 ? slot_ptr<T>(p, 2 + n / r) : slot_ptr<T>(p, n & 1); };
@@ -663,6 +703,7 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
     const bool g = mm % r == 0;
     STTRY(adjoint_launch<T>(p, mm, g, resid, g ? uf : nullptr, s));
     if (g && r > 1) STTRY(pair_finish<T>(p, adj_par(mm), s));
+    if ((mm + 1) % kCheckEvery == 0) STTRY(check_level<T>(p, lam_ptr<T>(p, mm + 1), s));  // complete now
     // the next launch overwrites level mm + lam_k - 1
     if (lb && (lam_top >= mm + kLamRing - 1 || mm == 1)) STTRY(record_lam(mm + 1));
     return OK;
@@ -687,8 +728,9 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
     }
   }
   STTRY(adjoint_end<T>(p, r == 1, s));
+  STTRY(check_level<T>(p, lam_ptr<T>(p, 1), s));
   STTRY(record_lam(1));
-  HIPTRY(launch_finalize_grad(c, p->d_gacc, p->nshot, 2.0 * p->dt * p->dt * (double)r, grad, N, s));
+  HIPTRY(launch_finalize_grad(c, p->d_gacc, p->nshot, 2.0 * p->dt * p->dt * (double)r, grad, N, s, accumulate));
   if (lb) {
     const int chunks = (int)std::min<int64_t>(kBndChunks, p->nt);
     if (!p->d_bnd_part) STTRY(alloc((void**)&p->d_bnd_part, (size_t)kBndChunks * p->nbd * sizeof(double)));
@@ -696,10 +738,29 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
                                  chunks, grad, s));
   }
   double hJ = 0;
+  int flag = 0;
   HIPTRY(hipMemcpyAsync(&hJ, p->d_red + p->red_blocks, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPTRY(hipMemcpyAsync(&flag, p->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPTRY(hipStreamSynchronize(s));
+  *J = accumulate ? *J + hJ : hJ;
+  if (flag || !std::isfinite(hJ)) return classify_nonfinite<T>(p, s);
+  return OK;
+}
+
+// The forward sweep and the float64 misfit only (no stored states, no adjoint).
+template <typename T>
+Status misfit_t(Problem* p, const double* c, const T* obs, double* J, T* traces_out, hipStream_t s) {
+  T* traces = traces_out ? traces_out : (T*)p->d_traces_tmp;
+  STTRY(forward_t<T>(p, c, traces, s));
+  HIPTRY(launch_misfit<T>(traces, obs, (T*)p->d_resid, p->nt * p->rec.npts * p->nshot, p->d_red,
+                          p->red_blocks, p->d_red + p->red_blocks, s));
+  double hJ = 0;
+  int flag = 0;
+  HIPTRY(hipMemcpyAsync(&hJ, p->d_red + p->red_blocks, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPTRY(hipMemcpyAsync(&flag, p->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPTRY(hipStreamSynchronize(s));
   *J = hJ;
-  if (!std::isfinite(hJ)) return Status{KMV_ENUMERIC, "misfit is not finite"};
+  if (flag || !std::isfinite(hJ)) return classify_nonfinite<T>(p, s);
   return OK;
 }
 
@@ -708,6 +769,7 @@ Status adjoint_t(Problem* p, const double* c, const T* adj, T* lambda_out, T* sr
   const Mesh& m = *p->mesh;
   const int64_t N = m.n_dofs;
   const size_t vb = (size_t)N * sizeof(T);
+  STTRY(clear_flag(p, s));
   STTRY(set_c2<T>(p, c, s));
   STTRY(adjoint_start<T>(p, s));
   if (lambda_out) HIPTRY(launch_fill<T>(lambda_out + p->nt * N, T(0), N, s));
@@ -729,8 +791,10 @@ Status adjoint_t(Problem* p, const double* c, const T* adj, T* lambda_out, T* sr
   for (int64_t mm = p->nt; mm >= 1; --mm) {
     STTRY(adjoint_launch<T>(p, mm, false, adj, nullptr, s));
     if (mm + 1 <= p->nt) STTRY(record(mm + 1));
+    if ((mm + 1) % kCheckEvery == 0) STTRY(check_level<T>(p, lam_ptr<T>(p, mm + 1), s));
   }
   STTRY(adjoint_end<T>(p, false, s));
+  STTRY(check_level<T>(p, lam_ptr<T>(p, 1), s));
   return record(1);
 }
 
@@ -848,7 +912,7 @@ Status alloc_sweep(Sweep& S, const Mesh& m, size_t ts, bool with_r, int nshot) {
 Problem::~Problem() {
   for (void* q : {(void*)d_lmap, d_geom, (void*)d_cell_start, (void*)d_own_start, (void*)d_sh_start,
                   (void*)d_sh_idx, (void*)d_shp_ptr, (void*)d_shp_slot, (void*)d_ref_slots, (void*)d_gword,
-                  (void*)d_glist, (void*)d_gword_off, (void*)d_glist_off, (void*)d_damp_patch, d_gamma, d_gdet, d_beta, d_c2, d_c2_ref, d_gamma_ref, d_beta_ref, d_minv_sqrt, d_lam[0], d_lam[1], d_lam_ring, (void*)d_gacc, (void*)d_red, d_slots,
+                  (void*)d_glist, (void*)d_gword_off, (void*)d_glist_off, (void*)d_damp_patch, d_gamma, d_gdet, d_beta, d_c2, d_c2_ref, d_gamma_ref, d_beta_ref, d_minv_sqrt, d_lam[0], d_lam[1], d_lam_ring, (void*)d_gacc, (void*)d_red, (void*)d_flag, d_slots,
                   d_ck_u, d_ck_du, d_resid, d_traces_tmp, d_wavelet, (void*)d_bnd_dof, (void*)d_bnd_ref,
                   (void*)d_bnd_coef, (void*)d_bnd_hb, d_ub, d_lb, (void*)d_bnd_part})
     dfree(q);
@@ -906,7 +970,7 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
   p->ckpt_every = ckpt_every;
   p->budget = budget ? budget : ((size_t)8 << 30);
   HIPTRY(hipGetDevice(&p->device));
-  p->block = std::max(64, ((m->max_patch_cells + 63) / 64) * 64);
+  p->block = step_block(m->max_patch_cells);
   p->nref = m->n_shared_refs;
   p->rs = std::max<int64_t>(1, p->nref);
   p->ls = m->n_dofs + p->nref;
@@ -977,6 +1041,8 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
   STTRY(alloc(&p->d_lam[1], (size_t)p->ls * n_shots * p->ts));
   STTRY(alloc((void**)&p->d_gacc, (size_t)m->n_dofs * n_shots * 8));
   STTRY(alloc((void**)&p->d_red, (size_t)(p->red_blocks + 8) * 8));
+  STTRY(alloc((void**)&p->d_flag, 256));
+  HIPTRY(launch_fill_i32(p->d_flag, 0, 1, nullptr));
   *out = guard.release();
   return OK;
 }
@@ -1068,13 +1134,30 @@ Status forward(Problem* p, const double* c, void* traces, hipStream_t s) {
 }
 
 Status misfit_gradient(Problem* p, const double* c, const void* obs, double* J, double* grad, void* traces,
-                       hipStream_t s) {
+                       hipStream_t s, bool accumulate) {
   DeviceGuard dg(p->device);
   if (!p->has_src || p->rec.npts == 0) return Status{KMV_ESTATE, "sources and receivers must be set first"};
   if (!c || !obs || !J || !grad) return Status{KMV_EINVAL, "null pointer"};
   return p->prec == KMV_FP64
-             ? misfit_gradient_t<double>(p, c, (const double*)obs, J, grad, (double*)traces, s)
-             : misfit_gradient_t<float>(p, c, (const float*)obs, J, grad, (float*)traces, s);
+             ? misfit_gradient_t<double>(p, c, (const double*)obs, J, grad, (double*)traces, s, accumulate)
+             : misfit_gradient_t<float>(p, c, (const float*)obs, J, grad, (float*)traces, s, accumulate);
+}
+
+Status misfit(Problem* p, const double* c, const void* obs, double* J, void* traces, hipStream_t s) {
+  DeviceGuard dg(p->device);
+  if (!p->has_src || p->rec.npts == 0) return Status{KMV_ESTATE, "sources and receivers must be set first"};
+  if (!c || !obs || !J) return Status{KMV_EINVAL, "null pointer"};
+  return p->prec == KMV_FP64 ? misfit_t<double>(p, c, (const double*)obs, J, (double*)traces, s)
+                             : misfit_t<float>(p, c, (const float*)obs, J, (float*)traces, s);
+}
+
+Status solve_status(Problem* p, hipStream_t s) {
+  DeviceGuard dg(p->device);
+  int flag = 0;
+  HIPTRY(hipMemcpyAsync(&flag, p->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPTRY(hipStreamSynchronize(s));
+  if (!flag) return OK;
+  return p->prec == KMV_FP64 ? classify_nonfinite<double>(p, s) : classify_nonfinite<float>(p, s);
 }
 
 Status adjoint(Problem* p, const double* c, const void* adj, void* lambda_out, void* src_trace, hipStream_t s) {

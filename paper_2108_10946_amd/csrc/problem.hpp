@@ -122,6 +122,7 @@ struct Problem {
   int lam_k = 2;
   double* d_gacc = nullptr;
   double* d_red = nullptr;      // reduction scratch
+  int* d_flag = nullptr;        // non-finite sentinel of the most recent solve (see check_every)
   int red_blocks = 256;
   void* d_slots = nullptr;      // forward state slots
   int64_t n_slots = 0;
@@ -151,8 +152,16 @@ Status set_wavelet(Problem* p, const double* w);
 Status set_wavelets(Problem* p, const double* w);
 Status set_receivers(Problem* p, const double* xr, int nrec);
 Status forward(Problem* p, const double* c_dev, void* traces_dev, hipStream_t s);
+// J and, unless grad_dev is NULL, dJ/dc.  accumulate: *J and grad_dev receive the
+// sums of their old values and this problem's (several problems summed in place).
 Status misfit_gradient(Problem* p, const double* c_dev, const void* obs_dev, double* J,
-                       double* grad_dev, void* traces_dev, hipStream_t s);
+                       double* grad_dev, void* traces_dev, hipStream_t s, bool accumulate = false);
+// Misfit only: the forward solve and J, no adjoint sweep.
+Status misfit(Problem* p, const double* c_dev, const void* obs_dev, double* J, void* traces_dev, hipStream_t s);
+// Synchronise s and report the non-finite sentinel of the most recent solve:
+// KMV_ECFL if it tripped and dt exceeds the Gershgorin step bound for the solve's
+// wave speed, KMV_ENUMERIC if it tripped otherwise, else KMV_OK.
+Status solve_status(Problem* p, hipStream_t s);
 Status adjoint(Problem* p, const double* c_dev, const void* adj_dev, void* lambda_out,
                void* src_trace_out, hipStream_t s);
 Status stiffness_apply(Problem* p, const double* c_dev, const void* u_dev, void* y_dev, hipStream_t s);

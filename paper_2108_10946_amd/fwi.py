@@ -97,11 +97,9 @@ def library_objective(problems, observed):
 
     def objective(c):
         ct = torch.as_tensor(np.ascontiguousarray(c), dtype=torch.float64, device="cuda")
-        J, g = 0.0, None
-        for prob, obs in zip(problems, observed):
-            Jp, gp, _ = prob.misfit_gradient(ct, obs)
-            J += Jp
-            g = gp if g is None else g + gp
+        J, g = 0.0, torch.zeros_like(ct)
+        for prob, obs in zip(problems, observed):  # summed in the library, in problem order
+            J = prob.misfit_gradient_accumulate(ct, obs, J, g)
         return J, g.cpu().numpy()
 
     return objective

@@ -29,10 +29,11 @@ ERROR_NAMES = {0: "KMV_OK", -1: "KMV_EINVAL", -2: "KMV_ENOMEM", -3: "KMV_EDEGREE
 DECLARED = [
     "kmv_last_error", "kmv_element_tables", "kmv_mesh_create", "kmv_mesh_info",
     "kmv_mesh_dof_coords", "kmv_mesh_lumped_mass", "kmv_mesh_boundary_mass", "kmv_mesh_cell_dofs", "kmv_mesh_validate",
+    "kmv_mesh_patch_stats",
     "kmv_mesh_destroy",
     "kmv_problem_create", "kmv_cfl_dt", "kmv_spectral_radius", "kmv_set_damping", "kmv_set_absorbing_boundary",
     "kmv_set_sources", "kmv_set_source_wavelet", "kmv_set_source_wavelets", "kmv_set_receivers", "kmv_forward",
-    "kmv_misfit_gradient", "kmv_adjoint", "kmv_stiffness_apply", "kmv_problem_info", "kmv_problem_num_shots",
+    "kmv_misfit_gradient", "kmv_misfit_gradient_accumulate", "kmv_misfit", "kmv_problem_status", "kmv_adjoint", "kmv_stiffness_apply", "kmv_problem_info", "kmv_problem_num_shots",
     "kmv_profile_enable", "kmv_profile_read", "kmv_problem_destroy",
     "kmv_server_create", "kmv_server_submit", "kmv_server_poll", "kmv_server_wait",
     "kmv_server_release", "kmv_server_stats", "kmv_server_destroy",
@@ -93,6 +94,8 @@ def lib():
         "kmv_mesh_boundary_mass": (C.c_int, [_P, _D]),
         "kmv_mesh_cell_dofs": (C.c_int, [_P, C.POINTER(C.c_int64)]),
         "kmv_mesh_validate": (C.c_int, [_P]),
+        "kmv_mesh_patch_stats": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                           C.POINTER(C.c_int64)]),
         "kmv_mesh_destroy": (C.c_int, [_P]),
         "kmv_problem_create": (C.c_int, [_P, C.POINTER(kmv_options), C.POINTER(_P)]),
         "kmv_cfl_dt": (C.c_int, [_P, _D, _D]),
@@ -105,6 +108,9 @@ def lib():
         "kmv_set_receivers": (C.c_int, [_P, _D, C.c_int]),
         "kmv_forward": (C.c_int, [_P, _P, _P, _P]),
         "kmv_misfit_gradient": (C.c_int, [_P, _P, _P, _D, _P, _P, _P]),
+        "kmv_misfit_gradient_accumulate": (C.c_int, [_P, _P, _P, _D, _P, _P, _P]),
+        "kmv_misfit": (C.c_int, [_P, _P, _P, _D, _P, _P]),
+        "kmv_problem_status": (C.c_int, [_P, _P]),
         "kmv_adjoint": (C.c_int, [_P, _P, _P, _P, _P, _P]),
         "kmv_stiffness_apply": (C.c_int, [_P, _P, _P, _P, _P]),
         "kmv_problem_num_shots": (C.c_int, [_P, C.POINTER(C.c_int)]),
@@ -249,6 +255,12 @@ def kmv_mesh_validate(m):
     _check(lib().kmv_mesh_validate(m))
 
 
+def kmv_mesh_patch_stats(m, adjoint=False):
+    v = [C.c_int64(), C.c_int64(), C.c_int64()]
+    _check(lib().kmv_mesh_patch_stats(m, 1 if adjoint else 0, *[C.byref(x) for x in v]))
+    return dict(max_patch_cells=v[0].value, max_shared_refs=v[1].value, first_batch_refs=v[2].value)
+
+
 def kmv_spectral_radius(p, c_dev, iters=200, seed=0, stream=None):
     out = C.c_double()
     _check(lib().kmv_spectral_radius(p, _tptr(c_dev), iters, seed, C.byref(out), _stream(stream)))
@@ -298,6 +310,25 @@ def kmv_misfit_gradient(p, c_dev, observed_dev, grad_dev, traces_dev=None, strea
     return J.value
 
 
+def kmv_misfit_gradient_accumulate(p, c_dev, observed_dev, J_acc, grad_acc, traces_dev=None, stream=None):
+    """Returns J_acc + J; grad_acc (device) receives grad_acc + dJ/dc."""
+    J = C.c_double(J_acc)
+    _check(lib().kmv_misfit_gradient_accumulate(p, _tptr(c_dev), _tptr(observed_dev), C.byref(J),
+                                                _tptr(grad_acc), _tptr(traces_dev), _stream(stream)))
+    return J.value
+
+
+def kmv_misfit(p, c_dev, observed_dev, traces_dev=None, stream=None):
+    J = C.c_double()
+    _check(lib().kmv_misfit(p, _tptr(c_dev), _tptr(observed_dev), C.byref(J), _tptr(traces_dev),
+                            _stream(stream)))
+    return J.value
+
+
+def kmv_problem_status(p, stream=None):
+    _check(lib().kmv_problem_status(p, _stream(stream)))
+
+
 def kmv_adjoint(p, c_dev, adj_src_dev, lambda_out_dev=None, src_trace_dev=None, stream=None):
     _check(lib().kmv_adjoint(p, _tptr(c_dev), _tptr(adj_src_dev), _tptr(lambda_out_dev),
                              _tptr(src_trace_dev), _stream(stream)))
@@ -339,6 +370,12 @@ def kmv_server_submit(s, mesh, precision, dt, n_steps, c, xs, xr, f0, t0, amp=1.
     Ricker wavelet of f0, t0, amp for every shot) or [n_shots, n_steps], one per
     shot.  Host inputs are copied before this returns."""
     c = np.ascontiguousarray(c, dtype=np.float64)
+    if mesh is not None:  # the library copies n_dofs values from c and eta
+        n_dofs = kmv_mesh_info(mesh)["n_dofs"]
+        if c.size != n_dofs:
+            raise ValueError(f"c must hold the mesh's {n_dofs} DOF values, got {c.size}")
+        if eta is not None and np.size(eta) != n_dofs:
+            raise ValueError(f"eta must hold the mesh's {n_dofs} DOF values, got {np.size(eta)}")
     xs = np.asarray(xs, dtype=np.float64)
     n_shots = xs.shape[0] if xs.ndim == 3 else 1
     xs = np.ascontiguousarray(xs.reshape(-1, xs.shape[-1]) if xs.ndim == 3 else np.atleast_2d(xs))

@@ -1,0 +1,88 @@
+"""KMV3 tetrahedra on meshes whose patches hold more shared refs than the step
+kernel finishes in its first batch of loads, so that the loop over the remaining
+refs runs in the forward step as well as in the adjoint step; misfit, traces and
+gradient against the oracle (FP64 1e-10 relative L2 on J, traces and gradient; FP32
+1e-4 on the traces, 1e-3 on the gradient).  kmv_mesh_patch_stats shows from the
+host that the loop is entered: the most shared refs in one patch exceed the first
+batch of both step variants."""
+import numpy as np
+import pytest
+
+from gpu_util import say, dof_map, rel_l2
+from oracle.fem import Discretization
+from oracle import solver
+from synth import configs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# (Kuhn-cube subdivisions, cells per patch): 64-cell patches on 750 tetrahedra (up to
+# 498 refs against a first batch of 384), and the default 128-cell patches on 2058
+# (up to 833 refs against 768)
+MESHES = [(5, 64), (7, 0)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_10946_amd as kmv
+    kmv.lib()
+
+
+@pytest.fixture(scope="module")
+def cache():
+    return {}
+
+
+def oracle_case(n, cache):
+    if n in cache:
+        return cache[n]
+    coords, cells = configs.small_tet(n, seed=21)
+    d = Discretization(coords, cells, 3)
+    x, y, z = d.dof_coords.T
+    c_true = 1.5 + 0.3 * z + 0.15 * np.exp(-((x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2) / 0.05)
+    c0 = 1.5 + 0.3 * z
+    eta = 4.0 * np.maximum(0.0, x - 0.7) ** 2
+    src = [[0.4, 0.45, 0.2]]
+    rec = np.stack([np.linspace(0.15, 0.85, 5), np.full(5, 0.5), np.full(5, 0.3)], axis=1)
+    dt = 0.8 * solver.cfl_dt_gershgorin(d.stiffness(c_true), d.lumped_mass())
+    nt = int(np.ceil(0.3 / dt))
+    sh = solver.Shot(d, src, rec, dt, nt, f0=8.0, t0=0.1)
+    dobs, _ = sh.forward(c_true, eta)
+    J, g, tr = sh.misfit_gradient(c0, dobs, eta)
+    cache[n] = (coords, cells, d, c0, eta, src, rec, nt, dt, dobs, J, g, tr)
+    return cache[n]
+
+
+@pytest.mark.parametrize("n,patch", MESHES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tet_kmv3_remaining_refs_loop(n, patch, prec, cache):
+    from paper_2108_10946_amd import Mesh, Problem
+    coords, cells, d, c0, eta, src, rec, nt, dt, dobs, J_or, g_or, tr_or = oracle_case(n, cache)
+    m = Mesh(coords, cells, 3, patch_cells=patch)
+    fw, ad = m.patch_stats(adjoint=False), m.patch_stats(adjoint=True)
+    assert fw["max_shared_refs"] > fw["first_batch_refs"], fw
+    assert ad["max_shared_refs"] > ad["first_batch_refs"], ad
+    say(f"tet overflow: KMV3tet n={n} patch={patch} {prec} refs {fw['max_shared_refs']} "
+        f"> {fw['first_batch_refs']} (forward), {ad['first_batch_refs']} (adjoint); {nt} steps")
+    p = dof_map(m.dof_coords(), d.dof_coords)
+    prob = Problem(m, dt, nt, precision=prec)
+    prob.set_damping(eta[p])
+    prob.set_sources(src, f0=8.0, t0=0.1)
+    prob.set_receivers(rec)
+    obs = torch.as_tensor(dobs, dtype=prob.dtype, device="cuda")
+    c = torch.as_tensor(c0[p], dtype=torch.float64, device="cuda")
+    tr_f = prob.forward(c)
+    prob.status()
+    J, g, tr = prob.misfit_gradient(c, obs, keep_traces=True)
+    prob.close()
+    ef = rel_l2(tr_f.double().cpu().numpy(), tr_or)
+    et, eg = rel_l2(tr.double().cpu().numpy(), tr_or), rel_l2(g.cpu().numpy(), g_or[p])
+    say(f"  J {J:.9e} (oracle {J_or:.9e}) forward traces {ef:.2e} traces {et:.2e} gradient {eg:.2e}")
+    if prec == "fp64":
+        assert abs(J - J_or) < 1e-10 * J_or
+        assert ef < 1e-10 and et < 1e-10 and eg < 1e-10
+    else:
+        assert ef < 1e-4 and et < 1e-4 and eg < 1e-3

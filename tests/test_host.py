@@ -132,3 +132,17 @@ def test_server_request_checks_wavelet_size():
     with pytest.raises(ValueError, match="wavelets"):
         K.kmv_server_submit(None, None, K.KMV_FP32, 1e-3, 10, np.ones(4), xs, np.zeros((1, 2)), 5.0, 0.2,
                             forward_only=True, wavelets=np.zeros(10))
+
+
+def test_server_request_checks_model_sizes():
+    """The binding refuses a wave speed or damping array whose length is not the mesh's
+    DOF count before the library copies n_dofs values from it (host only)."""
+    coords, cells = configs.small_tri(3, seed=1)
+    m = Mesh(coords, cells, 2)
+    xs, xr = np.array([[0.5, 0.5]]), np.array([[0.2, 0.2]])
+    with pytest.raises(ValueError, match="c must hold"):
+        K.kmv_server_submit(None, m.handle, K.KMV_FP32, 1e-3, 10, np.ones(m.n_dofs - 1), xs, xr, 5.0, 0.2,
+                            forward_only=True)
+    with pytest.raises(ValueError, match="eta must hold"):
+        K.kmv_server_submit(None, m.handle, K.KMV_FP32, 1e-3, 10, np.ones(m.n_dofs), xs, xr, 5.0, 0.2,
+                            eta=np.zeros(m.n_dofs + 3), forward_only=True)
