@@ -14,6 +14,8 @@ Modules
   solver    Ricker wavelet, CFL bounds, forward, adjoint, gradient, misfit,
             absorbing boundary damping and its gradient term.
   green     closed-form 2D homogeneous solution used as an accuracy pin.
+  pml       the perfectly matched layer (2D: p; 3D: p and omega), its exact
+            discrete adjoint and its terms in the gradient.
 
 Parity status: every function is pinned by tests in ``tests/test_oracle_*.py``
 except the degree-5 triangle's identity with the published element (the paper does

@@ -14,6 +14,9 @@ infrastructure only.  Plain float64 NumPy/SciPy, written from the definitions:
   cell (section "Receivers and sources");
 * gradient pairing sum_{(e,q)->i} w_q |det J_e| grad lam(x_eq).grad u(x_eq), the
   integrand of eq. gradient3 at the quadrature nodes;
+* derivative matrices D_k, (D_k)_ij = integral of phi_i dphi_j/dx_k by the nodal
+  rule (appendix, matrix D; the PML couplings of eqs. acoustic_pml_FEM and
+  acoustic_pml_II_FEM);
 * boundary mass b_i = integral over the mesh boundary of phi_i, the row sums of the
   boundary integral of c phi_i phi_j in the damping matrix M_{u,1} (appendix, with c
   taken at node i), by Gauss quadrature of the trace of the cell basis on every
@@ -108,6 +111,21 @@ class Discretization:
         for s in range(d):
             g += self.Jinv[:, None, s, :] * ghat[:, :, s, None]
         return g
+
+    def derivative_matrices(self):
+        """D_k [n_dofs, n_dofs], k < dim: (D_k)_ij = integral of phi_i dphi_j/dx_k by the
+        nodal rule, sum over (e,q) with g(e,q) = i of W[e,q] dphi_a/dx_k(x_eq) with
+        j = g(e,a) (appendix, matrix D).  (D_k u)_i is the mass-weighted sum over the
+        cells at DOF i of du/dx_k there; D_k^T is the weak divergence of the
+        appendix's u-row coupling, integrated by parts."""
+        nd = self.elem.n_d
+        rows = np.repeat(self.cell_dofs, nd, axis=1).ravel()       # i = g(e, q)
+        cols = np.tile(self.cell_dofs, (1, nd)).ravel()            # j = g(e, a)
+        out = []
+        for k in range(self.dim):
+            vals = (self.W[:, :, None] * self.B[:, :, :, k]).ravel()  # [e, q, a]
+            out.append(sps.coo_matrix((vals, (rows, cols)), shape=(self.n_dofs, self.n_dofs)).tocsr())
+        return out
 
     def gradient_pairing(self, lam, u):
         """r_i = sum_{(e,q) -> i} W[e,q] grad lam(x_eq) . grad u(x_eq)."""

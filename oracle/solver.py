@@ -183,18 +183,39 @@ class Shot:
             a = ab if a is None else a + ab
         return a
 
-    def forward(self, c, eta=None, keep_states=False, absorb=False):
+    def forward(self, c, eta=None, keep_states=False, absorb=False, pml=None):
+        """pml: per-axis damping functions sigma [n_dofs, dim] of the PML (oracle.pml),
+        which then replaces the sponge (eta must be None)."""
         disc = self.disc
         K = disc.stiffness(c)
         M = disc.lumped_mass()
+        if pml is not None:
+            from . import pml as PML
+            assert eta is None, "the PML replaces the sponge"
+            pm = PML.PML(disc, pml)
+            a = self.damping(c, M, pm.tr1, absorb)
+            tr, st, _ = PML.forward(pm, K, M, a, c, self.dt, self.nt,
+                                    point_source_load(self.s_vec, self.wavelet), P=self.P,
+                                    keep_states=keep_states)
+            return tr, st
         a = self.damping(c, M, eta, absorb)
         return forward(K, M, a, self.dt, self.nt, point_source_load(self.s_vec, self.wavelet),
                        P=self.P, keep_states=keep_states)
 
-    def misfit_gradient(self, c, dobs, eta=None, r=1, offset=0, absorb=False):
+    def misfit_gradient(self, c, dobs, eta=None, r=1, offset=0, absorb=False, pml=None):
         disc = self.disc
         K = disc.stiffness(c)
         M = disc.lumped_mass()
+        if pml is not None:
+            from . import pml as PML
+            assert eta is None and r == 1, "the PML replaces the sponge; no subsampling with it"
+            pm = PML.PML(disc, pml)
+            a = self.damping(c, M, pm.tr1, absorb)
+            _, states, aux = PML.forward(pm, K, M, a, c, self.dt, self.nt,
+                                         point_source_load(self.s_vec, self.wavelet), P=None,
+                                         keep_states=True)
+            return PML.gradient(pm, disc, c, K, M, a, self.dt, self.P, dobs, states, aux,
+                                bmass=disc.boundary_mass() if absorb else None)
         a = self.damping(c, M, eta, absorb)
         _, states = forward(K, M, a, self.dt, self.nt,
                             point_source_load(self.s_vec, self.wavelet), P=None,

@@ -79,6 +79,30 @@ def sponge_eta(x, z, x_lo, x_hi, z_hi, width, c_max, R=1e-3):
     return eta_max * ((dx / width) ** 2 + (dz / width) ** 2)
 
 
+def pml_sigma(x, z, x_lo, x_hi, z_hi, width, c_max, R=1e-3):
+    """Per-axis damping functions of the PML, sigma_x and sigma_z, each the quadratic
+    sigma_max (d_k/L)^2 of the distance d_k into the layer along its axis (left and
+    right layers: sigma_x; bottom layer: sigma_z; the top is open), zero inside the
+    physical box; sigma_max = 3 c_max ln(1/R) / (2L).  Returns [n, 2]; their sum is
+    sponge_eta."""
+    x = np.asarray(x, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    s_max = 3.0 * c_max * np.log(1.0 / R) / (2.0 * width)
+    dx = np.maximum(x_lo - x, 0.0) + np.maximum(x - x_hi, 0.0)
+    dz = np.maximum(z - z_hi, 0.0)
+    return np.stack([s_max * (dx / width) ** 2, s_max * (dz / width) ** 2], axis=1)
+
+
+def pml_sigma_3d(x, y, z, lo, hi, width, c_max, R=1e-3):
+    """3D per-axis damping functions (sigma_x, sigma_y, sigma_z) on the five faces
+    other than the top z = 0.  Returns [n, 3]; their sum is sponge_eta_3d."""
+    s_max = 3.0 * c_max * np.log(1.0 / R) / (2.0 * width)
+    d = [np.maximum(lo[0] - x, 0.0) + np.maximum(x - hi[0], 0.0),
+         np.maximum(lo[1] - y, 0.0) + np.maximum(y - hi[1], 0.0),
+         np.maximum(z - hi[2], 0.0)]
+    return np.stack([s_max * (di / width) ** 2 for di in d], axis=1)
+
+
 def sponge_eta_3d(x, y, z, lo, hi, width, c_max, R=1e-3):
     """3D version of ``sponge_eta`` on the five faces other than the top z = 0."""
     eta_max = 3.0 * c_max * np.log(1.0 / R) / (2.0 * width)
