@@ -222,6 +222,19 @@ int kmv_set_receivers(kmv_problem p, const double* xr, int n_rec);
  * a shot = d^n.  Asynchronous on stream; a blow-up is reported by
  * kmv_problem_status. */
 int kmv_forward(kmv_problem p, const void* c_dev, void* traces_dev, void* stream);
+/* As kmv_forward, but allocating nothing: for callers that cannot call hipMalloc
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * device allocation).  The two level buffers of the forward sweep live in the
+ * library's static workspace of 64 MiB per device (held until the process ends)
+ * instead of the problem's own, so the call needs 2 n_shots (n_dofs + shared refs)
+ * elements of workspace; a larger problem is refused with KMV_EINVAL before any
+ * work.  Everything else it uses was allocated when the problem was set up.  The
+ * traces are bitwise those of kmv_forward.  Every call on one device shares that
+ * workspace, so calls that overlap on one device (other streams, other threads)
+ * race and must be serialised by the caller.  Launches are counted but not timed
+ * by kmv_profile_enable.  Asynchronous on stream; a blow-up is reported by
+ * kmv_problem_status.  Errors: KMV_EINVAL, KMV_ESTATE, KMV_EDEVICE. */
+int kmv_forward_noalloc(kmv_problem p, const void* c_dev, void* traces_dev, void* stream);
 /* Misfit and gradient: forward with stored or checkpointed states, J (eq.
  * l2error, no dt), adjoint sweep (eq. acoustic_pml_FEM_adj) fused with the
  * gradient accumulation (eq. gradient3).  observed_dev: [n_shots*n_steps*n_rec]

@@ -266,6 +266,13 @@ int kmv_forward(kmv_problem h, const void* c_dev, void* traces_dev, void* stream
   });
 }
 
+int kmv_forward_noalloc(kmv_problem h, const void* c_dev, void* traces_dev, void* stream) {
+  return guarded([&]() {
+    if (!h) return fail(KMV_EINVAL, "problem is NULL");
+    return done(kmv::forward_noalloc(h->p, (const double*)c_dev, traces_dev, (hipStream_t)stream));
+  });
+}
+
 int kmv_misfit_gradient(kmv_problem h, const void* c_dev, const void* observed_dev, double* J_out,
                         double* grad_dev, void* traces_dev, void* stream) {
   return guarded([&]() {

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 
 #include "../../include/kmvwave.h"
 #include "boundary.hpp"
@@ -565,13 +566,45 @@ Status set_c2(Problem* p, const double* c, hipStream_t s) {
   return OK;
 }
 
+// The forward sweep with its two level buffers at base (level n in buffer n & 1).
+template <typename T>
+Status forward_run(Problem* p, const double* c, T* traces, T* base, hipStream_t s) {
+  const int64_t lvl = p->ls * p->nshot;
+  STTRY(clear_flag(p, s));
+  STTRY(set_c2<T>(p, c, s));
+  STTRY(zero_level<T>(p, p->fwd, base, 0, s));
+  return run_forward<T>(p, 0, p->nt, [base, lvl](int64_t n) { return base + (n & 1) * lvl; }, traces, false,
+                        s);
+}
+
 template <typename T>
 Status forward_t(Problem* p, const double* c, T* traces, hipStream_t s) {
   STTRY(ensure_slots(p, 2));
-  STTRY(clear_flag(p, s));
-  STTRY(set_c2<T>(p, c, s));
-  STTRY(zero_level<T>(p, p->fwd, slot_ptr<T>(p, 0), 0, s));
-  return run_forward<T>(p, 0, p->nt, [p](int64_t n) { return slot_ptr<T>(p, n & 1); }, traces, false, s);
+  return forward_run<T>(p, c, traces, slot_ptr<T>(p, 0), s);
+}
+
+// Workspace of the allocation-free forward (kmv_forward_noalloc): its two level
+// buffers.  Each device holds its own copy for the life of the process; host code
+// uses the address from hipGetSymbolAddress, taken once per device at set-up.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's workspace (the device must be current).
+Status scratch_ptr(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return Status{KMV_EDEVICE, "device index out of range"};
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return Status{KMV_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return OK;
 }
 
 Status plan_storage(Problem* p) {
@@ -1043,6 +1076,13 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
   STTRY(alloc((void**)&p->d_red, (size_t)(p->red_blocks + 8) * 8));
   STTRY(alloc((void**)&p->d_flag, 256));
   HIPTRY(launch_fill_i32(p->d_flag, 0, 1, nullptr));
+  {
+    // set-up of the allocation-free forward's workspace address on this device; a
+    // failure is reported by kmv_forward_noalloc, which asks again
+    void* ws = nullptr;
+    (void)scratch_ptr(p->device, &ws);
+    (void)hipGetLastError();
+  }
   *out = guard.release();
   return OK;
 }
@@ -1124,6 +1164,26 @@ Status set_receivers(Problem* p, const double* xr, int nrec) {
   STTRY(alloc(&p->d_resid, tb));
   STTRY(alloc(&p->d_traces_tmp, tb));
   return OK;
+}
+
+Status forward_noalloc(Problem* p, const double* c, void* traces, hipStream_t s) {
+  DeviceGuard dg(p->device);
+  if (!p->has_src || p->rec.npts == 0) return Status{KMV_ESTATE, "sources and receivers must be set first"};
+  if (!c || !traces) return Status{KMV_EINVAL, "null device pointer"};
+  const size_t need = 2 * (size_t)p->ls * p->nshot * p->ts;
+  if (need > kScratchBytes)
+    return Status{KMV_EINVAL, "the allocation-free forward needs " + std::to_string(need) +
+                                  " bytes of workspace; the static workspace holds " +
+                                  std::to_string(kScratchBytes) + " (use kmv_forward)"};
+  void* base = nullptr;
+  STTRY(scratch_ptr(p->device, &base));
+  // no timing events either: the launches are counted but not timed
+  const int every = p->probe.every;
+  p->probe.every = 0;
+  const Status st = p->prec == KMV_FP64 ? forward_run<double>(p, c, (double*)traces, (double*)base, s)
+                                        : forward_run<float>(p, c, (float*)traces, (float*)base, s);
+  p->probe.every = every;
+  return st;
 }
 
 Status forward(Problem* p, const double* c, void* traces, hipStream_t s) {

@@ -152,6 +152,9 @@ Status set_wavelet(Problem* p, const double* w);
 Status set_wavelets(Problem* p, const double* w);
 Status set_receivers(Problem* p, const double* xr, int nrec);
 Status forward(Problem* p, const double* c_dev, void* traces_dev, hipStream_t s);
+// As forward, with its two level buffers in the library's static per-device
+// workspace instead of the problem's (no device allocation in the call).
+Status forward_noalloc(Problem* p, const double* c_dev, void* traces_dev, hipStream_t s);
 // J and, unless grad_dev is NULL, dJ/dc.  accumulate: *J and grad_dev receive the
 // sums of their old values and this problem's (several problems summed in place).
 Status misfit_gradient(Problem* p, const double* c_dev, const void* obs_dev, double* J,

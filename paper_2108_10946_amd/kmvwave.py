@@ -33,7 +33,7 @@ DECLARED = [
     "kmv_mesh_destroy",
     "kmv_problem_create", "kmv_cfl_dt", "kmv_spectral_radius", "kmv_set_damping", "kmv_set_absorbing_boundary",
     "kmv_set_sources", "kmv_set_source_wavelet", "kmv_set_source_wavelets", "kmv_set_receivers", "kmv_forward",
-    "kmv_misfit_gradient", "kmv_misfit_gradient_accumulate", "kmv_misfit", "kmv_problem_status", "kmv_adjoint", "kmv_stiffness_apply", "kmv_problem_info", "kmv_problem_num_shots",
+    "kmv_forward_noalloc", "kmv_misfit_gradient", "kmv_misfit_gradient_accumulate", "kmv_misfit", "kmv_problem_status", "kmv_adjoint", "kmv_stiffness_apply", "kmv_problem_info", "kmv_problem_num_shots",
     "kmv_profile_enable", "kmv_profile_read", "kmv_problem_destroy",
     "kmv_server_create", "kmv_server_submit", "kmv_server_poll", "kmv_server_wait",
     "kmv_server_release", "kmv_server_stats", "kmv_server_destroy",
@@ -107,6 +107,7 @@ def lib():
         "kmv_set_source_wavelets": (C.c_int, [_P, _D]),
         "kmv_set_receivers": (C.c_int, [_P, _D, C.c_int]),
         "kmv_forward": (C.c_int, [_P, _P, _P, _P]),
+        "kmv_forward_noalloc": (C.c_int, [_P, _P, _P, _P]),
         "kmv_misfit_gradient": (C.c_int, [_P, _P, _P, _D, _P, _P, _P]),
         "kmv_misfit_gradient_accumulate": (C.c_int, [_P, _P, _P, _D, _P, _P, _P]),
         "kmv_misfit": (C.c_int, [_P, _P, _P, _D, _P, _P]),
@@ -301,6 +302,10 @@ def kmv_set_receivers(p, xr):
 
 def kmv_forward(p, c_dev, traces_dev, stream=None):
     _check(lib().kmv_forward(p, _tptr(c_dev), _tptr(traces_dev), _stream(stream)))
+
+
+def kmv_forward_noalloc(p, c_dev, traces_dev, stream=None):
+    _check(lib().kmv_forward_noalloc(p, _tptr(c_dev), _tptr(traces_dev), _stream(stream)))
 
 
 def kmv_misfit_gradient(p, c_dev, observed_dev, grad_dev, traces_dev=None, stream=None):
