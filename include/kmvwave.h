@@ -180,8 +180,31 @@ int kmv_problem_num_shots(kmv_problem p, int* n_shots);
 int kmv_spectral_radius(kmv_problem p, const void* c_dev, int iters, uint64_t seed,
                         double* rho, void* stream);
 /* Damping eta [n_dofs] in 1/s (host, DOF order; NULL = none).  The step uses
- * a = eta*dt/2 as the pointwise tr(Psi_1) term of eq. forward3. */
+ * a = eta*dt/2 as the pointwise tr(Psi_1) term of eq. forward3.  Errors:
+ * KMV_EINVAL (negative or non-finite), KMV_ESTATE (the PML is on). */
 int kmv_set_damping(kmv_problem p, const double* eta);
+/* Perfectly matched layer (section "Forward wave simulation in a PML truncated
+ * medium", eqs. forward2d_I / forward2d_II; the appendix matrices), triangles only.
+ * sigma: [n_dofs*2] host, DOF order, (sigma_x, sigma_z) per DOF, the damping
+ * functions of the layer (zero in the physical domain), in 1/s; NULL turns it off.
+ * With it on, each step also advances the auxiliary vector p (in the same KMV
+ * space) and the u row gains the PML terms:
+ *   u row: damping a = dt (sigma_x + sigma_z)/2 (tr Psi_1 in place of eta; kmv_set_
+ *          damping is refused while the PML is on), the zeroth-order term
+ *          M sigma_x sigma_z u, and sum_k D_k^T p_k, the divergence of p integrated
+ *          by parts with n.p = 0, D_k = the integral of phi_i dphi_j/dx_k;
+ *   p row: (1 + b_k) p_k^{n+1} = (1 - b_k) p_k^{n-1}
+ *          - 2 dt M^-1 c^2 Psi_2^kk D_k u^n, b_k = sigma_k dt, Psi_2 = diag(sigma_x -
+ *          sigma_z, sigma_z - sigma_x) (the damping term centred in time);
+ * the adjoint is its exact transpose and dJ/dc gains
+ * 2 c_i dt^2 sum_n sum_k Psi_2^kk_i mu_k,i^{n+1} (D_k u^n)_i (zero outside the layer).
+ * The patches that touch the layer run a kernel instance of their own.  The
+ * gradient needs the forward states kept (checkpoint_every = 0 with the states
+ * fitting mem_budget, or gradient_every > 1's every r-th state); recomputing
+ * from checkpoints is refused with KMV_ENOMEM.  Device memory: 4 n_shots (n_dofs +
+ * shared refs) elements per sweep for p or mu, 4 n_shots shared refs for their
+ * partial sums.  Errors: KMV_EINVAL (3D mesh, negative or non-finite sigma, LDS). */
+int kmv_set_pml(kmv_problem p, const double* sigma);
 /* First-order absorbing boundary (the condition du/dt + c du/dn = 0 on the outer
  * boundary of the forward problem; its weak form is the boundary integral of
  * c phi_i phi_j in the damping matrix M_{u,1} of the appendix).  enable = 1 turns

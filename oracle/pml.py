@@ -160,9 +160,10 @@ def adjoint(pml, K, M, a, c, dt, P, ydata, record=None):
     return out
 
 
-def gradient(pml, disc, c, K, M, a, dt, P, dobs, states, aux, bmass=None):
+def gradient(pml, disc, c, K, M, a, dt, P, dobs, states, aux, bmass=None, r=1, offset=0):
     """Misfit J, dJ/dc and the traces d from the stored forward states (U^n and the
-    auxiliary Y^n)."""
+    auxiliary Y^n).  r > 1: gradient subsampling as in solver.gradient, the pairing
+    and its PML terms taken at the reverse steps m with m % r == offset, scaled by r."""
     nt = dobs.shape[0]
     d = np.stack([P @ states[n] for n in range(1, nt + 1)])
     J = solver.misfit(d, dobs)
@@ -171,6 +172,8 @@ def gradient(pml, disc, c, K, M, a, dt, P, dobs, states, aux, bmass=None):
     Ys = aux[1]
 
     def record(m, lam_mp1, mu_mp1):
+        if m % r != offset:
+            return
         acc[:] += disc.gradient_pairing(lam_mp1, states[m])
         for k in range(pml.dim):
             acc[:] += pml.psi2[:, k] * mu_mp1[k] * (pml.D[k] @ states[m])
@@ -178,7 +181,7 @@ def gradient(pml, disc, c, K, M, a, dt, P, dobs, states, aux, bmass=None):
                 acc[:] -= pml.psi3[:, k] * mu_mp1[k] * (pml.D[k] @ Ys[m])
 
     lam = adjoint(pml, K, M, a, c, dt, P, ydata, record=record)
-    g = 2.0 * np.asarray(c) * dt * dt * acc
+    g = 2.0 * np.asarray(c) * dt * dt * r * acc
     if bmass is not None:
         bt = np.zeros(disc.n_dofs)
         for n in range(1, nt + 1):

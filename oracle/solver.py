@@ -208,14 +208,14 @@ class Shot:
         M = disc.lumped_mass()
         if pml is not None:
             from . import pml as PML
-            assert eta is None and r == 1, "the PML replaces the sponge; no subsampling with it"
+            assert eta is None, "the PML replaces the sponge"
             pm = PML.PML(disc, pml)
             a = self.damping(c, M, pm.tr1, absorb)
             _, states, aux = PML.forward(pm, K, M, a, c, self.dt, self.nt,
                                          point_source_load(self.s_vec, self.wavelet), P=None,
                                          keep_states=True)
             return PML.gradient(pm, disc, c, K, M, a, self.dt, self.P, dobs, states, aux,
-                                bmass=disc.boundary_mass() if absorb else None)
+                                bmass=disc.boundary_mass() if absorb else None, r=r, offset=offset)
         a = self.damping(c, M, eta, absorb)
         _, states = forward(K, M, a, self.dt, self.nt,
                             point_source_load(self.s_vec, self.wavelet), P=None,

@@ -107,6 +107,13 @@ class Problem:
     def set_damping(self, eta):
         K.kmv_set_damping(self.handle, eta)
 
+    def set_pml(self, sigma):
+        """Perfectly matched layer with damping functions sigma [n_dofs, 2] (DOF order),
+        or None to turn it off (kmv_set_pml)."""
+        if sigma is not None and len(sigma) != self.mesh.n_dofs:
+            raise ValueError("sigma must hold the mesh's n_dofs rows")
+        K.kmv_set_pml(self.handle, sigma)
+
     def set_absorbing_boundary(self, enable=True):
         """First-order absorbing boundary on every boundary facet (du/dt + c du/dn = 0),
         with its term in the gradient; off by default (homogeneous Neumann)."""

@@ -214,6 +214,13 @@ int kmv_spectral_radius(kmv_problem h, const void* c_dev, int iters, uint64_t se
   });
 }
 
+int kmv_set_pml(kmv_problem h, const double* sigma) {
+  return guarded([&]() {
+    if (!h) return fail(KMV_EINVAL, "problem is NULL");
+    return done(kmv::set_pml(h->p, sigma));
+  });
+}
+
 int kmv_set_damping(kmv_problem h, const double* eta) {
   return guarded([&]() {
     if (!h) return fail(KMV_EINVAL, "problem is NULL");

@@ -42,9 +42,13 @@ __host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) / 16 * 
 // the slot arrays are the largest part, and LDS limits the resident workgroups).
 // With gst (2D adjoints whose occupancy registers limit, not LDS) the float64
 // gradient accumulators of the owned non-interior DOFs follow, at sg.
+// With pml (2D) the auxiliary level and the two damping functions of the
+// non-interior DOFs follow at sp (four arrays of LB), then the two cell-node slot
+// arrays of the gradient term t at st.
 struct StepLds {
-  size_t sx, gl, sg, total;
-  __host__ __device__ StepLds(int LB, int cs, int nb, int glmax, bool adj, size_t ts, bool ovl, bool gst) {
+  size_t sx, gl, sg, sp, st, total;
+  __host__ __device__ StepLds(int LB, int cs, int nb, int glmax, bool adj, size_t ts, bool ovl, bool gst,
+                              bool pml = false) {
     const size_t nslot = (size_t)nb * cs + 1;
     const size_t stage = (size_t)(adj ? 3 : 2) * LB * ts, slots = (adj ? 2 : 1) * nslot * ts;
     if (ovl) {
@@ -56,6 +60,11 @@ struct StepLds {
     }
     sg = gl + align16((size_t)glmax * 2);
     total = sg + (gst ? align16((size_t)LB * 8) : 0);
+    sp = st = total;
+    if (pml) {
+      st = sp + align16((size_t)4 * LB * ts);
+      total = st + align16((size_t)2 * nslot * ts);
+    }
   }
 };
 
@@ -107,17 +116,21 @@ __device__ __forceinline__ T gather_sum(uint32_t w, const T* x, const uint16_t* 
 // tetrahedra forward 4 (at most 128 VGPRs), so that four workgroups fit per CU
 // when many are queued (several shots); FP64 KMV4 triangles forward and FP32 KMV4
 // triangles adjoint (with its staged accumulators) 3 (at most 168 VGPRs).
-template <typename T, int DIM, int ND, bool ADJ>
+// The PML instances run on the patches of the absorbing layer only and take no
+// cap: their extra fields would spill under it.
+template <typename T, int DIM, int ND, bool ADJ, bool PML = false>
 struct StepWaves {
   static constexpr int kMin =
-      ADJ ? (sizeof(T) == 4 && DIM == 2 && ND == 18 ? 3 : 1)
-          : sizeof(T) == 4 ? ((DIM == 2 && ND == 18) || (DIM == 3 && ND == 15) ? 4 : 1)
-                           : (DIM == 2 && ND == 18 ? 3 : 1);
+      PML ? 1
+      : ADJ ? (sizeof(T) == 4 && DIM == 2 && ND == 18 ? 3 : 1)
+            : sizeof(T) == 4 ? ((DIM == 2 && ND == 18) || (DIM == 3 && ND == 15) ? 4 : 1)
+                             : (DIM == 2 && ND == 18 ? 3 : 1);
 };
 
-template <typename T, int DIM, int ND, bool ADJ>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(StepWaves<T, DIM, ND, ADJ>::kMin)))
+template <typename T, int DIM, int ND, bool ADJ, bool PML = false>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(StepWaves<T, DIM, ND, ADJ, PML>::kMin)))
 k_step(const StepArgs<T> A0) {
+  static_assert(!PML || DIM == 2, "the PML instances are 2D");
   // XCD-aware work order: the dispatcher deals workgroups round-robin over the 8
   // XCDs (separate L2 caches), so workgroup b runs on XCD b % 8.  Each XCD gets a
   // contiguous run of work items, patch-major: neighbouring patches, which
@@ -132,6 +145,7 @@ k_step(const StepArgs<T> A0) {
     const int ns = A0.n_shots;
     p = ns == 1 ? i : i / ns;
     shot = i - p * ns;
+    if (A0.patch_list != nullptr) p = A0.patch_list[p];
   }
   StepArgs<T> A = A0;
   if (shot != 0) {
@@ -153,6 +167,13 @@ k_step(const StepArgs<T> A0) {
       A.partr_cur += shot * A.ss_ref;
       A.gacc += shot * A.ss_dof;
     }
+    if (PML) {
+      A.pp_in += shot * A.ss_pml;
+      A.pp_in_sh += shot * A.ss_pml;
+      A.pp_io += shot * A.ss_pml;
+      A.pt_prev += shot * A.ss_pt;
+      A.pt_cur += shot * A.ss_pt;
+    }
   }
   using Tab = KmvTab<T, DIM, ND>;  // compile-time reference gradients, weights, node classes
   constexpr int NI = Tab::NI, NB = Tab::NB;
@@ -161,7 +182,7 @@ k_step(const StepArgs<T> A0) {
   const int LB = A.nbl_max, CS = A.slot_stride;
   constexpr bool OVL = DIM == 3;  // slots overlay the c^2 [and u^m] staging
   constexpr bool GST = kStageGrad<T, ADJ, DIM, ND>;
-  const StepLds lay(LB, CS, NB, A.glist_max, ADJ, sizeof(T), OVL, GST);
+  const StepLds lay(LB, CS, NB, A.glist_max, ADJ, sizeof(T), OVL, GST, PML);
   T* su = reinterpret_cast<T*>(smem_raw);  // level n of the non-interior DOFs
   T* sc = su + LB;                         // c^2
   T* sf = sc + LB;                         // forward state u^m (ADJ)
@@ -169,6 +190,14 @@ k_step(const StepArgs<T> A0) {
   T* sr = sx + (NB * CS + 1);                       // gradient pairing per cell node (ADJ)
   uint16_t* gl = reinterpret_cast<uint16_t*>(smem_raw + lay.gl);
   double* sg = reinterpret_cast<double*>(smem_raw + lay.sg);  // GST: owned accumulators
+  // PML: auxiliary level (p^n, or mu^{m+1} in the adjoint) and sigma_x, sigma_z of the
+  // non-interior DOFs; t slots per cell node
+  T* sPx = reinterpret_cast<T*>(smem_raw + lay.sp);
+  T* sPz = sPx + LB;
+  T* sSx = sPz + LB;
+  T* sSz = sSx + LB;
+  T* stx = reinterpret_cast<T*>(smem_raw + lay.st);
+  T* stz = stx + (NB * CS + 1);
   const int tid = threadIdx.x, bs = blockDim.x;
   const int c0 = A.cell_start[p], nc = A.cell_start[p + 1] - c0;
   const int own0 = A.own_start[p], bo0 = own0 + NI * nc, nbo = A.own_start[p + 1] - bo0;
@@ -438,6 +467,78 @@ k_step(const StepArgs<T> A0) {
     sx[NB * CS] = T(0);
     if (ADJ) sr[NB * CS] = T(0);
   }
+  // ---- PML: the auxiliary level and the damping functions.  Forward: p^n, whose
+  // shared DOFs are finished here (lagged, as u) from p^{n-2} at their ref copies and
+  // the previous step's partial sums T of D_k u^{n-1}:
+  //   (1 + b_k) p_k^n = (1 - b_k) p_k^{n-2} - (2 dt / M) c^2 Psi_2^kk T_k,
+  // b_k = sigma_k dt, Psi_2^xx = sigma_x - sigma_z = -Psi_2^zz.  Adjoint (pml_trans,
+  // with or without the gradient pairing): mu^{m+1} from mu^{m+3} and the partial
+  // sums of D_k lambda^{m+2}, without the c^2 Psi_2 factor (it sits in the u row
+  // there).  2 dt / M = 4 gamma / (dt (1 + beta)).
+  T piX[NIa], piZ[NIa], pmX[NIa], pmZ[NIa], siX[NIa], siZ[NIa], Bm[4];
+  if constexpr (PML) {
+    const T* pin = A.pp_in;
+    const int64_t ls = A.pml_ls, rs = A.pml_rs;
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int gx = own0 + j * nc + tc;
+      piX[j] = pin[gx];
+      piZ[j] = pin[ls + gx];
+      pmX[j] = A.pp_io[gx];
+      pmZ[j] = A.pp_io[ls + gx];
+      siX[j] = A.sig[gx];
+      siZ[j] = A.sig[N + gx];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Bm[k] = A.pml_b[(int64_t)k * A.n_cells + e];
+    for (int i = tid; i < nbo; i += bs) {
+      sPx[i] = pin[bo0 + i];
+      sPz[i] = pin[ls + bo0 + i];
+      sSx[i] = A.sig[bo0 + i];
+      sSz[i] = A.sig[N + bo0 + i];
+    }
+    const int64_t nref = A.pml_rs;
+    for (int j = tid; j < nsh; j += bs) {
+      const int r = sh0 + j;
+      T px = pin[N + r], pz = pin[ls + N + r];
+      const T sxr = A.sig_ref[r], szr = A.sig_ref[nref + r];
+      if (step && A.prev) {
+        const int2 sj = reinterpret_cast<const int2*>(A.ref_slots)[r];
+        T tx, tz;
+        if (sj.y >= 0) {
+          tx = A.pt_prev[sj.x] + A.pt_prev[sj.y];
+          tz = A.pt_prev[rs + sj.x] + A.pt_prev[rs + sj.y];
+        } else {
+          const int64_t sd = A.sh_idx[r] - A.n_own;
+          tx = T(0);
+          tz = T(0);
+          for (int k = A.shp_ptr[sd]; k < A.shp_ptr[sd + 1]; ++k) {
+            tx += A.pt_prev[A.shp_slot[k]];
+            tz += A.pt_prev[rs + A.shp_slot[k]];
+          }
+        }
+        const T m2 = T(4) * A.gamma_ref[r] * A.inv_dt / (T(1) + A.beta_ref[r]);
+        if (!A.pml_trans) {
+          const T cd = A.c2_ref[r] * (sxr - szr);
+          tx = cd * tx;
+          tz = -cd * tz;
+        }
+        const T bx = sxr * A.pml_dt, bz = szr * A.pml_dt;
+        px = ((T(1) - bx) * px - m2 * tx) / (T(1) + bx);
+        pz = ((T(1) - bz) * pz - m2 * tz) / (T(1) + bz);
+        A.pp_in_sh[N + r] = px;
+        A.pp_in_sh[ls + N + r] = pz;
+      }
+      sPx[nbo + j] = px;
+      sPz[nbo + j] = pz;
+      sSx[nbo + j] = sxr;
+      sSz[nbo + j] = szr;
+    }
+    if (tid == 0) {
+      stx[NB * CS] = T(0);
+      stz[NB * CS] = T(0);
+    }
+  }
   __syncthreads();
 
   // ---- per cell: receivers, element stiffness (and pairing), sources, interior DOFs
@@ -476,6 +577,8 @@ k_step(const StepArgs<T> A0) {
           A.trace_row[A.rec_pt[r]] = s;
         }
     }
+    T tiX[NIa], tiZ[NIa];  // PML: t at the interior nodes
+    const T absJ = PML ? (T)fabs(Bm[0] * Bm[3] - Bm[1] * Bm[2]) : T(0);  // |det B_e| = |det J_e|
 #pragma unroll
     for (int q = 0; q < ND; ++q) {
       T g[DIM];
@@ -502,6 +605,43 @@ k_step(const StepArgs<T> A0) {
       T z[DIM];
 #pragma unroll
       for (int r = 0; r < DIM; ++r) z[r] = cw * v[r];
+      // PML at node q: the u row's coupling sum_k D_k^T p_k (forward) or
+      // sum_k D_k^T c^2 Psi_2^kk mu_k (adjoint) enters z as w_q B_e^T (.)_q; t_q =
+      // w_q B_e ghat_q is node q's share of D_k u (of the level being stepped); and
+      // the zeroth-order term M sigma_x sigma_z u enters the element vector
+      T pxq = T(0), pzq = T(0), sxq = T(0), szq = T(0);
+      if constexpr (PML) {
+        const int x = Tab::IDX[q];
+        if (Tab::INT[q]) {
+          const int j = x < NI ? x : 0;
+          pxq = piX[j];
+          pzq = piZ[j];
+          sxq = siX[j];
+          szq = siZ[j];
+        } else {
+          const int l = m[x < NB ? x : 0];
+          pxq = sPx[l];
+          pzq = sPz[l];
+          sxq = sSx[l];
+          szq = sSz[l];
+        }
+        T qx = pxq, qz = pzq;
+        if (A.pml_trans) {
+          qx = ce[q] * (sxq - szq) * pxq;
+          qz = ce[q] * (szq - sxq) * pzq;
+        }
+        z[0] += wq * (Bm[0] * qx + Bm[2] * qz);
+        z[1] += wq * (Bm[1] * qx + Bm[3] * qz);
+        const T tx = wq * (Bm[0] * g[0] + Bm[1] * g[1]), tz = wq * (Bm[2] * g[0] + Bm[3] * g[1]);
+        if (Tab::INT[q]) {
+          tiX[x < NI ? x : 0] = tx;
+          tiZ[x < NI ? x : 0] = tz;
+        } else {
+          stx[x * CS + tid] = tx;
+          stz[x * CS + tid] = tz;
+        }
+        ye[q] += wq * absJ * (sxq * szq) * ue[q];
+      }
 #pragma unroll
       for (int b = 0; b < ND; ++b)
 #pragma unroll
@@ -524,6 +664,10 @@ k_step(const StepArgs<T> A0) {
 #pragma unroll
         for (int r = 0; r < DIM; ++r) s += gf[r] * v[r];
         re[ADJ ? q : 0] = wq * s;
+        if constexpr (PML) {  // gradient's PML term: sum_k Psi_2^kk mu_k (D_k u^m) at node q
+          const T tfx = wq * (Bm[0] * gf[0] + Bm[1] * gf[1]), tfz = wq * (Bm[2] * gf[0] + Bm[3] * gf[1]);
+          re[ADJ ? q : 0] += (sxq - szq) * (pxq * tfx - pzq * tfz);
+        }
       }
     }
     // point sources in this cell: b enters the element vector as K u - b
@@ -546,6 +690,18 @@ k_step(const StepArgs<T> A0) {
         A.du[gx] = dn;
         A.u_out[gx] = ui[j] + dn;
         if (ADJ) A.gacc[gx] = ga[ADJ ? j : 0] + (double)re[ADJ ? a : 0];
+        if constexpr (PML) {  // the auxiliary level n+1 (adjoint: m) of the interior DOF
+          const T m2 = T(2) * A.pml_dt / (Tab::W[a] * absJ);
+          T tx = tiX[j], tz = tiZ[j];
+          if (!A.pml_trans) {
+            const T cd = ce[a] * (siX[j] - siZ[j]);
+            tx = cd * tx;
+            tz = -cd * tz;
+          }
+          const T bx = siX[j] * A.pml_dt, bz = siZ[j] * A.pml_dt;
+          A.pp_io[gx] = ((T(1) - bx) * pmX[j] - m2 * tx) / (T(1) + bx);
+          A.pp_io[A.pml_ls + gx] = ((T(1) - bz) * pmZ[j] - m2 * tz) / (T(1) + bz);
+        }
       } else {
         A.y_out[gx] = ye[a];
       }
@@ -616,6 +772,32 @@ k_step(const StepArgs<T> A0) {
       }
     } else {
       produce(l - nbo, y, r);
+    }
+  }
+  // ---- PML: t summed per non-interior DOF in the same fixed slot order; owned DOFs
+  // take their auxiliary level n+1 (adjoint: m), shared ones write this patch's
+  // partial sums
+  if constexpr (PML) {
+    const int64_t ls = A.pml_ls, rs = A.pml_rs;
+    for (int l = tid; l < nbl; l += bs) {
+      const uint32_t w = gwp[l];
+      T tx = gather_sum(w, stx, gl), tz = gather_sum(w, stz, gl);
+      if (l < nbo) {
+        const int gx = bo0 + l;
+        const T sxl = sSx[l], szl = sSz[l];
+        const T m2 = T(4) * A.gamma[gx] * A.inv_dt / (T(1) + A.beta[gx]);
+        if (!A.pml_trans) {
+          const T cd = A.c2[gx] * (sxl - szl);
+          tx = cd * tx;
+          tz = -cd * tz;
+        }
+        const T bx = sxl * A.pml_dt, bz = szl * A.pml_dt;
+        A.pp_io[gx] = ((T(1) - bx) * A.pp_io[gx] - m2 * tx) / (T(1) + bx);
+        A.pp_io[ls + gx] = ((T(1) - bz) * A.pp_io[ls + gx] - m2 * tz) / (T(1) + bz);
+      } else {
+        A.pt_cur[sh0 + (l - nbo)] = tx;
+        A.pt_cur[rs + sh0 + (l - nbo)] = tz;
+      }
     }
   }
 }
@@ -809,19 +991,19 @@ void launch_ev(K kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, hip
     hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
 }
 
-template <typename T, int DIM, int ND, bool ADJ>
+template <typename T, int DIM, int ND, bool ADJ, bool PML = false>
 hipError_t launch_step_t(const StepArgs<T>& a, int np, int block, hipStream_t s, hipEvent_t e0,
                          hipEvent_t e1) {
   const size_t lds = StepLds(a.nbl_max, a.slot_stride, KmvTab<T, DIM, ND>::NB, a.glist_max, ADJ, sizeof(T),
-                             DIM == 3, kStageGrad<T, ADJ, DIM, ND>)
+                             DIM == 3, kStageGrad<T, ADJ, DIM, ND>, PML)
                           .total;
-  launch_ev(k_step<T, DIM, ND, ADJ>, dim3(np * a.n_shots), dim3(block), (uint32_t)lds, s, e0, e1, a);
+  launch_ev(k_step<T, DIM, ND, ADJ, PML>, dim3(np * a.n_shots), dim3(block), (uint32_t)lds, s, e0, e1, a);
   return hipGetLastError();
 }
 
-template <typename T, int DIM, int ND, bool ADJ>
+template <typename T, int DIM, int ND, bool ADJ, bool PML = false>
 hipError_t set_lds_t(int bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step<T, DIM, ND, ADJ>),
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step<T, DIM, ND, ADJ, PML>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
@@ -837,22 +1019,40 @@ hipError_t set_lds_t(int bytes) {
     case 332: return adjoint ? FN<T, 3, 32, true>(__VA_ARGS__) : FN<T, 3, 32, false>(__VA_ARGS__); \
     default: return hipErrorInvalidValue;                                                          \
   }
+
+// the PML instances (triangles)
+#define KMV_DISPATCH_PML(FN, ...)                                                                              \
+  switch (dim * 100 + nd) {                                                                                    \
+    case 203: return adjoint ? FN<T, 2, 3, true, true>(__VA_ARGS__) : FN<T, 2, 3, false, true>(__VA_ARGS__);   \
+    case 207: return adjoint ? FN<T, 2, 7, true, true>(__VA_ARGS__) : FN<T, 2, 7, false, true>(__VA_ARGS__);   \
+    case 212: return adjoint ? FN<T, 2, 12, true, true>(__VA_ARGS__) : FN<T, 2, 12, false, true>(__VA_ARGS__); \
+    case 218: return adjoint ? FN<T, 2, 18, true, true>(__VA_ARGS__) : FN<T, 2, 18, false, true>(__VA_ARGS__); \
+    case 230: return adjoint ? FN<T, 2, 30, true, true>(__VA_ARGS__) : FN<T, 2, 30, false, true>(__VA_ARGS__); \
+    default: return hipErrorInvalidValue;                                                                      \
+  }
 }  // namespace
 
 size_t step_lds_bytes(int dim, int nd, int nbl_max, int slot_stride, int nb, int glist_max, bool adjoint,
-                      size_t elem_size) {
+                      size_t elem_size, bool pml) {
   const bool gst = stage_grad(adjoint, dim, nd, elem_size);
-  return StepLds(nbl_max, slot_stride, nb, glist_max, adjoint, elem_size, dim == 3, gst).total;
+  return StepLds(nbl_max, slot_stride, nb, glist_max, adjoint, elem_size, dim == 3, gst, pml).total;
 }
 
 template <typename T>
-hipError_t launch_step(int dim, int nd, bool adjoint, const StepArgs<T>& a, int n_patches, int block,
-                       hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  KMV_DISPATCH(launch_step_t, a, n_patches, block, s, e0, e1)
+hipError_t launch_step(int dim, int nd, bool adjoint, const StepArgs<T>& a, int n_items, int block,
+                       hipStream_t s, hipEvent_t e0, hipEvent_t e1, bool pml) {
+  if (n_items <= 0) return hipSuccess;
+  if (pml) {
+    KMV_DISPATCH_PML(launch_step_t, a, n_items, block, s, e0, e1)
+  }
+  KMV_DISPATCH(launch_step_t, a, n_items, block, s, e0, e1)
 }
 
 template <typename T>
-hipError_t set_step_lds_limit(int dim, int nd, bool adjoint, int bytes) {
+hipError_t set_step_lds_limit(int dim, int nd, bool adjoint, int bytes, bool pml) {
+  if (pml) {
+    KMV_DISPATCH_PML(set_lds_t, bytes)
+  }
   KMV_DISPATCH(set_lds_t, bytes)
 }
 
@@ -951,8 +1151,8 @@ hipError_t launch_normalize(T* v, const T* w, const double* dot_ww, int64_t n, h
 
 #define KMV_INST(T)                                                                                    \
   template hipError_t launch_step<T>(int, int, bool, const StepArgs<T>&, int, int, hipStream_t,        \
-                                     hipEvent_t, hipEvent_t);                                         \
-  template hipError_t set_step_lds_limit<T>(int, int, bool, int);                                      \
+                                     hipEvent_t, hipEvent_t, bool);                                   \
+  template hipError_t set_step_lds_limit<T>(int, int, bool, int, bool);                                \
   template hipError_t launch_finish<T>(bool, const FinishArgs<T>&, hipStream_t, hipEvent_t,           \
                                        hipEvent_t);                                                   \
   template hipError_t launch_sample<T>(const T*, const int32_t*, const T*, int, int, T*, hipStream_t,  \

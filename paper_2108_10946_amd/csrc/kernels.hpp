@@ -99,6 +99,21 @@ struct StepArgs {
   int64_t ss_amp;              // amp
   int64_t ss_trace;            // trace_row
   int64_t ss_inj;              // inj_ptr (a [np+1] block per shot, or shared)
+  // work items: patch_list[i] is the patch of item i (nullptr: item i is patch i)
+  const int32_t* patch_list;
+  // PML (2D, the k_step<..., PML = true> instances; see StepPml)
+  const T* pml_b;              // [4 * n_cells] B_e = |det J_e| J_e^-T, entry (k, r) at (2k + r) * n_cells + e
+  const T* sig;                // [2 * n_dofs] sigma_x then sigma_z at the DOFs
+  const T* sig_ref;            // [2 * n_shared_refs] the same at each shared ref
+  const T* pp_in;              // auxiliary level n: [2][ls] (component k at k * ls), DOF values then ref copies
+  T* pp_in_sh;                 // same buffer: finished shared entries are stored here
+  T* pp_io;                    // auxiliary level n-1, overwritten by level n+1 (owned DOFs)
+  const T* pt_prev;            // [2][rs] partial sums of the gradient term t of the previous step
+  T* pt_cur;                   // [2][rs] this step's
+  int64_t pml_ls, pml_rs;      // component strides of pp_* (ls) and pt_* (rs)
+  int64_t ss_pml, ss_pt;       // per-shot strides (2 ls, 2 rs)
+  T pml_dt, inv_dt;            // dt, 1 / dt
+  int pml_trans;               // 1: the transposed (adjoint) PML couplings, with or without the gradient pairing
 };
 
 // Finisher: the shared DOFs of a level from the last step's partials (end of a
@@ -127,9 +142,11 @@ struct FinishArgs {
 };
 
 // e0/e1: optional events recorded by the dispatch itself at kernel start and end.
+// n_items: patches in the launch (a.patch_list's length when it is set).  pml:
+// the PML instance (2D only).
 template <typename T>
-hipError_t launch_step(int dim, int nd, bool adjoint, const StepArgs<T>& a, int n_patches, int block,
-                       hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_step(int dim, int nd, bool adjoint, const StepArgs<T>& a, int n_items, int block,
+                       hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, bool pml = false);
 // Threads per workgroup of k_step for patches of up to max_patch_cells cells (one
 // thread per cell, whole wavefronts).
 int step_block(int max_patch_cells);
@@ -138,7 +155,7 @@ int step_block(int max_patch_cells);
 int step_first_batch_refs(int dim, int nd, bool adjoint, int block);
 // Dynamic LDS bytes of one k_step workgroup.
 size_t step_lds_bytes(int dim, int nd, int nbl_max, int slot_stride, int nb, int glist_max, bool adjoint,
-                      size_t elem_size);
+                      size_t elem_size, bool pml = false);
 template <typename T>
 hipError_t launch_finish(bool adjoint, const FinishArgs<T>& a, hipStream_t s, hipEvent_t e0 = nullptr,
                          hipEvent_t e1 = nullptr);
@@ -175,6 +192,6 @@ hipError_t launch_dot(const T* x, const T* y, int64_t n, double* scratch, int nb
 template <typename T>
 hipError_t launch_normalize(T* v, const T* w, const double* dot_ww, int64_t n, hipStream_t s);
 template <typename T>
-hipError_t set_step_lds_limit(int dim, int nd, bool adjoint, int bytes);
+hipError_t set_step_lds_limit(int dim, int nd, bool adjoint, int bytes, bool pml = false);
 
 }  // namespace kmv

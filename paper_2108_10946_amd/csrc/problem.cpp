@@ -383,9 +383,48 @@ Status step(Problem* p, Sweep& S, bool grad, bool prev, const T* u_in, const T* 
     a.partr_cur = (T*)S.partr[q.step_cur];
     a.gacc = p->d_gacc;
   }
-  return probed(p, grad ? 1 : 0, s, [&](hipEvent_t e0, hipEvent_t e1) {
-    return launch_step<T>(m.dim, m.nd, grad, a, (int)m.n_patches, p->block, s, e0, e1);
-  });
+  if (!p->pml())
+    return probed(p, grad ? 1 : 0, s, [&](hipEvent_t e0, hipEvent_t e1) {
+      return launch_step<T>(m.dim, m.nd, grad, a, (int)m.n_patches, p->block, s, e0, e1);
+    });
+  // PML: the patches away from the layer, then those touching it (their own kernel
+  // instance with the auxiliary fields); the two sets are disjoint and neither reads
+  // what the other writes in this step
+  const int sw = &S == &p->adj ? 1 : 0;
+  a.patch_list = p->d_list[0];
+  if (p->n_list[0] > 0)
+    STTRY(probed(p, grad ? 1 : 0, s, [&](hipEvent_t e0, hipEvent_t e1) {
+      return launch_step<T>(m.dim, m.nd, grad, a, p->n_list[0], p->block, s, e0, e1);
+    }));
+  a.patch_list = p->d_list[1];
+  a.pml_b = (const T*)p->d_pml_b;
+  a.sig = (const T*)p->d_sig;
+  a.sig_ref = (const T*)p->d_sig_ref;
+  a.pp_in = (const T*)p->d_pp[sw][q.lvl_cur];
+  a.pp_in_sh = (T*)p->d_pp[sw][q.lvl_cur];
+  a.pp_io = (T*)p->d_pp[sw][q.lvl_prev];
+  a.pt_prev = (const T*)p->d_pt[sw][q.step_prev];
+  a.pt_cur = (T*)p->d_pt[sw][q.step_cur];
+  a.pml_ls = p->ls;
+  a.pml_rs = p->rs;
+  a.ss_pml = 2 * p->ls;
+  a.ss_pt = 2 * p->rs;
+  a.pml_dt = (T)p->dt;
+  a.inv_dt = (T)(1.0 / p->dt);
+  a.pml_trans = sw;  // the reverse sweep, also its launches without the pairing
+  HIPTRY(launch_step<T>(m.dim, m.nd, grad, a, p->n_list[1], p->block, s, nullptr, nullptr, true));
+  return OK;
+}
+
+// Zero the PML's auxiliary levels and partial sums of one sweep (0 forward, 1 adjoint).
+template <typename T>
+Status zero_pml(Problem* p, int sw, hipStream_t s) {
+  if (!p->pml()) return OK;
+  for (int k = 0; k < 2; ++k) {
+    HIPTRY(launch_fill<T>((T*)p->d_pp[sw][k], T(0), 2 * p->ls * p->nshot, s));
+    HIPTRY(launch_fill<T>((T*)p->d_pt[sw][k], T(0), 2 * p->rs * p->nshot, s));
+  }
+  return OK;
 }
 
 // Finish the shared DOFs of one level (u_cur, S.dsh[q.lvl_cur]) from the partials
@@ -573,6 +612,7 @@ Status forward_run(Problem* p, const double* c, T* traces, T* base, hipStream_t 
   STTRY(clear_flag(p, s));
   STTRY(set_c2<T>(p, c, s));
   STTRY(zero_level<T>(p, p->fwd, base, 0, s));
+  STTRY(zero_pml<T>(p, 0, s));
   return run_forward<T>(p, 0, p->nt, [base, lvl](int64_t n) { return base + (n & 1) * lvl; }, traces, false,
                         s);
 }
@@ -664,6 +704,7 @@ Status adjoint_launch(Problem* p, int64_t m, bool grad, const T* adj_rows, const
 
 template <typename T>
 Status adjoint_start(Problem* p, hipStream_t s) {
+  STTRY(zero_pml<T>(p, 1, s));
   STTRY(zero_level<T>(p, p->adj, lam_ptr<T>(p, p->nt + 1), (int)((p->nt + 1) & 1), s));
   HIPTRY(launch_fill<T>(lam_ptr<T>(p, p->nt), T(0), p->ls * p->nshot, s));
   if (p->lam_k > 2) HIPTRY(launch_fill<T>(lam_ptr<T>(p, p->nt + 2), T(0), p->ls * p->nshot, s));
@@ -682,9 +723,14 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
   const Mesh& m = *p->mesh;
   const int64_t N = m.n_dofs;
   STTRY(plan_storage(p));
+  if (p->pml() && !p->store_all && !p->store_sub)
+    return Status{KMV_ENOMEM, "with the PML the forward states must be kept (all of them, or every r-th with "
+                              "gradient_every = r): they do not fit mem_budget, and recomputing from "
+                              "checkpoints does not carry the auxiliary fields"};
   T* traces = traces_out ? traces_out : (T*)p->d_traces_tmp;
   STTRY(clear_flag(p, s));
   STTRY(set_c2<T>(p, c, s));
+  STTRY(zero_pml<T>(p, 0, s));
   const int64_t r = p->grad_every;
   auto sub_slot = [p, r](int64_t n) { return n % r == 0 ? slot_ptr<T>(p, 2 + n / r) : slot_ptr<T>(p, n & 1); };
   STTRY(zero_level<T>(p, p->fwd, p->store_sub ? sub_slot(0) : slot_ptr<T>(p, 0), 0, s));
@@ -947,7 +993,9 @@ Problem::~Problem() {
                   (void*)d_sh_idx, (void*)d_shp_ptr, (void*)d_shp_slot, (void*)d_ref_slots, (void*)d_gword,
                   (void*)d_glist, (void*)d_gword_off, (void*)d_glist_off, (void*)d_damp_patch, d_gamma, d_gdet, d_beta, d_c2, d_c2_ref, d_gamma_ref, d_beta_ref, d_minv_sqrt, d_lam[0], d_lam[1], d_lam_ring, (void*)d_gacc, (void*)d_red, (void*)d_flag, d_slots,
                   d_ck_u, d_ck_du, d_resid, d_traces_tmp, d_wavelet, (void*)d_bnd_dof, (void*)d_bnd_ref,
-                  (void*)d_bnd_coef, (void*)d_bnd_hb, d_ub, d_lb, (void*)d_bnd_part})
+                  (void*)d_bnd_coef, (void*)d_bnd_hb, d_ub, d_lb, (void*)d_bnd_part, d_sig, d_sig_ref, d_pml_b,
+                  (void*)d_list[0], (void*)d_list[1], d_pp[0][0], d_pp[0][1], d_pp[1][0], d_pp[1][1], d_pt[0][0],
+                  d_pt[0][1], d_pt[1][0], d_pt[1][1]})
     dfree(q);
   free_sweep(fwd);
   free_sweep(adj);
@@ -1112,6 +1160,7 @@ Status set_absorbing_boundary(Problem* p, bool on) {
 
 Status set_damping(Problem* p, const double* eta) {
   DeviceGuard dg(p->device);
+  if (p->pml()) return Status{KMV_ESTATE, "the PML's damping takes the place of eta; turn the PML off first"};
   if (eta) {
     for (int64_t i = 0; i < p->mesh->n_dofs; ++i)
       if (!(eta[i] >= 0) || !std::isfinite(eta[i])) return Status{KMV_EINVAL, "damping must be finite and >= 0"};
@@ -1119,6 +1168,82 @@ Status set_damping(Problem* p, const double* eta) {
   } else {
     p->eta.clear();
   }
+  return upload_coefficients(p);
+}
+
+Status set_pml(Problem* p, const double* sigma) {
+  DeviceGuard dg(p->device);
+  const Mesh& m = *p->mesh;
+  const int64_t N = m.n_dofs;
+  if (!sigma) {
+    p->sigma.clear();
+    p->eta.clear();
+    for (void* q : {p->d_sig, p->d_sig_ref, p->d_pml_b, (void*)p->d_list[0], (void*)p->d_list[1]}) dfree(q);
+    for (int w = 0; w < 2; ++w)
+      for (int k = 0; k < 2; ++k) {
+        dfree(p->d_pp[w][k]);
+        dfree(p->d_pt[w][k]);
+        p->d_pp[w][k] = p->d_pt[w][k] = nullptr;
+      }
+    p->d_sig = p->d_sig_ref = p->d_pml_b = nullptr;
+    p->d_list[0] = p->d_list[1] = nullptr;
+    p->n_list[0] = p->n_list[1] = 0;
+    return upload_coefficients(p);
+  }
+  if (m.dim != 2) return Status{KMV_EINVAL, "the PML is built for triangles (2D)"};
+  for (int64_t i = 0; i < 2 * N; ++i)
+    if (!(sigma[i] >= 0) || !std::isfinite(sigma[i]))
+      return Status{KMV_EINVAL, "PML damping functions must be finite and >= 0"};
+  for (bool adjv : {false, true}) {
+    const size_t bytes =
+        step_lds_bytes(m.dim, m.nd, m.max_nbl, m.slot_stride, m.nb, m.max_glist, adjv, p->ts, true);
+    if (bytes > 160 * 1024) return Status{KMV_EINVAL, "PML patch LDS footprint above 160 KiB; use smaller patches"};
+    if (bytes > 64 * 1024) {
+      if (p->prec == KMV_FP64)
+        HIPTRY(set_step_lds_limit<double>(m.dim, m.nd, adjv, (int)bytes, true));
+      else
+        HIPTRY(set_step_lds_limit<float>(m.dim, m.nd, adjv, (int)bytes, true));
+    }
+  }
+  std::vector<double> sc(2 * N), eta(N), sr(2 * p->rs, 0.0);
+  for (int64_t i = 0; i < N; ++i) {
+    sc[i] = sigma[2 * i];
+    sc[N + i] = sigma[2 * i + 1];
+    eta[i] = sc[i] + sc[N + i];  // tr Psi_1
+  }
+  p->sigma = sc;
+  for (int64_t r = 0; r < m.n_shared_refs; ++r) {
+    sr[r] = sc[m.sh_idx[r]];
+    sr[p->rs + r] = sc[N + m.sh_idx[r]];
+  }
+  p->eta = eta;
+  STTRY(upload_real(&p->d_sig, sc, p->prec));
+  STTRY(upload_real(&p->d_sig_ref, sr, p->prec));
+  {
+    std::vector<double> b(4 * (size_t)m.n_cells);  // B_e = |det J| J^-T, entry (k, r) at (2k + r)
+    for (int64_t e = 0; e < m.n_cells; ++e)
+      for (int k = 0; k < 2; ++k)
+        for (int r = 0; r < 2; ++r) b[(size_t)(2 * k + r) * m.n_cells + e] = m.absdet[e] * m.jinv[e * 4 + r * 2 + k];
+    STTRY(upload_real(&p->d_pml_b, b, p->prec));
+  }
+  // patches with a DOF in the layer run the PML instance
+  std::vector<int32_t> list[2];
+  for (int64_t q = 0; q < m.n_patches; ++q) {
+    bool in = false;
+    for (int32_t i = m.patch_own_start[q]; i < m.patch_own_start[q + 1] && !in; ++i) in = eta[i] != 0.0;
+    for (int32_t r = m.patch_sh_start[q]; r < m.patch_sh_start[q + 1] && !in; ++r) in = eta[m.sh_idx[r]] != 0.0;
+    list[in ? 1 : 0].push_back((int32_t)q);
+  }
+  for (int k = 0; k < 2; ++k) {
+    p->n_list[k] = (int)list[k].size();
+    if (list[k].empty()) list[k].push_back(0);
+    STTRY(upload_i(&p->d_list[k], list[k]));
+  }
+  for (int w = 0; w < 2; ++w)
+    for (int k = 0; k < 2; ++k) {
+      STTRY(alloc(&p->d_pp[w][k], 2 * (size_t)p->ls * p->nshot * p->ts));
+      STTRY(alloc(&p->d_pt[w][k], 2 * (size_t)p->rs * p->nshot * p->ts));
+    }
   return upload_coefficients(p);
 }
 

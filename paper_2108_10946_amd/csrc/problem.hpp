@@ -113,6 +113,17 @@ struct Problem {
   void *d_ub = nullptr, *d_lb = nullptr;  // [n_shots][nt+1][nbd] u^n, lambda^n at the boundary DOFs
   size_t bnd_rec_bytes = 0;
   double* d_bnd_part = nullptr;  // [kBndChunks*nbd] ordered partial sums of the gradient term
+  // PML (triangles): per-axis damping functions sigma_x, sigma_z; its tr Psi_1 is
+  // the damping eta.  Off while sigma is empty.
+  std::vector<double> sigma;    // [2*n_dofs] host, sigma_x then sigma_z
+  void* d_sig = nullptr;        // [2*n_dofs]
+  void* d_sig_ref = nullptr;    // [2*rs] per shared ref
+  void* d_pml_b = nullptr;      // [4*n_cells] |det J| J^-T
+  int32_t* d_list[2] = {nullptr, nullptr};  // patches without / with a DOF in the layer
+  int n_list[2] = {0, 0};
+  void* d_pp[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [sweep][level parity]: [n_shots][2][ls]
+  void* d_pt[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [sweep][step parity]: [n_shots][2][rs]
+  bool pml() const { return !sigma.empty(); }
   // sweeps
   Sweep fwd, adj;
   void* d_lam[2] = {nullptr, nullptr};
@@ -146,6 +157,8 @@ struct Problem {
 Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_every, size_t budget,
                       int n_shots, int64_t grad_every, Problem** out);
 Status set_damping(Problem* p, const double* eta);
+// PML damping functions sigma [n_dofs*2] (sigma_x, sigma_z per DOF), or NULL = off.
+Status set_pml(Problem* p, const double* sigma);
 Status set_absorbing_boundary(Problem* p, bool on);
 Status set_sources(Problem* p, const double* xs, int nsrc, double f0, double t0, double amp);
 Status set_wavelet(Problem* p, const double* w);

@@ -31,7 +31,7 @@ DECLARED = [
     "kmv_mesh_dof_coords", "kmv_mesh_lumped_mass", "kmv_mesh_boundary_mass", "kmv_mesh_cell_dofs", "kmv_mesh_validate",
     "kmv_mesh_patch_stats",
     "kmv_mesh_destroy",
-    "kmv_problem_create", "kmv_cfl_dt", "kmv_spectral_radius", "kmv_set_damping", "kmv_set_absorbing_boundary",
+    "kmv_problem_create", "kmv_cfl_dt", "kmv_spectral_radius", "kmv_set_damping", "kmv_set_pml", "kmv_set_absorbing_boundary",
     "kmv_set_sources", "kmv_set_source_wavelet", "kmv_set_source_wavelets", "kmv_set_receivers", "kmv_forward",
     "kmv_forward_noalloc", "kmv_misfit_gradient", "kmv_misfit_gradient_accumulate", "kmv_misfit", "kmv_problem_status", "kmv_adjoint", "kmv_stiffness_apply", "kmv_problem_info", "kmv_problem_num_shots",
     "kmv_profile_enable", "kmv_profile_read", "kmv_problem_destroy",
@@ -101,6 +101,7 @@ def lib():
         "kmv_cfl_dt": (C.c_int, [_P, _D, _D]),
         "kmv_spectral_radius": (C.c_int, [_P, _P, C.c_int, C.c_uint64, _D, _P]),
         "kmv_set_damping": (C.c_int, [_P, _D]),
+        "kmv_set_pml": (C.c_int, [_P, _D]),
         "kmv_set_absorbing_boundary": (C.c_int, [_P, C.c_int]),
         "kmv_set_sources": (C.c_int, [_P, _D, C.c_int, C.c_double, C.c_double, C.c_double]),
         "kmv_set_source_wavelet": (C.c_int, [_P, _D]),
@@ -278,6 +279,17 @@ def kmv_set_damping(p, eta):
     else:
         eta = np.ascontiguousarray(eta, dtype=np.float64)
         _check(lib().kmv_set_damping(p, _dptr(eta)))
+
+
+def kmv_set_pml(p, sigma):
+    """sigma: [n_dofs, 2] (sigma_x, sigma_z per DOF), or None (off)."""
+    if sigma is None:
+        _check(lib().kmv_set_pml(p, None))
+    else:
+        sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+        if sigma.ndim != 2 or sigma.shape[1] != 2:
+            raise ValueError("sigma must be [n_dofs, 2]")
+        _check(lib().kmv_set_pml(p, _dptr(sigma)))
 
 
 def kmv_set_sources(p, xs, f0, t0, amp=1.0):

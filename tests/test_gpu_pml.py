@@ -1,0 +1,196 @@
+"""The perfectly matched layer on the GPU against the oracle (oracle.pml): misfit,
+traces and gradient for every triangle degree, with the default patches (every
+patch touches the layer on these small meshes) and with small ragged ones (patches
+with and without the layer, shared DOFs between them), several shots, and the
+adjoint's dot-product identity.  Tolerances: FP64 1e-10 relative L2 on J, traces
+and gradient; FP32 1e-4 on the traces and 1e-3 on the gradient; the dot product
+1e-12 (FP64) and 1e-5 (FP32)."""
+import numpy as np
+import pytest
+
+from gpu_util import say, dof_map, rel_l2
+from oracle.fem import Discretization
+from oracle import solver
+from synth import configs
+from synth.models import pml_sigma
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_10946_amd as kmv
+    kmv.lib()
+
+
+@pytest.fixture(scope="module")
+def cache():
+    return {}
+
+
+def case(k, cache, n_shots=1):
+    key = (k, n_shots)
+    if key in cache:
+        return cache[key]
+    coords, cells = configs.small_tri(7, seed=30 + k)
+    d = Discretization(coords, cells, k)
+    x, z = d.dof_coords.T
+    c_true = 1.5 + 0.4 * z + 0.15 * np.exp(-((x - 0.5) ** 2 + (z - 0.45) ** 2) / 0.03)
+    c0 = 1.5 + 0.4 * z
+    sig = pml_sigma(x, z, 0.2, 0.8, 0.75, 0.2, c_max=2.0)
+    srcs = [[[0.45, 0.1]], [[0.6, 0.15]]][:n_shots]
+    rec = np.stack([np.linspace(0.05, 0.95, 7), np.full(7, 0.3)], axis=1)
+    # the step also keeps sigma_max dt <= 0.25 (the workloads have 0.02): the
+    # explicit PML terms, like the stiffness, bound the step (KMV1 on this coarse
+    # mesh would otherwise take sigma_max dt = 3.6, where the scheme grows)
+    dt = min(0.8 * solver.cfl_dt_gershgorin(d.stiffness(c_true), d.lumped_mass()), 0.25 / sig.max())
+    nt = max(60, int(np.ceil(0.6 / dt)))
+    dobs, J, g, tr = [], 0.0, 0.0, []
+    for src in srcs:
+        sh = solver.Shot(d, src, rec, dt, nt, f0=8.0, t0=0.1)
+        do, _ = sh.forward(c_true, pml=sig)
+        Js, gs, ts = sh.misfit_gradient(c0, do, pml=sig)
+        dobs.append(do)
+        tr.append(ts)
+        J += Js
+        g = g + gs
+    cache[key] = dict(coords=coords, cells=cells, d=d, c0=c0, sig=sig, srcs=srcs, rec=rec, nt=nt, dt=dt,
+                      dobs=np.array(dobs), J=J, g=g, tr=np.array(tr))
+    return cache[key]
+
+
+def problem(cs, k, prec, patch, n_shots=1):
+    from paper_2108_10946_amd import Mesh, Problem
+    m = Mesh(cs["coords"], cs["cells"], k, patch_cells=patch)
+    p = dof_map(m.dof_coords(), cs["d"].dof_coords)
+    prob = Problem(m, cs["dt"], cs["nt"], precision=prec, n_shots=n_shots)
+    prob.set_pml(cs["sig"][p])
+    prob.set_sources(np.array(cs["srcs"]) if n_shots > 1 else cs["srcs"][0], f0=8.0, t0=0.1)
+    prob.set_receivers(cs["rec"])
+    return m, p, prob
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("small_patches", [False, True])
+def test_pml_misfit_gradient_every_degree(k, prec, small_patches, cache):
+    cs = case(k, cache)
+    patch = 9 if small_patches else 0
+    say(f"pml: tri k={k} {prec} patch={patch} nt={cs['nt']}")
+    m, p, prob = problem(cs, k, prec, patch)
+    c = torch.as_tensor(cs["c0"][p], dtype=torch.float64, device="cuda")
+    obs = torch.as_tensor(cs["dobs"][0], dtype=prob.dtype, device="cuda")
+    trf = prob.forward(c)
+    prob.status()
+    J, g, tr = prob.misfit_gradient(c, obs, keep_traces=True)
+    prob.close()
+    ef = rel_l2(trf.double().cpu().numpy(), cs["tr"][0])
+    et, eg = rel_l2(tr.double().cpu().numpy(), cs["tr"][0]), rel_l2(g.cpu().numpy(), cs["g"][p])
+    say(f"  J {J:.9e} (oracle {cs['J']:.9e}) forward {ef:.2e} traces {et:.2e} gradient {eg:.2e}")
+    if prec == "fp64":
+        assert abs(J - cs["J"]) < 1e-10 * cs["J"]
+        assert ef < 1e-10 and et < 1e-10 and eg < 1e-10
+    else:
+        assert ef < 1e-4 and et < 1e-4 and eg < 1e-3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pml_two_shots(prec, cache):
+    cs = case(3, cache, n_shots=2)
+    say(f"pml: two shots {prec}")
+    m, p, prob = problem(cs, 3, prec, 9, n_shots=2)
+    c = torch.as_tensor(cs["c0"][p], dtype=torch.float64, device="cuda")
+    obs = torch.as_tensor(cs["dobs"], dtype=prob.dtype, device="cuda")
+    J, g, tr = prob.misfit_gradient(c, obs, keep_traces=True)
+    prob.close()
+    et, eg = rel_l2(tr.double().cpu().numpy(), cs["tr"]), rel_l2(g.cpu().numpy(), cs["g"][p])
+    say(f"  J {J:.9e} (oracle {cs['J']:.9e}) traces {et:.2e} gradient {eg:.2e}")
+    if prec == "fp64":
+        assert abs(J - cs["J"]) < 1e-10 * cs["J"] and et < 1e-10 and eg < 1e-10
+    else:
+        assert et < 1e-4 and eg < 1e-3
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_pml_adjoint_dot_product(prec, tol, cache):
+    """<y, P u> = dt^2 sum_n w(t_n) s . lambda^{n+1}(y) for the coupled u, p scheme."""
+    cs = case(4, cache)
+    say(f"pml: dot product {prec}")
+    m, p, prob = problem(cs, 4, prec, 9)
+    c = torch.as_tensor(cs["c0"][p], dtype=torch.float64, device="cuda")
+    u = prob.forward(c)
+    y = torch.as_tensor(np.random.default_rng(5).standard_normal(u.shape), dtype=prob.dtype, device="cuda")
+    _, st = prob.adjoint(c, y, src_trace=True)
+    w = solver.ricker(np.arange(cs["nt"]) * cs["dt"], 8.0, 0.1)
+    lhs = float((y.double() * u.double()).sum())
+    rhs = cs["dt"] ** 2 * float(np.sum(w[:, None] * st.double().cpu().numpy()))
+    prob.close()
+    say(f"  <y, Pu> {lhs:.12e}  dt^2 sum w s.lam {rhs:.12e}")
+    assert abs(lhs - rhs) < tol * abs(lhs)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pml_gradient_subsampling(prec, cache):
+    """gradient_every = 3: the reverse launches that do not pair still take the
+    transposed PML couplings; the pairing (with its PML term) every third step."""
+    from paper_2108_10946_amd import Problem
+    cs = case(3, cache)
+    say(f"pml: gradient subsampling r=3 {prec}")
+    d = cs["d"]
+    sh = solver.Shot(d, cs["srcs"][0], cs["rec"], cs["dt"], cs["nt"], f0=8.0, t0=0.1)
+    J_or, g_or, _ = sh.misfit_gradient(cs["c0"], cs["dobs"][0], pml=cs["sig"], r=3)
+    m, p, prob0 = problem(cs, 3, prec, 9)
+    prob0.close()
+    prob = Problem(m, cs["dt"], cs["nt"], precision=prec, gradient_every=3)
+    prob.set_pml(cs["sig"][p])
+    prob.set_sources(cs["srcs"][0], f0=8.0, t0=0.1)
+    prob.set_receivers(cs["rec"])
+    c = torch.as_tensor(cs["c0"][p], dtype=torch.float64, device="cuda")
+    J, g, _ = prob.misfit_gradient(c, torch.as_tensor(cs["dobs"][0], dtype=prob.dtype, device="cuda"))
+    prob.close()
+    eg = rel_l2(g.cpu().numpy(), g_or[p])
+    say(f"  J {J:.9e} (oracle {J_or:.9e}) gradient {eg:.2e}")
+    assert eg < (1e-10 if prec == "fp64" else 1e-3)
+
+
+def test_pml_limits_and_switching(cache):
+    from paper_2108_10946_amd import Mesh, Problem
+    from paper_2108_10946_amd import kmvwave as K
+    cs = case(2, cache)
+    say("pml: limits and switching off")
+    m, p, prob = problem(cs, 2, "fp64", 0)
+    with pytest.raises(K.KMVError) as e:
+        prob.set_damping(np.zeros(m.n_dofs))
+    assert e.value.code == K.KMV_ESTATE
+    c = torch.as_tensor(cs["c0"][p], dtype=torch.float64, device="cuda")
+    obs = torch.as_tensor(cs["dobs"][0], device="cuda")
+    # checkpoints do not carry the auxiliary fields: refused
+    ck = Problem(m, cs["dt"], cs["nt"], precision="fp64", checkpoint_every=10)
+    ck.set_pml(cs["sig"][p])
+    ck.set_sources(cs["srcs"][0], f0=8.0, t0=0.1)
+    ck.set_receivers(cs["rec"])
+    with pytest.raises(K.KMVError) as e:
+        ck.misfit_gradient(c, obs)
+    assert e.value.code == K.KMV_ENOMEM
+    ck.close()
+    # off again: bitwise the problem that never had it
+    prob.set_pml(None)
+    a = prob.forward(c)
+    plain = Problem(m, cs["dt"], cs["nt"], precision="fp64")
+    plain.set_sources(cs["srcs"][0], f0=8.0, t0=0.1)
+    plain.set_receivers(cs["rec"])
+    assert torch.equal(a, plain.forward(c))
+    plain.close()
+    prob.close()
+    # tetrahedra: refused
+    coords, cells = configs.small_tet(2, seed=1)
+    mt = Mesh(coords, cells, 1)
+    pt = Problem(mt, 1e-3, 4, precision="fp64")
+    with pytest.raises(K.KMVError) as e:
+        pt.set_pml(np.zeros((mt.n_dofs, 2)))
+    assert e.value.code == K.KMV_EINVAL
+    pt.close()

@@ -219,3 +219,17 @@ def test_auxiliary_damping_centring(sdt):
     assert np.abs(centred).max() < 1.0
     assert np.abs(level_n).max() == pytest.approx(sdt + np.sqrt(1.0 + sdt * sdt), rel=1e-12)
     assert np.abs(level_n).max() > 1.0
+
+
+def test_pml_subsampling_partitions_the_full_gradient():
+    """Gradient subsampling with the PML: the mean over the r offsets of the r-scaled
+    subsampled gradients is the full gradient (the pairing sum partitioned by m mod r)."""
+    d, sig, c = small2d()
+    K, M = d.stiffness(c), d.lumped_mass()
+    dt = 0.7 * solver.cfl_dt_gershgorin(K, M)
+    x = d.dof_coords
+    sh = solver.Shot(d, [[0.5, 0.3]], [[0.3, 0.6], [0.7, 0.5]], dt, 90, f0=6.0, t0=0.15)
+    dobs, _ = sh.forward(c * (1.0 + 0.05 * np.exp(-np.sum((x - 0.45) ** 2, axis=1) / 0.02)), pml=sig)
+    _, g, _ = sh.misfit_gradient(c, dobs, pml=sig)
+    gs = [sh.misfit_gradient(c, dobs, pml=sig, r=3, offset=o)[1] for o in range(3)]
+    assert np.abs(sum(gs) / 3.0 - g).max() < 1e-12 * np.abs(g).max()
