@@ -16,6 +16,17 @@ Names describe the workload:
                     full model, current model = layers only.
   layered_kmv4_40shots  the same with 40 shots along the surface.
   serving_meshes    three layered/anomaly meshes of about 20k, 80k, 300k cells.
+  gradient_check_2d the gradient-verification problem: 1 km x 1 km physical
+                    domain, upper half 4.0 km/s and lower half 1.0 km/s (initial
+                    model 4.0 km/s everywhere), a 200 m absorbing layer (sponge or
+                    PML) on the left, right and bottom, uniform right triangles with
+                    20 m legs (8400 cells), KMV2, a 5 Hz Ricker at 0.1 km depth,
+                    100 receivers at 0.9 km depth from x = 0.1 to 0.9 km, T = 1 s,
+                    dt = 0.5 ms.
+  gradient_check_3d its 3D analogue: 1 km cube, 200 m sponge on the five faces
+                    other than the top, Kuhn tetrahedra with 20 m box edges (1.76M
+                    cells), KMV2tet, source at (0.5, 0.5, 0.1), a 10 x 10 receiver
+                    grid at 0.9 km depth over [0.1, 0.9]^2, T = 1 s, dt = 0.5 ms.
   layered_tet_kmv3  3D 4 x 4 x 2 km layered + anomalies, 500 m sponge on five
                     faces, Maubach-graded Kuhn tetrahedra (shortest edge below
                     s * vp / (5 Hz * 2.5), s = 0.355 -> 1.33M tetrahedra, 16.9M KMV3 DOFs),
@@ -33,7 +44,8 @@ import numpy as np
 from .meshes import (structured_tri, nvb_graded_tri, jitter_vertices, kuhn_tet_box,
                      graded_tet_box)
 from .models import (homogeneous_vp, layered_anomaly_vp, layered_anomaly_vp_3d, sponge_eta,
-                     sponge_eta_3d, surface_receivers, surface_sources, grid_receivers_3d)
+                     sponge_eta_3d, surface_receivers, surface_sources, grid_receivers_3d, pml_sigma,
+                     pml_sigma_3d)
 
 
 @dataclass
@@ -156,3 +168,54 @@ def layered_tet_kmv3(seed=21, coarse_h=0.5, scale=0.355):
         sources=np.array([[2.0, 2.0, 0.01]]),
         receivers=grid_receivers_3d(40, 40, (0.1, 0.1), (3.9, 3.9), 0.1),
         T=2.0, dt=None, extra={"seed": seed, "scale": scale})
+
+
+def _half_space(v_top, v_bottom, depth):
+    """v_top above the depth, v_bottom at and below it."""
+    def f(*xs):
+        return np.where(np.asarray(xs[-1], dtype=np.float64) < depth, float(v_top), float(v_bottom))
+    return f
+
+
+@functools.lru_cache(maxsize=None)
+def gradient_check_2d(le=0.02, width=0.2):
+    """The paper's 2D gradient-verification problem (a reading of its layout: the
+    slow half is the lower one, between source and receivers, so the experiment is
+    a transmission through the interface).  extra['sigma'](x, z) gives the PML's
+    per-axis damping functions; eta is their sum (the sponge)."""
+    nx, nz = int(round((1.0 + 2 * width) / le)), int(round((1.0 + width) / le))
+    coords, cells = structured_tri(nx, nz, -width, 1.0 + width, 0.0, 1.0 + width)
+    c_max = 4.0
+
+    def eta(x, z):
+        return sponge_eta(x, z, 0.0, 1.0, 1.0, width, c_max=c_max)
+
+    def sigma(x, z):
+        return pml_sigma(x, z, 0.0, 1.0, 1.0, width, c_max=c_max)
+
+    return Workload(
+        name="gradient_check_2d", dim=2, degree=2, coords=coords, cells=cells,
+        vp=homogeneous_vp(4.0), vp_obs=_half_space(4.0, 1.0, 0.5), eta=eta,
+        sources=np.array([[0.5, 0.1]]), receivers=surface_receivers(100, 0.1, 0.9, 0.9),
+        T=1.0, dt=5e-4, extra={"sigma": sigma, "width": width, "le": le})
+
+
+@functools.lru_cache(maxsize=None)
+def gradient_check_3d(le=0.02, width=0.2):
+    """The 3D analogue of gradient_check_2d (sponge on five faces)."""
+    n = int(round((1.0 + 2 * width) / le))
+    nzz = int(round((1.0 + width) / le))
+    coords, cells = kuhn_tet_box(n, n, nzz, (-width, -width, 0.0), (1.0 + width, 1.0 + width, 1.0 + width))
+    c_max = 4.0
+
+    def eta(x, y, z):
+        return sponge_eta_3d(x, y, z, (0.0, 0.0), (1.0, 1.0, 1.0), width, c_max=c_max)
+
+    def sigma(x, y, z):
+        return pml_sigma_3d(x, y, z, (0.0, 0.0), (1.0, 1.0, 1.0), width, c_max=c_max)
+
+    return Workload(
+        name="gradient_check_3d", dim=3, degree=2, coords=coords, cells=cells,
+        vp=homogeneous_vp(4.0), vp_obs=_half_space(4.0, 1.0, 0.5), eta=eta,
+        sources=np.array([[0.5, 0.5, 0.1]]), receivers=grid_receivers_3d(10, 10, (0.1, 0.1), (0.9, 0.9), 0.9),
+        T=1.0, dt=5e-4, extra={"sigma": sigma, "width": width, "le": le})
