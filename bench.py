@@ -107,7 +107,7 @@ WORKLOADS = ("layered_kmv4", "layered_tet_kmv3")
 
 
 def setup_workload(precision, budget_frac=0.75, window=0, workload="layered_kmv4", checkpoint_every=0,
-                   mesh_cache={}, problem=True, gradient_every=1, absorbing=False):
+                   mesh_cache={}, problem=True, gradient_every=1, absorbing=False, pml=False):
     import torch
     from paper_2108_10946_amd import Mesh, Problem
     from synth import configs
@@ -138,7 +138,10 @@ def setup_workload(precision, budget_frac=0.75, window=0, workload="layered_kmv4
         return w, m, None, c_cur, None, dt, nt
     prob = Problem(m, dt, nt, precision=precision, mem_budget=budget, checkpoint_every=checkpoint_every,
                    gradient_every=gradient_every)
-    prob.set_damping(eta)
+    if pml:
+        prob.set_pml(w.extra["sigma"](*x.T))
+    else:
+        prob.set_damping(eta)
     if absorbing:
         prob.set_absorbing_boundary(True)
     prob.set_sources(w.sources, f0=w.f0, t0=w.t0, amp=w.amp)
@@ -149,12 +152,12 @@ def setup_workload(precision, budget_frac=0.75, window=0, workload="layered_kmv4
 
 
 def time_gpu(precision, steps, warmup, every, window=0, workload="layered_kmv4", checkpoint_every=0,
-             gradient_every=1, absorbing=False):
+             gradient_every=1, absorbing=False, pml=False):
     import torch
     from paper_2108_10946_amd import kmvwave as K
     w, m, prob, c, obs, dt, nt = setup_workload(precision, window=window, workload=workload,
                                                 checkpoint_every=checkpoint_every, gradient_every=gradient_every,
-                                                absorbing=absorbing)
+                                                absorbing=absorbing, pml=pml)
     K.kmv_profile_enable(prob.handle, every)
     for i in range(warmup):
         t = time.time()
@@ -287,7 +290,7 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - np.asarray(b, np.float64)) / np.linalg.norm(b))
 
 
-def serving_bench(n_requests=48, t_scale=0.1, slots=6, load=0.7, seed=11):
+def serving_bench(n_requests=32, t_scale=1.0, slots=6, load=0.7, seed=11):
     """The serving mix: Poisson arrivals of shot requests over three seeded layered
     meshes (about 20k, 80k and 300k triangles), KMV degree uniform in {2,3,4,5},
     duration uniform in [1, 4] s x t_scale, 10% forward-only, the rest misfit +
@@ -474,84 +477,191 @@ def bench_3d(args):
     print(json.dumps(out), flush=True)
 
 
-def multi_shot_bench(shots=8, every=16, subsample=10):
-    """Several shots of the 40-shot line (x_s = linspace(0.1, 7.9, 40), every fifth
-    one) in one problem: one launch per step advances all of them.  Observed data
-    from the layered model with anomalies, current model the layers only; the whole
-    T = 4 s window; reverse sweep from checkpoints (segments of sqrt(2 N_t) steps),
-    since the stored states of several shots exceed the GPU's memory."""
+def five_gaussians(x, seed=17, n=5, radius=0.5, box=(0.0, 8.0, 0.0, 3.0)):
+    """The seeded smooth perturbation direction of the 40-shot check: a sum of n
+    Gaussians of the given radius (km) with seeded centres and signs in the physical
+    box, scaled to a maximum of 1 km/s and zero outside the box (the sponge)."""
+    rng = np.random.default_rng(seed)
+    x0, x1, z0, z1 = box
+    cx = x0 + (x1 - x0) * rng.random(n)
+    cz = z0 + (z1 - z0) * rng.random(n)
+    sg = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    d = sum(s * np.exp(-((x[:, 0] - a) ** 2 + (x[:, 1] - b) ** 2) / radius ** 2) for s, a, b in zip(sg, cx, cz))
+    inside = (x[:, 0] >= x0) & (x[:, 0] <= x1) & (x[:, 1] >= z0) & (x[:, 1] <= z1)
+    d = np.where(inside, d, 0.0)
+    return d / np.abs(d).max()
+
+
+def c3_bench(n_shots=40, batch=8, h=1e-3, every=16, subsample=10):
+    """The 40-shot FWI gradient of the layered KMV4 workload: shots at
+    x_s = linspace(0.1, 7.9, 40), 10 m deep, T = 4 s; observed data from the model
+    with anomalies (FP64), current model the layers.  J and dJ/dc are summed over
+    the shots through the torch.autograd.Function (fwi_misfit) over 5 problems of 8
+    shots (one launch per step for 8 shots, J and the gradient accumulated in the
+    library), FP32 fields with FP64 accumulation, checkpointed reverse sweep.
+    Checks: central differences of J at h along the seeded five-Gaussian direction
+    (zero in the sponge) against the gradient; the adjoint's dot-product identity
+    on one 8-shot problem; the FP32 J and gradient against the same 40 shots in
+    FP64; and the 40 shots with the paper's gradient subsampling (r = 10)."""
     import torch
     from paper_2108_10946_amd import Problem, kmvwave as K
-    from synth import configs
+    from paper_2108_10946_amd.autograd import fwi_misfit
     w, m, _, c_cur, _, dt, nt = setup_workload("fp32", workload="layered_kmv4", problem=False)
     x = m.dof_coords()
+    eta = w.eta(*x.T)
     c_obs = torch.tensor(w.vp_obs(*x.T), dtype=torch.float64, device="cuda")
-    line = np.linspace(0.1, 7.9, 40)
-    pick = line[::40 // shots][:shots]
-    xs = np.stack([[[xx, 0.01]] for xx in pick])
+    line = np.linspace(0.1, 7.9, n_shots)
+    groups = [np.stack([[[xx, 0.01]] for xx in line[k:k + batch]]) for k in range(0, n_shots, batch)]
+
+    def make(prec, xs, budget, r=1, ck=-1):
+        p = Problem(m, dt, nt, precision=prec, n_shots=len(xs), checkpoint_every=ck, mem_budget=budget,
+                    gradient_every=r)
+        p.set_damping(eta)
+        p.set_sources(xs, f0=w.f0, t0=w.t0, amp=w.amp)
+        p.set_receivers(w.receivers)
+        return p
+
     free, _ = torch.cuda.mem_get_info()
-    prob = Problem(m, dt, nt, precision="fp32", n_shots=shots, checkpoint_every=-1,
-                   mem_budget=int(free * 0.45))
-    prob.set_damping(w.eta(*x.T))
-    prob.set_sources(xs, f0=w.f0, t0=w.t0, amp=w.amp)
-    prob.set_receivers(w.receivers)
+    # FP64: observed data and the reference J and gradient, one 8-shot problem at a time
     t = time.time()
-    obs = prob.forward(c_obs)
+    obs64, J64, g64 = [], 0.0, torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda")
+    for xs in groups:
+        p = make("fp64", xs, int(free * 0.4))
+        obs64.append(p.forward(c_obs))
+        J64 = p.misfit_gradient_accumulate(c_cur, obs64[-1], J64, g64)
+        p.close()
     torch.cuda.synchronize()
-    log(f"multi-shot: observed data for {shots} shots ({time.time() - t:.1f}s)")
-    J, g, _ = prob.misfit_gradient(c_cur, obs)  # warm-up
-    K.kmv_profile_enable(prob.handle, every)
+    sec64 = time.time() - t
+    log(f"c3: FP64 observed data and 40-shot J, gradient ({sec64:.1f}s)")
+    # FP32 through the autograd Function, 5 problems of 8 shots
+    free, _ = torch.cuda.mem_get_info()
+    probs = [make("fp32", xs, int(free * 0.15)) for xs in groups]
+    obs32 = [o.float().contiguous() for o in obs64]
+    K.kmv_profile_enable(probs[0].handle, every)
+    cg = c_cur.clone().requires_grad_(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    J, g, _ = prob.misfit_gradient(c_cur, obs)
+    J = fwi_misfit(cg, probs, obs32)
+    J.backward()
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
-    prof = {K.PROFILE_VARIANTS[v]: K.kmv_profile_read(prob.handle, v) for v in K.PROFILE_VARIANTS}
-    info = prob.info()
-    prob.close()
+    J32, g32 = float(J), cg.grad.detach().clone()
+    prof = {K.PROFILE_VARIANTS[v]: K.kmv_profile_read(probs[0].handle, v) for v in K.PROFILE_VARIANTS}
+    info = probs[0].info()
+    value = m.n_dofs * nt * n_shots / sec
+    log(f"c3: 40 shots FP32 misfit + gradient in {sec:.2f}s -> {value:.4g} DOF-timesteps/s")
+    # central differences (J only) along the five-Gaussian direction
+    ct = torch.as_tensor(five_gaussians(x), dtype=torch.float64, device="cuda")
+    with torch.no_grad():
+        Jp = float(fwi_misfit(c_cur + h * ct, probs, obs32))
+        Jm = float(fwi_misfit(c_cur - h * ct, probs, obs32))
+    fd = (Jp - Jm) / (2 * h)
+    an = float(torch.dot(ct, g32))
+    log(f"c3: central differences {fd:.9e} vs gradient {an:.9e} ({abs(fd - an) / abs(an):.2e})")
+    # dot-product identity on one 8-shot problem
+    p0 = probs[0]
+    u = p0.forward(c_cur)
+    y = torch.randn(u.shape, generator=torch.Generator(device="cuda").manual_seed(3), device="cuda",
+                    dtype=torch.float32)
+    _, st = p0.adjoint(c_cur, y, src_trace=True)
+    wav = torch.as_tensor(np.asarray([w.amp * (1 - 2 * (np.pi * w.f0 * (n * dt - w.t0)) ** 2)
+                                      * np.exp(-(np.pi * w.f0 * (n * dt - w.t0)) ** 2) for n in range(nt)]),
+                          dtype=torch.float64, device="cuda")
+    lhs = float((y.double() * u.double()).sum())
+    rhs = dt * dt * float((wav[None, :, None] * st.double()).sum())
+    for p in probs:
+        p.close()
+    del probs
+    torch.cuda.empty_cache()
+    # the paper's gradient subsampling over the 40 shots, r = 10 (every 10th state kept)
     sub = None
     if subsample > 1:
-        # the paper's gradient subsampling: pairing and stored states every r-th step only
-        ps = Problem(m, dt, nt, precision="fp32", n_shots=shots, gradient_every=subsample,
-                     mem_budget=int(free * 0.45))
-        ps.set_damping(w.eta(*x.T))
-        ps.set_sources(xs, f0=w.f0, t0=w.t0, amp=w.amp)
-        ps.set_receivers(w.receivers)
-        ps.misfit_gradient(c_cur, obs)
+        free, _ = torch.cuda.mem_get_info()
+        t = time.time()
+        Js, gs = 0.0, torch.zeros_like(g32)
+        for xs, o in zip(groups, obs32):
+            p = make("fp32", xs, int(free * 0.6), r=subsample, ck=0)
+            Js = p.misfit_gradient_accumulate(c_cur, o, Js, gs)
+            p.close()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        Js, gs, _ = ps.misfit_gradient(c_cur, obs)
-        torch.cuda.synchronize()
-        secs = time.perf_counter() - t0
-        sinfo = ps.info()
-        ps.close()
-        rel = float(torch.linalg.vector_norm(gs - g) / torch.linalg.vector_norm(g))
-        sub = {"gradient_every": subsample, "value": round(m.n_dofs * nt * shots / secs, 1),
+        secs = time.time() - t
+        sub = {"gradient_every": subsample, "value": round(m.n_dofs * nt * n_shots / secs, 1),
                "sec_per_misfit_gradient": round(secs, 3),
-               "storage": ("every r-th state kept, no recompute" if sinfo["checkpoint_every"] == 0
-                           else f"checkpoints every {sinfo['checkpoint_every']} steps"),
-               "gradient_rel_l2_vs_exact": rel}
-        log(f"multi-shot, gradient every {subsample} steps: {secs:.2f} s, "
-            f"{sub['value']:.4g} DOF-timesteps/s, gradient vs exact {rel:.2e}")
+               "gradient_rel_l2_vs_exact": float(torch.linalg.vector_norm(gs - g32) / torch.linalg.vector_norm(g32)),
+               "note": "problems of 8 shots one after another, every 10th state kept (no recompute); "
+                       "allocation included"}
+        log(f"c3: gradient every {subsample} steps: {secs:.2f}s, gradient vs exact {sub['gradient_rel_l2_vs_exact']:.2e}")
     res = dict(n_dofs=m.n_dofs, n_cells=m.n_cells, prof=prof)
-    roofline(res, 4, shots=shots)
-    value = m.n_dofs * nt * shots / sec
-    log(f"multi-shot: {shots} shots, {sec:.2f} s per misfit+gradient, {value:.4g} DOF-timesteps/s, J={J:.6g}")
+    roofline(res, 4, shots=batch)
     us = {k: round(v["mean_ms"] * 1e3, 3) for k, v in prof.items()}
     return {
-        "workload": f"{shots} shots (every fifth of the 40-shot surface line) of the layered KMV4 workload "
-                    "in one problem: one launch per step for all shots, FP32 fields, float64 misfit and "
-                    "gradient summed over the shots, checkpointed reverse sweep",
-        "shots": shots, "value": round(value, 1), "unit": "DOF-timesteps/s",
-        "sec_per_misfit_gradient": round(sec, 3), "n_steps": nt,
-        "checkpoint_every": info["checkpoint_every"], "J": J,
+        "workload": f"{n_shots} shots (x_s = linspace(0.1, 7.9, {n_shots}), 10 m deep) of the layered KMV4 "
+                    "workload, T = 4 s; J and dJ/dc summed over the shots through the torch.autograd.Function "
+                    f"over {len(groups)} problems of {batch} shots (one launch per step for {batch} shots), "
+                    "FP32 fields with float64 misfit and gradient accumulation, checkpointed reverse sweep",
+        "shots": n_shots, "value": round(value, 1), "unit": "DOF-timesteps/s", "sec_per_misfit_gradient": round(sec, 3),
+        "n_steps": nt, "checkpoint_every": info["checkpoint_every"],
+        "J": J32,
+        "fp32_vs_fp64": {"J": abs(J32 - J64) / abs(J64),
+                         "grad": float(torch.linalg.vector_norm(g32 - g64) / torch.linalg.vector_norm(g64))},
+        "central_differences": {"h": h, "direction": "five seeded Gaussians (r = 0.5 km), max 1 km/s, zero in "
+                                                     "the sponge", "fd": fd, "gradient": an,
+                                "rel_err": abs(fd - an) / abs(an)},
+        "dot_product": {"problem": f"one {batch}-shot problem, FP32, seeded normal adjoint data",
+                        "lhs": lhs, "rhs": rhs, "rel_err": abs(lhs - rhs) / abs(lhs)},
+        "fp64_reference_sec": round(sec64, 3),
         "kernel_mean_us": us,
-        "per_shot_step_us": {"forward": round(us["patch_forward"] / shots, 3),
-                             "adjoint": round(us["patch_adjoint"] / shots, 3)},
+        "per_shot_step_us": {"forward": round(us["patch_forward"] / batch, 3),
+                             "adjoint": round(us["patch_adjoint"] / batch, 3)},
         "rooflines": {k: {kk: vv for kk, vv in v.items() if kk != "total_ms"}
                       for k, v in res.get("rooflines", {}).items()},
         "gradient_subsampling": sub,
     }
+
+
+def gradient_check_bench(le3d=0.0):
+    """The paper's gradient verification (2D: KMV2 on 20 m triangles, 2000 steps;
+    with the sponge and with the PML) in FP64 and FP32: d^co = c~^T M G along the
+    masked gradient against forward differences at h = 1e-3, 1e-4, 1e-5.  le3d > 0
+    adds the 3D KMV2tet analogue with that box edge (sponge)."""
+    import torch
+    from paper_2108_10946_amd import Mesh, Problem
+    from paper_2108_10946_amd.fwi import directional_derivative_check
+    from synth import configs
+    cases = [("2d", "sponge", configs.gradient_check_2d()), ("2d", "pml", configs.gradient_check_2d())]
+    if le3d > 0:
+        cases.append(("3d", "sponge", configs.gradient_check_3d(le=le3d)))
+    out = {}
+    for dim, layer, w in cases:
+        t = time.time()
+        m = Mesh(w.coords, w.cells, w.degree)
+        x = m.dof_coords()
+        nt = int(round(w.T / w.dt))
+        c = torch.as_tensor(w.vp(*x.T), dtype=torch.float64, device="cuda")
+        c_true = torch.as_tensor(w.vp_obs(*x.T), dtype=torch.float64, device="cuda")
+        inside = w.eta(*x.T) == 0.0
+        rows = {}
+        obs = None
+        for prec in ("fp64", "fp32"):
+            p = Problem(m, w.dt, nt, precision=prec, mem_budget=64 << 30)
+            if layer == "pml":
+                p.set_pml(w.extra["sigma"](*x.T))
+            else:
+                p.set_damping(w.eta(*x.T))
+            p.set_sources(w.sources, f0=w.f0, t0=w.t0)
+            p.set_receivers(w.receivers)
+            if obs is None:
+                obs = p.forward(c_true)  # FP64 observed data
+            r = directional_derivative_check(p, c, obs.to(p.dtype), mask=inside)
+            p.close()
+            rows[prec] = {"d_co": r["d_co"], "d_fd": {f"{h:g}": v for h, v in r["d_fd"].items()},
+                          "rel_err": {f"{h:g}": v for h, v in r["rel_err"].items()}, "J": r["J"]}
+        key = f"{dim}_{layer}"
+        out[key] = dict(rows, n_cells=len(w.cells), n_dofs=m.n_dofs, n_steps=nt)
+        log(f"gradient check {key}: d_co {rows['fp64']['d_co']:.6g}, rel err "
+            + ", ".join(f"{h}: {v:.1e}" for h, v in rows["fp64"]["rel_err"].items()) + f" ({time.time() - t:.1f}s)")
+        m.close()
+    return out
 
 
 def copy_bandwidth(n_bytes=2 << 30, reps=10):
@@ -602,19 +712,27 @@ def main():
                     help="layered_tet_kmv3: the 3D workload (FP32, checkpointed reverse sweep, "
                          "ALU roofline); not the bench line")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--no-multi-shot", action="store_true")
-    ap.add_argument("--multi-shot", type=int, default=8, help="shots per problem in the multi-shot leg")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 40-shot leg")
+    ap.add_argument("--c3-batch", type=int, default=8, help="shots per problem in the 40-shot leg")
+    ap.add_argument("--no-pml", action="store_true", help="skip the leg with the PML in place of the sponge")
+    ap.add_argument("--pml-only", action="store_true", help="run only the PML leg (for a kernel-trace profile)")
+    ap.add_argument("--no-gradient-check", action="store_true")
+    ap.add_argument("--gradient-check-only", action="store_true",
+                    help="run only the gradient verification (with --gradient-check-3d for the 3D case)")
+    ap.add_argument("--gradient-check-3d", type=float, default=0.0,
+                    help="box edge (km) of the 3D gradient verification (0: skip; 0.02: the full size)")
     ap.add_argument("--subsample", type=int, default=10,
                     help="also time the paper's gradient subsampling with this ratio (1: skip)")
     ap.add_argument("--no-absorbing", action="store_true",
                     help="skip the leg with the absorbing boundary term on")
     ap.add_argument("--absorbing-only", action="store_true",
                     help="run only the absorbing-boundary leg (for a kernel-trace profile)")
-    ap.add_argument("--multi-shot-only", action="store_true",
-                    help="run only the multi-shot leg and print its object (profiling runs)")
-    ap.add_argument("--serving-requests", type=int, default=48)
-    ap.add_argument("--serving-scale", type=float, default=0.1,
-                    help="request durations are U[1,4] s times this (1.0: the full mix)")
+    ap.add_argument("--c3-only", action="store_true",
+                    help="run only the 40-shot leg and print its object (profiling runs)")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving mix")
+    ap.add_argument("--serving-requests", type=int, default=32)
+    ap.add_argument("--serving-scale", type=float, default=1.0,
+                    help="request durations are U[1,4] s times this (1.0: the configuration's own mix)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -633,8 +751,15 @@ def main():
     if args.workload == "layered_tet_kmv3":
         bench_3d(args)
         return
-    if args.multi_shot_only:
-        print(json.dumps({"multi_shot": multi_shot_bench(args.multi_shot, subsample=args.subsample)}), flush=True)
+    if args.c3_only:
+        print(json.dumps({"c3_40_shots": c3_bench(batch=args.c3_batch, subsample=args.subsample)}), flush=True)
+        return
+    if args.gradient_check_only:
+        print(json.dumps({"gradient_check": gradient_check_bench(args.gradient_check_3d)}), flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": serving_bench(n_requests=args.serving_requests,
+                                                   t_scale=args.serving_scale)}), flush=True)
         return
     import paper_2108_10946_amd as kmv
     kmv.lib()
@@ -654,6 +779,21 @@ def main():
         print(json.dumps({"absorbing_boundary": absorbing_leg()}), flush=True)
         return
 
+    def pml_leg(ref_sec=None):
+        a = time_gpu("fp32", args.steps, min(1, args.warmup), args.profile_every, pml=True)
+        out = {"value": round(a["n_dofs"] * a["nt"] / a["sec"], 1), "ms_per_step": round(a["sec"] * 1e3, 3),
+               "kernel_mean_us": {k: round(v["mean_ms"] * 1e3, 3) for k, v in a["prof"].items()},
+               "note": "the 750 m layer as the paper's PML (auxiliary p on the patches touching the layer, "
+                       "their own kernel instance) in place of the sponge; observed data with the same "
+                       "layer; kernel_mean_us times the launch over the patches away from the layer"}
+        if ref_sec:
+            out["overhead_vs_sponge"] = round(a["sec"] / ref_sec - 1.0, 4)
+        return out
+
+    if args.pml_only:
+        print(json.dumps({"pml": pml_leg()}), flush=True)
+        return
+
     res32 = time_gpu("fp32", args.steps, args.warmup, args.profile_every, args.window)
     rl = roofline(res32, 4)
     sub1 = None
@@ -662,14 +802,20 @@ def main():
     absorb = None
     if not args.window and not args.no_absorbing:
         absorb = absorbing_leg(res32["sec"])
+    pml = None
+    if not args.window and not args.no_pml:
+        pml = pml_leg(res32["sec"])
     res64 = None
     if not args.no_fp64:
         res64 = time_gpu("fp64", max(1, args.steps // 2), min(1, args.warmup), args.profile_every,
                          args.window)
         roofline(res64, 8)
     multi = None
-    if not args.no_multi_shot and not args.window:
-        multi = multi_shot_bench(args.multi_shot, subsample=args.subsample)
+    if not args.no_c3 and not args.window:
+        multi = c3_bench(batch=args.c3_batch, subsample=args.subsample)
+    gcheck = None
+    if not args.no_gradient_check and not args.window:
+        gcheck = gradient_check_bench()
     serving = None
     if not args.no_serving and not args.window:
         serving = serving_bench(n_requests=args.serving_requests, t_scale=args.serving_scale)
@@ -713,7 +859,11 @@ def main():
         "cpu_baseline": cpu,
     }
     if multi:
-        out["multi_shot"] = multi
+        out["c3_40_shots"] = multi
+    if pml:
+        out["pml"] = pml
+    if gcheck:
+        out["gradient_check"] = gcheck
     if sub1:
         out["gradient_subsampling"] = {
             "gradient_every": args.subsample,

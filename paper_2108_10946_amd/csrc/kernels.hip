@@ -42,9 +42,10 @@ __host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) / 16 * 
 // the slot arrays are the largest part, and LDS limits the resident workgroups).
 // With gst (2D adjoints whose occupancy registers limit, not LDS) the float64
 // gradient accumulators of the owned non-interior DOFs follow, at sg.
-// With pml (2D) the auxiliary level and the two damping functions of the
-// non-interior DOFs follow at sp (four arrays of LB), then the two cell-node slot
-// arrays of the gradient term t at st.
+// With pml (2D) the auxiliary level, the two damping functions, and for the owned
+// DOFs' update the previous auxiliary level, gamma and beta of the non-interior DOFs
+// follow at sp (eight arrays of LB), then the two cell-node slot arrays of the
+// gradient term t at st.
 struct StepLds {
   size_t sx, gl, sg, sp, st, total;
   __host__ __device__ StepLds(int LB, int cs, int nb, int glmax, bool adj, size_t ts, bool ovl, bool gst,
@@ -62,7 +63,7 @@ struct StepLds {
     total = sg + (gst ? align16((size_t)LB * 8) : 0);
     sp = st = total;
     if (pml) {
-      st = sp + align16((size_t)4 * LB * ts);
+      st = sp + align16((size_t)8 * LB * ts);
       total = st + align16((size_t)2 * nslot * ts);
     }
   }
@@ -196,6 +197,10 @@ k_step(const StepArgs<T> A0) {
   T* sPz = sPx + LB;
   T* sSx = sPz + LB;
   T* sSz = sSx + LB;
+  T* sQx = sSz + LB;  // owned: the auxiliary level n-1 (adjoint: m+2), gamma, beta
+  T* sQz = sQx + LB;
+  T* sG = sQz + LB;
+  T* sB = sG + LB;
   T* stx = reinterpret_cast<T*>(smem_raw + lay.st);
   T* stz = stx + (NB * CS + 1);
   const int tid = threadIdx.x, bs = blockDim.x;
@@ -475,7 +480,7 @@ k_step(const StepArgs<T> A0) {
   // with or without the gradient pairing): mu^{m+1} from mu^{m+3} and the partial
   // sums of D_k lambda^{m+2}, without the c^2 Psi_2 factor (it sits in the u row
   // there).  2 dt / M = 4 gamma / (dt (1 + beta)).
-  T piX[NIa], piZ[NIa], pmX[NIa], pmZ[NIa], siX[NIa], siZ[NIa], Bm[4];
+  T piX[NIa], piZ[NIa], Bm[4];
   if constexpr (PML) {
     const T* pin = A.pp_in;
     const int64_t ls = A.pml_ls, rs = A.pml_rs;
@@ -484,55 +489,100 @@ k_step(const StepArgs<T> A0) {
       const int gx = own0 + j * nc + tc;
       piX[j] = pin[gx];
       piZ[j] = pin[ls + gx];
-      pmX[j] = A.pp_io[gx];
-      pmZ[j] = A.pp_io[ls + gx];
-      siX[j] = A.sig[gx];
-      siZ[j] = A.sig[N + gx];
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) Bm[k] = A.pml_b[(int64_t)k * A.n_cells + e];
-    for (int i = tid; i < nbo; i += bs) {
-      sPx[i] = pin[bo0 + i];
-      sPz[i] = pin[ls + bo0 + i];
-      sSx[i] = A.sig[bo0 + i];
-      sSz[i] = A.sig[N + bo0 + i];
-    }
-    const int64_t nref = A.pml_rs;
-    for (int j = tid; j < nsh; j += bs) {
-      const int r = sh0 + j;
-      T px = pin[N + r], pz = pin[ls + N + r];
-      const T sxr = A.sig_ref[r], szr = A.sig_ref[nref + r];
-      if (step && A.prev) {
-        const int2 sj = reinterpret_cast<const int2*>(A.ref_slots)[r];
-        T tx, tz;
-        if (sj.y >= 0) {
-          tx = A.pt_prev[sj.x] + A.pt_prev[sj.y];
-          tz = A.pt_prev[rs + sj.x] + A.pt_prev[rs + sj.y];
-        } else {
-          const int64_t sd = A.sh_idx[r] - A.n_own;
-          tx = T(0);
-          tz = T(0);
-          for (int k = A.shp_ptr[sd]; k < A.shp_ptr[sd + 1]; ++k) {
-            tx += A.pt_prev[A.shp_slot[k]];
-            tz += A.pt_prev[rs + A.shp_slot[k]];
-          }
-        }
-        const T m2 = T(4) * A.gamma_ref[r] * A.inv_dt / (T(1) + A.beta_ref[r]);
-        if (!A.pml_trans) {
-          const T cd = A.c2_ref[r] * (sxr - szr);
-          tx = cd * tx;
-          tz = -cd * tz;
-        }
-        const T bx = sxr * A.pml_dt, bz = szr * A.pml_dt;
-        px = ((T(1) - bx) * px - m2 * tx) / (T(1) + bx);
-        pz = ((T(1) - bz) * pz - m2 * tz) / (T(1) + bz);
-        A.pp_in_sh[N + r] = px;
-        A.pp_in_sh[ls + N + r] = pz;
+    // owned non-interior DOFs, two per pass with every load issued first
+    for (int i0 = tid; i0 < nbo; i0 += 2 * bs) {
+      T v[2][8];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int gx = bo0 + min(i0 + k * bs, nbo - 1);
+        v[k][0] = pin[gx];
+        v[k][1] = pin[ls + gx];
+        v[k][2] = A.sig[gx];
+        v[k][3] = A.sig[N + gx];
+        v[k][4] = A.pp_io[gx];
+        v[k][5] = A.pp_io[ls + gx];
+        v[k][6] = A.gamma[gx];
+        v[k][7] = A.beta[gx];
       }
-      sPx[nbo + j] = px;
-      sPz[nbo + j] = pz;
-      sSx[nbo + j] = sxr;
-      sSz[nbo + j] = szr;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int i = i0 + k * bs;
+        if (i >= nbo) continue;
+        sPx[i] = v[k][0];
+        sPz[i] = v[k][1];
+        sSx[i] = v[k][2];
+        sSz[i] = v[k][3];
+        sQx[i] = v[k][4];
+        sQz[i] = v[k][5];
+        sG[i] = v[k][6];
+        sB[i] = v[k][7];
+      }
+    }
+    // shared refs, two per pass: their copies, then the partial sums at their slots
+    const int64_t nref = A.pml_rs;
+    for (int j0 = tid; j0 < nsh; j0 += 2 * bs) {
+      int r2[2];
+      int2 sj[2];
+      T px[2], pz[2], sxr[2], szr[2], c2r[2], gr[2], br[2], ta[2], tb[2], tc_[2], td[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int r = sh0 + min(j0 + k * bs, nsh - 1);
+        r2[k] = r;
+        px[k] = pin[N + r];
+        pz[k] = pin[ls + N + r];
+        sxr[k] = A.sig_ref[r];
+        szr[k] = A.sig_ref[nref + r];
+        sj[k] = reinterpret_cast<const int2*>(A.ref_slots)[r];
+        c2r[k] = A.c2_ref[r];
+        gr[k] = A.gamma_ref[r];
+        br[k] = A.beta_ref[r];
+      }
+      if (step && A.prev) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int sy = sj[k].y >= 0 ? sj[k].y : sj[k].x;
+          ta[k] = A.pt_prev[sj[k].x];
+          tb[k] = A.pt_prev[sy];
+          tc_[k] = A.pt_prev[rs + sj[k].x];
+          td[k] = A.pt_prev[rs + sy];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int j = j0 + k * bs;
+        if (j >= nsh) continue;
+        const int r = r2[k];
+        if (step && A.prev) {
+          T tx = ta[k] + tb[k], tz = tc_[k] + td[k];
+          if (sj[k].y < 0) {  // three or more patches: the CSR list, in patch order
+            const int64_t sd = A.sh_idx[r] - A.n_own;
+            tx = T(0);
+            tz = T(0);
+            for (int q = A.shp_ptr[sd]; q < A.shp_ptr[sd + 1]; ++q) {
+              tx += A.pt_prev[A.shp_slot[q]];
+              tz += A.pt_prev[rs + A.shp_slot[q]];
+            }
+          }
+          const T m2 = T(4) * gr[k] * A.inv_dt / (T(1) + br[k]);
+          if (!A.pml_trans) {
+            const T cd = c2r[k] * (sxr[k] - szr[k]);
+            tx = cd * tx;
+            tz = -cd * tz;
+          }
+          const T bx = sxr[k] * A.pml_dt, bz = szr[k] * A.pml_dt;
+          px[k] = ((T(1) - bx) * px[k] - m2 * tx) / (T(1) + bx);
+          pz[k] = ((T(1) - bz) * pz[k] - m2 * tz) / (T(1) + bz);
+          A.pp_in_sh[N + r] = px[k];
+          A.pp_in_sh[ls + N + r] = pz[k];
+        }
+        sPx[nbo + j] = px[k];
+        sPz[nbo + j] = pz[k];
+        sSx[nbo + j] = sxr[k];
+        sSz[nbo + j] = szr[k];
+      }
     }
     if (tid == 0) {
       stx[NB * CS] = T(0);
@@ -616,8 +666,9 @@ k_step(const StepArgs<T> A0) {
           const int j = x < NI ? x : 0;
           pxq = piX[j];
           pzq = piZ[j];
-          sxq = siX[j];
-          szq = siZ[j];
+          const int gx = own0 + j * nc + tid;
+          sxq = A.sig[gx];
+          szq = A.sig[N + gx];
         } else {
           const int l = m[x < NB ? x : 0];
           pxq = sPx[l];
@@ -691,16 +742,18 @@ k_step(const StepArgs<T> A0) {
         A.u_out[gx] = ui[j] + dn;
         if (ADJ) A.gacc[gx] = ga[ADJ ? j : 0] + (double)re[ADJ ? a : 0];
         if constexpr (PML) {  // the auxiliary level n+1 (adjoint: m) of the interior DOF
+          const T sxj = A.sig[gx], szj = A.sig[N + gx];
+          const T pmx = A.pp_io[gx], pmz = A.pp_io[A.pml_ls + gx];
           const T m2 = T(2) * A.pml_dt / (Tab::W[a] * absJ);
           T tx = tiX[j], tz = tiZ[j];
           if (!A.pml_trans) {
-            const T cd = ce[a] * (siX[j] - siZ[j]);
+            const T cd = ce[a] * (sxj - szj);
             tx = cd * tx;
             tz = -cd * tz;
           }
-          const T bx = siX[j] * A.pml_dt, bz = siZ[j] * A.pml_dt;
-          A.pp_io[gx] = ((T(1) - bx) * pmX[j] - m2 * tx) / (T(1) + bx);
-          A.pp_io[A.pml_ls + gx] = ((T(1) - bz) * pmZ[j] - m2 * tz) / (T(1) + bz);
+          const T bx = sxj * A.pml_dt, bz = szj * A.pml_dt;
+          A.pp_io[gx] = ((T(1) - bx) * pmx - m2 * tx) / (T(1) + bx);
+          A.pp_io[A.pml_ls + gx] = ((T(1) - bz) * pmz - m2 * tz) / (T(1) + bz);
         }
       } else {
         A.y_out[gx] = ye[a];
@@ -785,15 +838,15 @@ k_step(const StepArgs<T> A0) {
       if (l < nbo) {
         const int gx = bo0 + l;
         const T sxl = sSx[l], szl = sSz[l];
-        const T m2 = T(4) * A.gamma[gx] * A.inv_dt / (T(1) + A.beta[gx]);
+        const T m2 = T(4) * sG[l] * A.inv_dt / (T(1) + sB[l]);
         if (!A.pml_trans) {
-          const T cd = A.c2[gx] * (sxl - szl);
+          const T cd = sc[l] * (sxl - szl);
           tx = cd * tx;
           tz = -cd * tz;
         }
         const T bx = sxl * A.pml_dt, bz = szl * A.pml_dt;
-        A.pp_io[gx] = ((T(1) - bx) * A.pp_io[gx] - m2 * tx) / (T(1) + bx);
-        A.pp_io[ls + gx] = ((T(1) - bz) * A.pp_io[ls + gx] - m2 * tz) / (T(1) + bz);
+        A.pp_io[gx] = ((T(1) - bx) * sQx[l] - m2 * tx) / (T(1) + bx);
+        A.pp_io[ls + gx] = ((T(1) - bz) * sQz[l] - m2 * tz) / (T(1) + bz);
       } else {
         A.pt_cur[sh0 + (l - nbo)] = tx;
         A.pt_cur[rs + sh0 + (l - nbo)] = tz;

@@ -101,7 +101,8 @@ struct StepArgs {
   int64_t ss_inj;              // inj_ptr (a [np+1] block per shot, or shared)
   // work items: patch_list[i] is the patch of item i (nullptr: item i is patch i)
   const int32_t* patch_list;
-  // PML (2D, the k_step<..., PML = true> instances; see StepPml)
+  // PML (2D, the k_step<..., PML = true> instances, launched on the patches with a
+  // DOF in the layer)
   const T* pml_b;              // [4 * n_cells] B_e = |det J_e| J_e^-T, entry (k, r) at (2k + r) * n_cells + e
   const T* sig;                // [2 * n_dofs] sigma_x then sigma_z at the DOFs
   const T* sig_ref;            // [2 * n_shared_refs] the same at each shared ref

@@ -387,15 +387,12 @@ Status step(Problem* p, Sweep& S, bool grad, bool prev, const T* u_in, const T* 
     return probed(p, grad ? 1 : 0, s, [&](hipEvent_t e0, hipEvent_t e1) {
       return launch_step<T>(m.dim, m.nd, grad, a, (int)m.n_patches, p->block, s, e0, e1);
     });
-  // PML: the patches away from the layer, then those touching it (their own kernel
-  // instance with the auxiliary fields); the two sets are disjoint and neither reads
-  // what the other writes in this step
+  // PML: the patches touching the layer in the PML instance, then the others in
+  // the plain one (the two sets are disjoint and neither reads what the other
+  // writes in this step; sweep 0 forward, 1 reverse).  A single launch of the PML
+  // instance over every patch measured slower: its LDS leaves one workgroup per CU.
   const int sw = &S == &p->adj ? 1 : 0;
-  a.patch_list = p->d_list[0];
-  if (p->n_list[0] > 0)
-    STTRY(probed(p, grad ? 1 : 0, s, [&](hipEvent_t e0, hipEvent_t e1) {
-      return launch_step<T>(m.dim, m.nd, grad, a, p->n_list[0], p->block, s, e0, e1);
-    }));
+  StepArgs<T> a0 = a;
   a.patch_list = p->d_list[1];
   a.pml_b = (const T*)p->d_pml_b;
   a.sig = (const T*)p->d_sig;
@@ -413,6 +410,11 @@ Status step(Problem* p, Sweep& S, bool grad, bool prev, const T* u_in, const T* 
   a.inv_dt = (T)(1.0 / p->dt);
   a.pml_trans = sw;  // the reverse sweep, also its launches without the pairing
   HIPTRY(launch_step<T>(m.dim, m.nd, grad, a, p->n_list[1], p->block, s, nullptr, nullptr, true));
+  a0.patch_list = p->d_list[0];
+  if (p->n_list[0] > 0)
+    STTRY(probed(p, grad ? 1 : 0, s, [&](hipEvent_t e0, hipEvent_t e1) {
+      return launch_step<T>(m.dim, m.nd, grad, a0, p->n_list[0], p->block, s, e0, e1);
+    }));
   return OK;
 }
 

@@ -105,6 +105,11 @@ def _sponge2d(x, z):
     return sponge_eta(x, z, 0.0, 8.0, 3.0, 0.75, c_max=4.5)
 
 
+def _pml2d(x, z):
+    """The same 750 m layer as a PML: per-axis damping functions whose sum is the sponge."""
+    return pml_sigma(x, z, 0.0, 8.0, 3.0, 0.75, c_max=4.5)
+
+
 @functools.lru_cache(maxsize=None)
 def layered_kmv4(seed=7, scale=0.125, degree=4, n_shots=1):
     coords, cells = _layered_mesh(seed, scale, seed + 1000)
@@ -118,7 +123,7 @@ def layered_kmv4(seed=7, scale=0.125, degree=4, n_shots=1):
         vp=layered_anomaly_vp(seed, with_anomalies=False),
         vp_obs=layered_anomaly_vp(seed), eta=_sponge2d,
         sources=src, receivers=surface_receivers(300, 0.1, 7.9, 0.1),
-        T=4.0, dt=None, extra={"seed": seed, "scale": scale})
+        T=4.0, dt=None, extra={"seed": seed, "scale": scale, "sigma": _pml2d})
 
 
 # mesh scale for ~20k, ~80k and ~300k triangles
