@@ -203,7 +203,8 @@ int kmv_set_damping(kmv_problem p, const double* eta);
  * fitting mem_budget, or gradient_every > 1's every r-th state); recomputing
  * from checkpoints is refused with KMV_ENOMEM.  Device memory: 4 n_shots (n_dofs +
  * shared refs) elements per sweep for p or mu, 4 n_shots shared refs for their
- * partial sums.  Errors: KMV_EINVAL (3D mesh, negative or non-finite sigma, LDS). */
+ * partial sums.  Errors: KMV_EINVAL (3D mesh, patches of more than 256 cells,
+ * negative or non-finite sigma, LDS). */
 int kmv_set_pml(kmv_problem p, const double* sigma);
 /* First-order absorbing boundary (the condition du/dt + c du/dn = 0 on the outer
  * boundary of the forward problem; its weak form is the boundary integral of

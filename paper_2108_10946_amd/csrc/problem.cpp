@@ -1193,6 +1193,7 @@ Status set_pml(Problem* p, const double* sigma) {
     return upload_coefficients(p);
   }
   if (m.dim != 2) return Status{KMV_EINVAL, "the PML is built for triangles (2D)"};
+  if (m.max_patch_cells > 256) return Status{KMV_EINVAL, "the PML takes patches of at most 256 cells"};
   for (int64_t i = 0; i < 2 * N; ++i)
     if (!(sigma[i] >= 0) || !std::isfinite(sigma[i]))
       return Status{KMV_EINVAL, "PML damping functions must be finite and >= 0"};

@@ -75,7 +75,7 @@ def test_central_differences(prec, h, tol):
     cm = torch.as_tensor(c0 - h * d, dtype=torch.float64, device="cuda")
     fd = (float(fwi_misfit(cp, probs, obs)) - float(fwi_misfit(cm, probs, obs))) / (2 * h)
     an = float(g @ d)
-    say(f"  J={float(J):.6e} fd={fd:.9e} an={an:.9e} rel={abs(fd - an) / abs(an):.2e}")
+    say(f"  J={float(J.detach()):.6e} fd={fd:.9e} an={an:.9e} rel={abs(fd - an) / abs(an):.2e}")
     assert abs(an) > 0
     assert abs(fd - an) <= tol * abs(an)
 
