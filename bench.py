@@ -290,7 +290,7 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - np.asarray(b, np.float64)) / np.linalg.norm(b))
 
 
-def serving_bench(n_requests=32, t_scale=1.0, slots=6, load=0.7, seed=11):
+def serving_bench(n_requests=32, t_scale=1.0, slots=6, load=0.7, seed=11, mode="full", solo=3):
     """The serving mix: Poisson arrivals of shot requests over three seeded layered
     meshes (about 20k, 80k and 300k triangles), KMV degree uniform in {2,3,4,5},
     duration uniform in [1, 4] s x t_scale, 10% forward-only, the rest misfit +
@@ -298,7 +298,12 @@ def serving_bench(n_requests=32, t_scale=1.0, slots=6, load=0.7, seed=11):
     positions per mesh, cached).  The offered load is `load` x the saturation
     throughput of the FP32 server (all requests submitted at once); the same
     arrival trace is then replayed through the FP32 server and through the plain
-    per-shot FP64 path (one solve at a time, in arrival order)."""
+    per-shot FP64 path (one solve at a time, in arrival order).
+
+    mode "burst": only the burst (for a kernel trace of the mix at full occupancy).
+    mode "solo": only the first `solo` requests on the smallest discretisation (the
+    23k-cell mesh, KMV2), one at a time on an idle server, each alone on the GPU (the
+    case where per-launch cost shows most)."""
     import torch
     from paper_2108_10946_amd import Mesh, Problem, Server
     from synth import configs
@@ -329,6 +334,8 @@ def serving_bench(n_requests=32, t_scale=1.0, slots=6, load=0.7, seed=11):
         d = disc[key]
         reqs.append(dict(key=key, pos=int(rng.integers(4)), nt=max(1, int(round(T / d["dt"]))),
                          fwd=bool(rng.random() < 0.1)))
+    if mode == "solo":
+        reqs = [q for q in reqs if q["key"] == (0, 2)][:solo]
     # observed data, FP64, per (mesh, degree, position) at the longest window used
     t = time.time()
     obs = {}
@@ -351,6 +358,18 @@ def serving_bench(n_requests=32, t_scale=1.0, slots=6, load=0.7, seed=11):
                           eta=d["eta"], observed=o, forward_only=q["fwd"], f0=5.0, t0=0.2)
 
     dof_steps = sum(disc[q["key"]]["mesh"].n_dofs * q["nt"] for q in reqs)
+    if mode == "solo":
+        srv = Server(max_slots=slots)
+        rows = []
+        for q in reqs:
+            t1 = time.perf_counter()
+            r = srv.result(submit(srv, q, "fp32"))
+            assert r["status"] == 0, r.get("error")
+            rows.append({"n_dofs": disc[q["key"]]["mesh"].n_dofs, "n_steps": q["nt"], "forward_only": q["fwd"],
+                         "seconds": round(time.perf_counter() - t1, 4)})
+            log(f"serving solo: {rows[-1]}")
+        srv.close()
+        return {"mesh_cells": disc[(0, 2)]["cells"], "degree": 2, "requests": rows}
 
     def collect(srv, tickets, what):  # results in order, with a progress line every 10
         out = []
@@ -372,6 +391,10 @@ def serving_bench(n_requests=32, t_scale=1.0, slots=6, load=0.7, seed=11):
     lam = load * sat
     arrivals = np.cumsum(rng.exponential(1.0 / lam, n_requests))
     log(f"serving: saturation {sat:.2f} shots/s over {t_sat:.1f}s; offered load {lam:.2f}/s")
+    if mode == "burst":
+        return {"requests": n_requests, "duration_scale": t_scale, "slots": slots,
+                "saturation_shots_per_s": round(sat, 3), "seconds": round(t_sat, 3),
+                "dof_timesteps_total": int(dof_steps), "dof_timesteps_per_s": round(dof_steps / t_sat, 1)}
 
     # FP32 server, Poisson arrivals
     srv = Server(max_slots=slots)
@@ -436,13 +459,61 @@ def serving_bench(n_requests=32, t_scale=1.0, slots=6, load=0.7, seed=11):
     }
 
 
-def bench_3d(args):
+def trace_busy_summary(path):
+    """GPU occupancy of a serving run from a rocprofv3 kernel trace (its
+    kernel_trace.csv): over the window in which the server's streams run (from the
+    first kernel on a stream other than the set-up stream to the last kernel end),
+    the time covered by at least one kernel, the idle rest, and per stream the
+    kernel time and the gaps between consecutive kernels of that stream."""
+    import csv
+    per = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            if row.get("Kind", "KERNEL_DISPATCH") != "KERNEL_DISPATCH":
+                continue
+            sid = row["Stream_Id"]
+            a, b = int(row["Start_Timestamp"]), int(row["End_Timestamp"])
+            per.setdefault(sid, []).append((a, b, "k_step" in row["Kernel_Name"]))
+    first = {sid: min(x[0] for x in v) for sid, v in per.items()}
+    setup = min(first, key=first.get)
+    others = [sid for sid in per if sid != setup]
+    if not others:
+        raise ValueError("no kernels outside the set-up stream")
+    lo = min(first[sid] for sid in others)
+    iv = sorted((a, b) for v in per.values() for a, b, _ in v if b > lo)
+    hi = max(b for _, b in iv)
+    busy, cur_a, cur_b = 0, None, None
+    for a, b in iv:
+        a = max(a, lo)
+        if cur_b is None or a > cur_b:
+            if cur_b is not None:
+                busy += cur_b - cur_a
+            cur_a, cur_b = a, b
+        else:
+            cur_b = max(cur_b, b)
+    busy += cur_b - cur_a
+    streams = {}
+    for sid in others:
+        v = sorted(per[sid])
+        ker = sum(b - a for a, b, _ in v)
+        gaps = [max(0, v[i + 1][0] - v[i][1]) for i in range(len(v) - 1)]
+        steps = [b - a for a, b, st in v if st]
+        streams[sid] = {"kernels": len(v), "kernel_ms": round(ker * 1e-6, 3), "gap_ms": round(sum(gaps) * 1e-6, 3),
+                        "gap_frac": round(sum(gaps) / max(1, sum(gaps) + ker), 4),
+                        "median_gap_us": round(float(np.median(gaps)) * 1e-3, 3) if gaps else None,
+                        "median_step_us": round(float(np.median(steps)) * 1e-3, 3) if steps else None}
+    span = hi - lo
+    return {"window_ms": round(span * 1e-6, 3), "busy_ms": round(busy * 1e-6, 3),
+            "idle_frac": round(1.0 - busy / span, 4), "streams": streams}
+
+
+def c5_leg(steps, warmup, every, window=0):
     """The 3D workload: layered model with anomalies on 1.33 M graded tetrahedra,
     KMV3tet (16.9 M DOFs), T = 2 s, FP32 fields, float64 misfit and gradient,
     reverse sweep from checkpoints (segments of sqrt(2 N_t) steps).  The element
-    work dominates here, so the roofline is the FP32 vector ALU."""
-    res = time_gpu("fp32", args.steps, args.warmup, args.profile_every, args.window,
-                   workload="layered_tet_kmv3", checkpoint_every=-1)
+    work dominates here, so the roofline is the FP32 vector ALU.  Returns the timing
+    result, its value and its rooflines."""
+    res = time_gpu("fp32", steps, warmup, every, window, workload="layered_tet_kmv3", checkpoint_every=-1)
     N, nt = res["n_dofs"], res["nt"]
     value = N * nt / res["sec"]
     roof = {}
@@ -458,6 +529,13 @@ def bench_3d(args):
                          "frac_of_nonpacked_peak": round(ach / FP32_NONPACKED_TFLOPS, 4),
                          "traffic": None, "algorithmic_flops": int(fl),
                          "mean_launch_us": round(p["mean_ms"] * 1e3, 3)}
+    return res, value, roof
+
+
+def bench_3d(args):
+    """The 3D workload as a bench line of its own."""
+    res, value, roof = c5_leg(args.steps, args.warmup, args.profile_every, args.window)
+    N, nt = res["n_dofs"], res["nt"]
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "DOF-timesteps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res["sec"] * 1e3, 3),
@@ -713,6 +791,7 @@ def main():
                          "ALU roofline); not the bench line")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the 40-shot leg")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D (KMV3 tetrahedra) leg")
     ap.add_argument("--c3-batch", type=int, default=8, help="shots per problem in the 40-shot leg")
     ap.add_argument("--no-pml", action="store_true", help="skip the leg with the PML in place of the sponge")
     ap.add_argument("--pml-only", action="store_true", help="run only the PML leg (for a kernel-trace profile)")
@@ -731,11 +810,20 @@ def main():
                     help="run only the 40-shot leg and print its object (profiling runs)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving mix")
     ap.add_argument("--serving-requests", type=int, default=32)
+    ap.add_argument("--serving-burst-only", action="store_true",
+                    help="run only the serving mix's burst (all requests at once), for a kernel trace")
+    ap.add_argument("--serving-solo", type=int, default=0,
+                    help="run only this many of the mix's smallest requests, one at a time, for a kernel trace")
+    ap.add_argument("--trace-summary", default="",
+                    help="print the GPU busy / idle summary of a rocprofv3 kernel_trace.csv and exit (no GPU)")
     ap.add_argument("--serving-scale", type=float, default=1.0,
                     help="request durations are U[1,4] s times this (1.0: the configuration's own mix)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(json.dumps({"trace_summary": trace_busy_summary(args.trace_summary)}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); shots would shard "
               "across GPUs with one float64 all-reduce of the gradient, which is not implemented",
@@ -756,6 +844,12 @@ def main():
         return
     if args.gradient_check_only:
         print(json.dumps({"gradient_check": gradient_check_bench(args.gradient_check_3d)}), flush=True)
+        return
+    if args.serving_burst_only or args.serving_solo > 0:
+        mode = "burst" if args.serving_burst_only else "solo"
+        print(json.dumps({f"serving_{mode}": serving_bench(n_requests=args.serving_requests,
+                                                           t_scale=args.serving_scale, mode=mode,
+                                                           solo=args.serving_solo)}), flush=True)
         return
     if args.serving_only:
         print(json.dumps({"serving": serving_bench(n_requests=args.serving_requests,
@@ -816,6 +910,17 @@ def main():
     gcheck = None
     if not args.no_gradient_check and not args.window:
         gcheck = gradient_check_bench()
+    c5 = None
+    if not args.no_3d and not args.window:
+        r3, v3, roof3 = c5_leg(1, 1, args.profile_every)
+        c5 = {"value": round(v3, 1), "unit": "DOF-timesteps/s", "sec_per_misfit_gradient": round(r3["sec"], 3),
+              "workload": "layered_tet_kmv3: 3D 4x4x2 km, 8 layers + 3 seeded anomalies, 500 m sponge on five "
+                          "faces, graded Kuhn/Maubach tetrahedra, KMV3tet, 1 Ricker shot (5 Hz), 40x40 receivers, "
+                          "T=2 s, FP32 fields, float64 misfit and gradient, checkpointed reverse sweep",
+              "n_cells": r3["n_cells"], "n_dofs": r3["n_dofs"], "n_steps": r3["nt"],
+              "checkpoint_every": r3["checkpoint_every"], "roofline": roof3.get("patch_adjoint"),
+              "rooflines": roof3}
+        log(f"3D: {v3:.3e} DOF-timesteps/s ({r3['sec']:.2f}s)")
     serving = None
     if not args.no_serving and not args.window:
         serving = serving_bench(n_requests=args.serving_requests, t_scale=args.serving_scale)
@@ -864,6 +969,8 @@ def main():
         out["pml"] = pml
     if gcheck:
         out["gradient_check"] = gcheck
+    if c5:
+        out["c5_3d"] = c5
     if sub1:
         out["gradient_subsampling"] = {
             "gradient_every": args.subsample,

@@ -95,3 +95,24 @@ def test_algorithmic_bytes():
     a1 = bench.algorithmic_bytes("patch_adjoint", N, E, 3, 8, 1)
     a3 = bench.algorithmic_bytes("patch_adjoint", N, E, 3, 8, 3)
     assert a3 - a1 == 2 * N * (5 * 8 + 16)
+
+
+def test_trace_busy_summary(tmp_path):
+    """The serving trace summary: a set-up stream, then two server streams whose
+    kernels overlap and leave two idle stretches (20 and 100 time units)."""
+    import csv
+    S = 1000000
+    rows = [("1", 0, 100, "k_dot"), ("2", 1000, 1100, "k_step<float>"), ("2", 1150, 1250, "k_step<float>"),
+            ("3", 1120, 1300, "k_step<float>"), ("2", 1400, 1500, "k_misfit")]
+    path = tmp_path / "kernel_trace.csv"
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Kind", "Stream_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        for sid, a, b, name in rows:
+            w.writerow(["KERNEL_DISPATCH", sid, name, a * S, b * S])
+    r = bench.trace_busy_summary(str(path))
+    assert r["window_ms"] == 500 and r["busy_ms"] == 380 and r["idle_frac"] == 0.24
+    s2 = r["streams"]["2"]
+    assert s2["kernels"] == 3 and s2["kernel_ms"] == 300 and s2["gap_ms"] == 200 and s2["gap_frac"] == 0.4
+    assert s2["median_step_us"] == 100000.0
+    assert "1" not in r["streams"]
