@@ -107,31 +107,32 @@ WORKLOADS = ("layered_kmv4", "layered_tet_kmv3")
 
 
 def setup_workload(precision, budget_frac=0.75, window=0, workload="layered_kmv4", checkpoint_every=0,
-                   mesh_cache={}, problem=True, gradient_every=1, absorbing=False, pml=False):
+                   mesh_cache={}, problem=True, gradient_every=1, absorbing=False, pml=False, patch_cells=0):
     import torch
     from paper_2108_10946_amd import Mesh, Problem
     from synth import configs
     w = getattr(configs, workload)()
-    if "mesh" not in mesh_cache:
+    cache = mesh_cache.setdefault((workload, patch_cells), {})  # one mesh and step per workload
+    if "mesh" not in cache:
         t = time.time()
-        mesh_cache["mesh"] = Mesh(w.coords, w.cells, w.degree)
-        log(f"mesh: {len(w.cells)} cells, {mesh_cache['mesh'].n_dofs} DOFs, "
-            f"{mesh_cache['mesh'].n_patches} patches ({time.time() - t:.1f}s)")
-    m = mesh_cache["mesh"]
+        cache["mesh"] = Mesh(w.coords, w.cells, w.degree, patch_cells=patch_cells)
+        log(f"mesh: {len(w.cells)} cells, {cache['mesh'].n_dofs} DOFs, "
+            f"{cache['mesh'].n_patches} patches ({time.time() - t:.1f}s)")
+    m = cache["mesh"]
     x = m.dof_coords()
     c_cur = torch.tensor(w.vp(*x.T), dtype=torch.float64, device="cuda")
     c_obs = torch.tensor(w.vp_obs(*x.T), dtype=torch.float64, device="cuda")
     eta = w.eta(*x.T)
     free, _ = torch.cuda.mem_get_info()
     budget = int(free * budget_frac)
-    if "dt" not in mesh_cache:
+    if "dt" not in cache:
         probe = Problem(m, 1e-4, 4, precision="fp64")
         rho = max(probe.spectral_radius(c_cur, iters=300), probe.spectral_radius(c_obs, iters=300))
         probe.close()
         nt = int(np.ceil(w.T / (w.cfl_fraction * 2.0 / np.sqrt(rho)) - 1e-12))
-        mesh_cache["dt"] = (w.T / nt, nt)
+        cache["dt"] = (w.T / nt, nt)
         log(f"CFL: rho={rho:.6g}, dt={w.T / nt * 1e3:.4f} ms, N_t={nt}")
-    dt, nt = mesh_cache["dt"]
+    dt, nt = cache["dt"]
     if window:
         nt = window
     if not problem:
@@ -152,12 +153,12 @@ def setup_workload(precision, budget_frac=0.75, window=0, workload="layered_kmv4
 
 
 def time_gpu(precision, steps, warmup, every, window=0, workload="layered_kmv4", checkpoint_every=0,
-             gradient_every=1, absorbing=False, pml=False):
+             gradient_every=1, absorbing=False, pml=False, patch_cells=0):
     import torch
     from paper_2108_10946_amd import kmvwave as K
     w, m, prob, c, obs, dt, nt = setup_workload(precision, window=window, workload=workload,
                                                 checkpoint_every=checkpoint_every, gradient_every=gradient_every,
-                                                absorbing=absorbing, pml=pml)
+                                                absorbing=absorbing, pml=pml, patch_cells=patch_cells)
     K.kmv_profile_enable(prob.handle, every)
     for i in range(warmup):
         t = time.time()
@@ -570,7 +571,7 @@ def five_gaussians(x, seed=17, n=5, radius=0.5, box=(0.0, 8.0, 0.0, 3.0)):
     return d / np.abs(d).max()
 
 
-def c3_bench(n_shots=40, batch=8, h=1e-3, every=16, subsample=10):
+def c3_bench(n_shots=40, batch=8, h=1e-3, every=16, subsample=10, checks=True):
     """The 40-shot FWI gradient of the layered KMV4 workload: shots at
     x_s = linspace(0.1, 7.9, 40), 10 m deep, T = 4 s; observed data from the model
     with anomalies (FP64), current model the layers.  J and dJ/dc are summed over
@@ -580,7 +581,8 @@ def c3_bench(n_shots=40, batch=8, h=1e-3, every=16, subsample=10):
     Checks: central differences of J at h along the seeded five-Gaussian direction
     (zero in the sponge) against the gradient; the adjoint's dot-product identity
     on one 8-shot problem; the FP32 J and gradient against the same 40 shots in
-    FP64; and the 40 shots with the paper's gradient subsampling (r = 10)."""
+    FP64; and the 40 shots with the paper's gradient subsampling (r = 10).
+    checks=False stops after the timed FP32 evaluation (for a kernel trace)."""
     import torch
     from paper_2108_10946_amd import Problem, kmvwave as K
     from paper_2108_10946_amd.autograd import fwi_misfit
@@ -606,7 +608,8 @@ def c3_bench(n_shots=40, batch=8, h=1e-3, every=16, subsample=10):
     for xs in groups:
         p = make("fp64", xs, int(free * 0.4))
         obs64.append(p.forward(c_obs))
-        J64 = p.misfit_gradient_accumulate(c_cur, obs64[-1], J64, g64)
+        if checks:
+            J64 = p.misfit_gradient_accumulate(c_cur, obs64[-1], J64, g64)
         p.close()
     torch.cuda.synchronize()
     sec64 = time.time() - t
@@ -628,6 +631,11 @@ def c3_bench(n_shots=40, batch=8, h=1e-3, every=16, subsample=10):
     info = probs[0].info()
     value = m.n_dofs * nt * n_shots / sec
     log(f"c3: 40 shots FP32 misfit + gradient in {sec:.2f}s -> {value:.4g} DOF-timesteps/s")
+    if not checks:
+        for p in probs:
+            p.close()
+        return {"shots": n_shots, "value": round(value, 1), "sec_per_misfit_gradient": round(sec, 3),
+                "kernel_mean_us": {k: round(v["mean_ms"] * 1e3, 3) for k, v in prof.items()}}
     # central differences (J only) along the five-Gaussian direction
     ct = torch.as_tensor(five_gaussians(x), dtype=torch.float64, device="cuda")
     with torch.no_grad():
@@ -792,6 +800,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the 40-shot leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D (KMV3 tetrahedra) leg")
+    ap.add_argument("--patch-cells", type=int, default=0,
+                    help="cells per patch of the layered_kmv4 mesh in the main legs (0: the library's choice)")
     ap.add_argument("--c3-batch", type=int, default=8, help="shots per problem in the 40-shot leg")
     ap.add_argument("--no-pml", action="store_true", help="skip the leg with the PML in place of the sponge")
     ap.add_argument("--pml-only", action="store_true", help="run only the PML leg (for a kernel-trace profile)")
@@ -806,6 +816,8 @@ def main():
                     help="skip the leg with the absorbing boundary term on")
     ap.add_argument("--absorbing-only", action="store_true",
                     help="run only the absorbing-boundary leg (for a kernel-trace profile)")
+    ap.add_argument("--c3-timing-only", action="store_true",
+                    help="run only the FP64 observed data and the timed FP32 40-shot evaluation (kernel traces)")
     ap.add_argument("--c3-only", action="store_true",
                     help="run only the 40-shot leg and print its object (profiling runs)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving mix")
@@ -839,8 +851,9 @@ def main():
     if args.workload == "layered_tet_kmv3":
         bench_3d(args)
         return
-    if args.c3_only:
-        print(json.dumps({"c3_40_shots": c3_bench(batch=args.c3_batch, subsample=args.subsample)}), flush=True)
+    if args.c3_only or args.c3_timing_only:
+        print(json.dumps({"c3_40_shots": c3_bench(batch=args.c3_batch, subsample=args.subsample,
+                                                  checks=not args.c3_timing_only)}), flush=True)
         return
     if args.gradient_check_only:
         print(json.dumps({"gradient_check": gradient_check_bench(args.gradient_check_3d)}), flush=True)
@@ -888,7 +901,7 @@ def main():
         print(json.dumps({"pml": pml_leg()}), flush=True)
         return
 
-    res32 = time_gpu("fp32", args.steps, args.warmup, args.profile_every, args.window)
+    res32 = time_gpu("fp32", args.steps, args.warmup, args.profile_every, args.window, patch_cells=args.patch_cells)
     rl = roofline(res32, 4)
     sub1 = None
     if not args.window and args.subsample > 1:
@@ -902,7 +915,7 @@ def main():
     res64 = None
     if not args.no_fp64:
         res64 = time_gpu("fp64", max(1, args.steps // 2), min(1, args.warmup), args.profile_every,
-                         args.window)
+                         args.window, patch_cells=args.patch_cells)
         roofline(res64, 8)
     multi = None
     if not args.no_c3 and not args.window:
@@ -956,6 +969,7 @@ def main():
             "state_storage": ("all states kept in HBM" if res32["checkpoint_every"] == 0
                               else f"checkpoints every {res32['checkpoint_every']} steps + recompute"),
             "n_patches": res32["n_patches"], "n_shared_dofs": res32["n_shared"],
+            "patch_cells": args.patch_cells or "library default",
         },
         "roofline": {k: v for k, v in rl.items() if k != "total_ms"} if rl else None,
         "rooflines": {k: {kk: vv for kk, vv in v.items() if kk != "total_ms"}

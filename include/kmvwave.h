@@ -90,7 +90,8 @@ int kmv_element_tables(int dim, int degree, int* n_nodes, double* nodes, double*
  * section "Receivers and sources"), cell patches (interior DOFs of a cell numbered
  * together, the rest per patch), geometry, lumped mass M_i = sum w_q |det J_e|.
  *   coords [n_vertices*dim] (copied), cells [n_cells*(dim+1)] 0-based (copied).
- *   patch_cells: cells per patch (0 = chosen from degree and dimension).
+ *   patch_cells: cells per patch, at most 256 (one GPU thread per cell; 0 = chosen
+ *   from degree and dimension).
  * Errors: KMV_EINVAL, KMV_EDEGREE, KMV_EMESH (index out of range, zero volume). */
 int kmv_mesh_create(int dim, int degree, const double* coords, int64_t n_vertices,
                     const int32_t* cells, int64_t n_cells, int patch_cells, kmv_mesh* out);
@@ -203,8 +204,7 @@ int kmv_set_damping(kmv_problem p, const double* eta);
  * fitting mem_budget, or gradient_every > 1's every r-th state); recomputing
  * from checkpoints is refused with KMV_ENOMEM.  Device memory: 4 n_shots (n_dofs +
  * shared refs) elements per sweep for p or mu, 4 n_shots shared refs for their
- * partial sums.  Errors: KMV_EINVAL (3D mesh, patches of more than 256 cells,
- * negative or non-finite sigma, LDS). */
+ * partial sums.  Errors: KMV_EINVAL (3D mesh, negative or non-finite sigma, LDS). */
 int kmv_set_pml(kmv_problem p, const double* sigma);
 /* First-order absorbing boundary (the condition du/dt + c du/dn = 0 on the outer
  * boundary of the forward problem; its weak form is the boundary integral of

@@ -81,7 +81,7 @@ int kmv_mesh_create(int dim, int degree, const double* coords, int64_t n_vertice
     if (!kmv::element_supported(dim, degree))
       return fail(KMV_EDEGREE, "unsupported (dim, degree): tri 1..5, tet 1..3");
     if (!coords || !cells || n_vertices <= 0 || n_cells <= 0) return fail(KMV_EINVAL, "empty mesh");
-    if (patch_cells < 0 || patch_cells > 512) return fail(KMV_EINVAL, "patch_cells must be in 0..512");
+    if (patch_cells < 0 || patch_cells > 256) return fail(KMV_EINVAL, "patch_cells must be in 0..256");
     kmv::Mesh* m = kmv::build_mesh(dim, degree, coords, n_vertices, cells, n_cells, patch_cells);
     *out = new kmv_mesh_s{m};
     return (int)KMV_OK;

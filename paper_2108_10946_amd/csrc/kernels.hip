@@ -118,12 +118,11 @@ __device__ __forceinline__ T gather_sum(uint32_t w, const T* x, const uint16_t* 
 // when many are queued (several shots); FP64 KMV4 triangles forward and FP32 KMV4
 // triangles adjoint (with its staged accumulators) 3 (at most 168 VGPRs).
 // The PML instances run on the patches of the absorbing layer only and take no
-// cap: their extra fields would spill under it.  They are also built for
-// workgroups of at most 256 threads (patches of at most 256 cells), so that one
-// wave per SIMD is a legal occupancy and the allocator may keep what does not fit
-// in the 256 architectural VGPRs in AGPRs rather than in scratch memory; their
-// launches are small (the patches that touch the layer) and their LDS footprint
-// already holds them near one workgroup per CU.
+// cap: their extra fields would spill under it.  Every instance is built for
+// workgroups of at most 256 threads (patches of at most 256 cells), so one wave
+// per SIMD is a legal occupancy: what does not fit in the 256 architectural VGPRs
+// (the PML instances, the FP64 KMV5-triangle and KMV3-tetrahedron adjoints) is kept
+// in AGPRs rather than in scratch memory.
 template <typename T, int DIM, int ND, bool ADJ, bool PML = false>
 struct StepWaves {
   static constexpr int kMin =
@@ -134,7 +133,7 @@ struct StepWaves {
 };
 
 template <typename T, int DIM, int ND, bool ADJ, bool PML = false>
-__global__ void __launch_bounds__(PML ? 256 : 512) __attribute__((amdgpu_waves_per_eu(StepWaves<T, DIM, ND, ADJ, PML>::kMin)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepWaves<T, DIM, ND, ADJ, PML>::kMin)))
 k_step(const StepArgs<T> A0) {
   static_assert(!PML || DIM == 2, "the PML instances are 2D");
   // XCD-aware work order: the dispatcher deals workgroups round-robin over the 8

@@ -1042,7 +1042,7 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
   if (n_shots < 1 || n_shots > 1024 || (int64_t)n_shots * m->n_patches > INT32_MAX)
     return Status{KMV_EINVAL, "n_shots must be in 1..1024"};
   if (grad_every < 1) return Status{KMV_EINVAL, "gradient_every must be >= 1"};
-  if (m->max_patch_cells > 512) return Status{KMV_EINVAL, "patches larger than 512 cells"};
+  if (m->max_patch_cells > 256) return Status{KMV_EINVAL, "patches larger than 256 cells"};
   auto p = new Problem();
   std::unique_ptr<Problem> guard(p);
   p->mesh = m;
@@ -1193,7 +1193,6 @@ Status set_pml(Problem* p, const double* sigma) {
     return upload_coefficients(p);
   }
   if (m.dim != 2) return Status{KMV_EINVAL, "the PML is built for triangles (2D)"};
-  if (m.max_patch_cells > 256) return Status{KMV_EINVAL, "the PML takes patches of at most 256 cells"};
   for (int64_t i = 0; i < 2 * N; ++i)
     if (!(sigma[i] >= 0) || !std::isfinite(sigma[i]))
       return Status{KMV_EINVAL, "PML damping functions must be finite and >= 0"};

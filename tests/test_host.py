@@ -72,6 +72,12 @@ def test_bad_meshes():
     with pytest.raises(K.KMVError) as ei:
         Mesh(coords, degen, 2)
     assert ei.value.code == K.KMV_EMESH
+    # one GPU thread per cell in workgroups of at most 256 threads
+    for pc in (-1, 257):
+        with pytest.raises(K.KMVError) as ei:
+            Mesh(coords, cells, 2, patch_cells=pc)
+        assert ei.value.code == K.KMV_EINVAL
+    assert Mesh(coords, cells, 2, patch_cells=256).patch_stats()["max_patch_cells"] <= 256
 
 
 MESHES = {
