@@ -508,13 +508,14 @@ def trace_busy_summary(path):
             "idle_frac": round(1.0 - busy / span, 4), "streams": streams}
 
 
-def c5_leg(steps, warmup, every, window=0):
+def c5_leg(steps, warmup, every, window=0, patch_cells=0):
     """The 3D workload: layered model with anomalies on 1.33 M graded tetrahedra,
     KMV3tet (16.9 M DOFs), T = 2 s, FP32 fields, float64 misfit and gradient,
     reverse sweep from checkpoints (segments of sqrt(2 N_t) steps).  The element
     work dominates here, so the roofline is the FP32 vector ALU.  Returns the timing
     result, its value and its rooflines."""
-    res = time_gpu("fp32", steps, warmup, every, window, workload="layered_tet_kmv3", checkpoint_every=-1)
+    res = time_gpu("fp32", steps, warmup, every, window, workload="layered_tet_kmv3", checkpoint_every=-1,
+                   patch_cells=patch_cells)
     N, nt = res["n_dofs"], res["nt"]
     value = N * nt / res["sec"]
     roof = {}
@@ -535,7 +536,7 @@ def c5_leg(steps, warmup, every, window=0):
 
 def bench_3d(args):
     """The 3D workload as a bench line of its own."""
-    res, value, roof = c5_leg(args.steps, args.warmup, args.profile_every, args.window)
+    res, value, roof = c5_leg(args.steps, args.warmup, args.profile_every, args.window, args.patch_cells)
     N, nt = res["n_dofs"], res["nt"]
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "DOF-timesteps/s", "n_gpus": 1,
@@ -709,14 +710,14 @@ def gradient_check_bench(le3d=0.0):
     """The paper's gradient verification (2D: KMV2 on 20 m triangles, 2000 steps;
     with the sponge and with the PML) in FP64 and FP32: d^co = c~^T M G along the
     masked gradient against forward differences at h = 1e-3, 1e-4, 1e-5.  le3d > 0
-    adds the 3D KMV2tet analogue with that box edge (sponge)."""
+    adds the 3D KMV2tet analogue with that box edge (sponge and PML)."""
     import torch
     from paper_2108_10946_amd import Mesh, Problem
     from paper_2108_10946_amd.fwi import directional_derivative_check
     from synth import configs
     cases = [("2d", "sponge", configs.gradient_check_2d()), ("2d", "pml", configs.gradient_check_2d())]
     if le3d > 0:
-        cases.append(("3d", "sponge", configs.gradient_check_3d(le=le3d)))
+        cases += [("3d", "sponge", configs.gradient_check_3d(le=le3d)), ("3d", "pml", configs.gradient_check_3d(le=le3d))]
     out = {}
     for dim, layer, w in cases:
         t = time.time()
@@ -801,7 +802,8 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the 40-shot leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D (KMV3 tetrahedra) leg")
     ap.add_argument("--patch-cells", type=int, default=0,
-                    help="cells per patch of the layered_kmv4 mesh in the main legs (0: the library's choice)")
+                    help="cells per patch of the main legs' mesh (layered_kmv4, or layered_tet_kmv3 with "
+                         "--workload; 0: the library's choice)")
     ap.add_argument("--c3-batch", type=int, default=8, help="shots per problem in the 40-shot leg")
     ap.add_argument("--no-pml", action="store_true", help="skip the leg with the PML in place of the sponge")
     ap.add_argument("--pml-only", action="store_true", help="run only the PML leg (for a kernel-trace profile)")

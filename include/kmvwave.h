@@ -170,7 +170,10 @@ typedef struct {
  * [n_shots][n_src/n_shots][dim], traces, observed and adjoint-source data
  * [n_shots][n_steps][n_rec], source traces [n_shots][n_steps][n_src/n_shots].
  * J and grad are sums over the shots (float64, fixed order).
- * Errors: KMV_EINVAL, KMV_ENOMEM, KMV_EDEVICE. */
+ * Errors: KMV_EINVAL (also when a patch's step kernel would need more than the
+ * 160 KiB of LDS of a CU, e.g. FP64 KMV3 tetrahedra on a mesh whose patches have
+ * unusually many non-interior DOFs: rebuild the mesh with a smaller patch_cells),
+ * KMV_ENOMEM, KMV_EDEVICE. */
 int kmv_problem_create(kmv_mesh m, const kmv_options* opt, kmv_problem* out);
 /* Shots of a problem. */
 int kmv_problem_num_shots(kmv_problem p, int* n_shots);
@@ -185,26 +188,36 @@ int kmv_spectral_radius(kmv_problem p, const void* c_dev, int iters, uint64_t se
  * KMV_EINVAL (negative or non-finite), KMV_ESTATE (the PML is on). */
 int kmv_set_damping(kmv_problem p, const double* eta);
 /* Perfectly matched layer (section "Forward wave simulation in a PML truncated
- * medium", eqs. forward2d_I / forward2d_II; the appendix matrices), triangles only.
- * sigma: [n_dofs*2] host, DOF order, (sigma_x, sigma_z) per DOF, the damping
+ * medium": the PML system, its 2D form in eqs. forward2d_I / forward2d_II; the
+ * appendix matrices).  sigma: [n_dofs*dim] host, DOF order, (sigma_x, sigma_z) per
+ * DOF on triangles, (sigma_x, sigma_y, sigma_z) on tetrahedra: the damping
  * functions of the layer (zero in the physical domain), in 1/s; NULL turns it off.
- * With it on, each step also advances the auxiliary vector p (in the same KMV
- * space) and the u row gains the PML terms:
- *   u row: damping a = dt (sigma_x + sigma_z)/2 (tr Psi_1 in place of eta; kmv_set_
- *          damping is refused while the PML is on), the zeroth-order term
- *          M sigma_x sigma_z u, and sum_k D_k^T p_k, the divergence of p integrated
- *          by parts with n.p = 0, D_k = the integral of phi_i dphi_j/dx_k;
+ * With it on, each step also advances the auxiliary vector p (and on tetrahedra
+ * omega, all in the same KMV space) and the u row gains the PML terms:
+ *   u row: damping a = dt tr(Psi_1)/2 (in place of eta; kmv_set_damping is refused
+ *          while the PML is on), the zeroth-order terms M tr(Psi_3) u + M det(Psi_1)
+ *          omega (2D: M sigma_x sigma_z u), and sum_k D_k^T p_k, the divergence of p
+ *          integrated by parts with n.p = 0, D_k = the integral of phi_i dphi_j/dx_k;
  *   p row: (1 + b_k) p_k^{n+1} = (1 - b_k) p_k^{n-1}
- *          - 2 dt M^-1 c^2 Psi_2^kk D_k u^n, b_k = sigma_k dt, Psi_2 = diag(sigma_x -
- *          sigma_z, sigma_z - sigma_x) (the damping term centred in time);
+ *          - 2 dt M^-1 c^2 (Psi_2^kk D_k u^n - Psi_3^kk D_k omega^n), b_k = sigma_k dt
+ *          (the damping term centred in time), Psi_2^kk = sigma_k - sum_{j!=k}
+ *          sigma_j, Psi_3^kk = prod_{j!=k} sigma_j (zero in 2D);
+ *   omega row (tetrahedra): omega^{n+1} = omega^n + dt (u^{n+1} + u^n)/2;
  * the adjoint is its exact transpose and dJ/dc gains
- * 2 c_i dt^2 sum_n sum_k Psi_2^kk_i mu_k,i^{n+1} (D_k u^n)_i (zero outside the layer).
- * The patches that touch the layer run a kernel instance of their own.  The
- * gradient needs the forward states kept (checkpoint_every = 0 with the states
- * fitting mem_budget, or gradient_every > 1's every r-th state); recomputing
- * from checkpoints is refused with KMV_ENOMEM.  Device memory: 4 n_shots (n_dofs +
- * shared refs) elements per sweep for p or mu, 4 n_shots shared refs for their
- * partial sums.  Errors: KMV_EINVAL (3D mesh, negative or non-finite sigma, LDS). */
+ * 2 c_i dt^2 sum_n sum_k mu_k,i^{n+1} (Psi_2^kk (D_k u^n)_i - Psi_3^kk (D_k omega^n)_i)
+ * (zero outside the layer).  Triangles: the patches that touch the layer run a kernel
+ * instance of their own; the gradient needs the forward states kept
+ * (checkpoint_every = 0 with the states fitting mem_budget, or gradient_every > 1's
+ * every r-th state), recomputing from checkpoints is refused with KMV_ENOMEM; device
+ * memory 4 n_shots (n_dofs + shared refs) elements per sweep for p or mu, 4 n_shots
+ * shared refs for their partial sums.  Tetrahedra: per-cell and per-DOF passes beside
+ * the stiffness apply; one shot per problem; the gradient keeps every forward level
+ * of u and omega ((N_t + 1) (2 n_dofs + shared refs) elements within mem_budget, else
+ * KMV_ENOMEM); device memory 12 n_cells n_nodes elements of cell-node values and
+ * 10 n_dofs of fields; not with the absorbing boundary term or kmv_forward_noalloc
+ * (KMV_ESTATE).  Errors: KMV_EINVAL (negative or non-finite sigma, LDS on triangles,
+ * several shots on tetrahedra), KMV_ESTATE (the absorbing boundary term is on, on
+ * tetrahedra). */
 int kmv_set_pml(kmv_problem p, const double* sigma);
 /* First-order absorbing boundary (the condition du/dt + c du/dn = 0 on the outer
  * boundary of the forward problem; its weak form is the boundary integral of

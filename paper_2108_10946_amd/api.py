@@ -108,11 +108,11 @@ class Problem:
         K.kmv_set_damping(self.handle, eta)
 
     def set_pml(self, sigma):
-        """Perfectly matched layer with damping functions sigma [n_dofs, 2] (DOF order),
-        or None to turn it off (kmv_set_pml)."""
+        """Perfectly matched layer with damping functions sigma [n_dofs, dim] (DOF
+        order; one column per axis), or None to turn it off (kmv_set_pml)."""
         if sigma is not None and len(sigma) != self.mesh.n_dofs:
             raise ValueError("sigma must hold the mesh's n_dofs rows")
-        K.kmv_set_pml(self.handle, sigma)
+        K.kmv_set_pml(self.handle, sigma, self.mesh.dim)
 
     def set_absorbing_boundary(self, enable=True):
         """First-order absorbing boundary on every boundary facet (du/dt + c du/dn = 0),

@@ -19,7 +19,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libkmvwave.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["element.cpp", "mesh.cpp", "problem.cpp", "server.cpp", "capi.cpp", "kernels.hip", "boundary.hip"]
+SOURCES = ["element.cpp", "mesh.cpp", "problem.cpp", "server.cpp", "capi.cpp", "kernels.hip", "boundary.hip",
+           "pml3d.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("KMV_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

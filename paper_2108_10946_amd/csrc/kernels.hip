@@ -80,7 +80,7 @@ template <typename T, bool ADJ, int DIM, int ND>
 constexpr bool kStageGrad = stage_grad(ADJ, DIM, ND, sizeof(T));
 
 // Shared refs per thread finished in the first batch of k_step (3D patches have
-// several times more than 2D ones: a 128-cell KMV3 tetrahedron patch about six per
+// several times more than 2D ones: a 256-cell KMV3 tetrahedron patch about five per
 // thread); the rest go through the loop over the remaining refs, two per pass.
 constexpr int first_batch_shared(int dim, int nd, bool adj) { return dim == 3 && !adj ? (nd == 32 ? 6 : 4) : 2; }
 

@@ -21,6 +21,7 @@
 #include "../../include/kmvwave.h"
 #include "boundary.hpp"
 #include "kernels.hpp"
+#include "pml3d.hpp"
 
 namespace kmv {
 
@@ -248,6 +249,9 @@ Status build_points(Problem* p, const double* xyz, int npts, int nshot, PointTab
   STTRY(upload_real(&T.pp_w, pw, p->prec));
   STTRY(upload_i(&T.s_dof, sdof));
   STTRY(upload_real(&T.s_w, sw, p->prec));
+  T.h_dof = sdof;
+  T.h_w = sw;
+  p->p3_points_dirty = true;
   return OK;
 }
 
@@ -607,6 +611,12 @@ Status set_c2(Problem* p, const double* c, hipStream_t s) {
   return OK;
 }
 
+// PML on tetrahedra: defined after the stiffness apply they use.
+template <typename T>
+Status pml3_forward(Problem* p, const double* c, T* traces, bool keep, hipStream_t s);
+template <typename T>
+Status pml3_reverse(Problem* p, const T* adj_rows, bool grad, T* lambda_out, T* src_trace, hipStream_t s);
+
 // The forward sweep with its two level buffers at base (level n in buffer n & 1).
 template <typename T>
 Status forward_run(Problem* p, const double* c, T* traces, T* base, hipStream_t s) {
@@ -621,6 +631,7 @@ Status forward_run(Problem* p, const double* c, T* traces, T* base, hipStream_t 
 
 template <typename T>
 Status forward_t(Problem* p, const double* c, T* traces, hipStream_t s) {
+  if (p->pml3) return pml3_forward<T>(p, c, traces, false, s);
   STTRY(ensure_slots(p, 2));
   return forward_run<T>(p, c, traces, slot_ptr<T>(p, 0), s);
 }
@@ -724,6 +735,27 @@ Status misfit_gradient_t(Problem* p, const double* c, const T* obs, double* J, d
                          hipStream_t s, bool accumulate) {
   const Mesh& m = *p->mesh;
   const int64_t N = m.n_dofs;
+  if (p->pml3) {  // tetrahedra: every level of u and omega kept, then the reverse sweep
+    const size_t need = (size_t)(p->nt + 1) * ((size_t)p->ls + (size_t)N) * p->ts;
+    if (need > p->budget)
+      return Status{KMV_ENOMEM, "with the PML on tetrahedra every forward level of u and omega is kept: " +
+                                    std::to_string(need) + " B exceed mem_budget"};
+    T* traces = traces_out ? traces_out : (T*)p->d_traces_tmp;
+    STTRY(pml3_forward<T>(p, c, traces, true, s));
+    HIPTRY(launch_misfit<T>(traces, obs, (T*)p->d_resid, p->nt * p->rec.npts, p->d_red, p->red_blocks,
+                            p->d_red + p->red_blocks, s));
+    STTRY(pml3_reverse<T>(p, (const T*)p->d_resid, true, nullptr, nullptr, s));
+    HIPTRY(launch_finalize_grad(c, p->d_gacc, 1, 2.0 * p->dt * p->dt * (double)p->grad_every, grad, N, s,
+                                accumulate));
+    double hJ = 0;
+    int flag = 0;
+    HIPTRY(hipMemcpyAsync(&hJ, p->d_red + p->red_blocks, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPTRY(hipMemcpyAsync(&flag, p->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPTRY(hipStreamSynchronize(s));
+    *J = accumulate ? *J + hJ : hJ;
+    if (flag || !std::isfinite(hJ)) return classify_nonfinite<T>(p, s);
+    return OK;
+  }
   STTRY(plan_storage(p));
   if (p->pml() && !p->store_all && !p->store_sub)
     return Status{KMV_ENOMEM, "with the PML the forward states must be kept (all of them, or every r-th with "
@@ -852,6 +884,7 @@ Status adjoint_t(Problem* p, const double* c, const T* adj, T* lambda_out, T* sr
   const size_t vb = (size_t)N * sizeof(T);
   STTRY(clear_flag(p, s));
   STTRY(set_c2<T>(p, c, s));
+  if (p->pml3) return pml3_reverse<T>(p, adj, false, lambda_out, src_trace, s);
   STTRY(adjoint_start<T>(p, s));
   if (lambda_out) HIPTRY(launch_fill<T>(lambda_out + p->nt * N, T(0), N, s));
   // shot sh samples its own sources: points [sh*nps, (sh+1)*nps) of the table
@@ -910,6 +943,177 @@ Status apply_t(Problem* p, const double* c, const T* u, T* y, hipStream_t s) {
   f.y_out = y;
   return probed(p, 2, s,
                 [&](hipEvent_t e0, hipEvent_t e1) { return launch_finish<T>(false, f, s, e0, e1); });
+}
+
+// ---- PML on tetrahedra (section on the PML: p_x, p_y, p_z and omega; the
+// transposed scheme of the adjoint; the gradient's PML terms).  The layer's terms
+// run beside the stiffness apply (pml3d.hip): per step the apply K u, the per-cell
+// pass, the per-DOF update rows and the receivers' samples.  Every level is complete
+// at the end of its step (no lagged finishing).
+
+// The source's nodal load vector and the transposed receiver rows (DOF -> receiver,
+// weight), rebuilt after the sources or receivers change.
+Status pml3_points(Problem* p) {
+  if (!p->p3_points_dirty) return OK;
+  const Mesh& m = *p->mesh;
+  const int64_t N = m.n_dofs;
+  const int nd = m.nd;
+  std::vector<double> sv(N, 0.0);
+  for (size_t k = 0; k < p->src.h_dof.size(); ++k) sv[p->src.h_dof[k]] += p->src.h_w[k];
+  const int nr = p->rec.npts;
+  std::vector<int32_t> ptr(N + 1, 0), idx((size_t)nr * nd);
+  std::vector<double> w((size_t)nr * nd);
+  for (int j = 0; j < nr; ++j)
+    for (int a = 0; a < nd; ++a) ptr[p->rec.h_dof[(size_t)j * nd + a] + 1]++;
+  for (int64_t i = 0; i < N; ++i) ptr[i + 1] += ptr[i];
+  std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+  for (int j = 0; j < nr; ++j)  // per DOF, receivers in ascending order
+    for (int a = 0; a < nd; ++a) {
+      const int32_t i = p->rec.h_dof[(size_t)j * nd + a];
+      idx[fill[i]] = j;
+      w[fill[i]++] = p->rec.h_w[(size_t)j * nd + a];
+    }
+  STTRY(upload_real(&p->d_svec, sv, p->prec));
+  STTRY(upload_i(&p->d_rptr, ptr));
+  STTRY(upload_i(&p->d_ridx, idx.empty() ? std::vector<int32_t>{0} : idx));
+  STTRY(upload_real(&p->d_rw, w.empty() ? std::vector<double>{0.0} : w, p->prec));
+  p->p3_points_dirty = false;
+  return OK;
+}
+
+template <typename T>
+Pml3CellArgs<T> pml3_cell_args(Problem* p) {
+  const Mesh& m = *p->mesh;
+  Pml3CellArgs<T> a;
+  a.n_cells = m.n_cells;
+  a.n_dofs = m.n_dofs;
+  a.cdof = p->d_cdof;
+  a.b3 = (const T*)p->d_b3;
+  a.geom = (const T*)p->d_geom;
+  a.c2 = (const T*)p->d_c2;
+  a.sig = (const T*)p->d_sig;
+  a.out = (T*)p->d_cellout;
+  return a;
+}
+
+template <typename T>
+Pml3UpdateArgs<T> pml3_update_args(Problem* p) {
+  const Mesh& m = *p->mesh;
+  Pml3UpdateArgs<T> a;
+  a.n_dofs = m.n_dofs;
+  a.n_slots = m.n_cells * m.nd;
+  a.csr_ptr = p->d_csr_ptr;
+  a.csr_slot = p->d_csr_slot;
+  a.cell_out = (const T*)p->d_cellout;
+  a.sig = (const T*)p->d_sig;
+  a.mass = (const T*)p->d_mass;
+  a.c2 = (const T*)p->d_c2;
+  a.dt = (T)p->dt;
+  a.ku = (const T*)p->d_ku;
+  return a;
+}
+
+// Forward levels n = 0..N_t from zero (u^{-1} = u^0 = 0, p and omega zero): keep =
+// every level of u (slot n) and omega stays, else two of each.  traces: row n-1 =
+// P u^n.
+template <typename T>
+Status pml3_forward(Problem* p, const double* c, T* traces, bool keep, hipStream_t s) {
+  const Mesh& m = *p->mesh;
+  const int64_t N = m.n_dofs;
+  STTRY(pml3_points(p));
+  const int64_t nl = keep ? p->nt + 1 : 2;
+  STTRY(ensure_slots(p, nl));
+  if (p->n_y3 < nl) {
+    STTRY(alloc(&p->d_y3, (size_t)nl * N * p->ts));
+    p->n_y3 = nl;
+  }
+  auto U = [&](int64_t n) { return slot_ptr<T>(p, keep ? n : (n & 1)); };
+  auto Y = [&](int64_t n) { return (T*)p->d_y3 + (keep ? n : (n & 1)) * N; };
+  STTRY(clear_flag(p, s));
+  STTRY(set_c2<T>(p, c, s));
+  HIPTRY(launch_fill<T>(U(0), T(0), N, s));
+  HIPTRY(launch_fill<T>(Y(0), T(0), N, s));
+  for (int k = 0; k < 2; ++k) HIPTRY(launch_fill<T>((T*)p->d_p3[k], T(0), 3 * N, s));
+  Pml3CellArgs<T> ca = pml3_cell_args<T>(p);
+  Pml3UpdateArgs<T> ua = pml3_update_args<T>(p);
+  ua.svec = (const T*)p->d_svec;
+  for (int64_t n = 0; n < p->nt; ++n) {
+    STTRY(apply_t<T>(p, nullptr, U(n), (T*)p->d_ku, s));
+    ca.u = U(n);
+    ca.y = Y(n);
+    ca.p = (const T*)p->d_p3[n & 1];  // p^n; p^{n-1} in the other buffer
+    HIPTRY(launch_pml3_cell<T>(m.nd, false, ca, s));
+    ua.u = U(n);
+    ua.u_prev = n > 0 ? U(n - 1) : nullptr;
+    ua.y = Y(n);
+    ua.u_out = U(n + 1);
+    ua.y_out = Y(n + 1);
+    ua.p_io = (T*)p->d_p3[(n + 1) & 1];  // p^{n-1} in, p^{n+1} out
+    ua.amp = (const T*)p->d_wavelet + n;
+    HIPTRY(launch_pml3_update<T>(false, ua, s));
+    if (traces)
+      STTRY(probed(p, 4, s, [&](hipEvent_t e0, hipEvent_t e1) {
+        return launch_sample<T>(U(n + 1), p->rec.s_dof, (const T*)p->rec.s_w, p->rec.npts, m.nd,
+                                traces + n * p->rec.npts, s, e0, e1);
+      }));
+    if ((n + 1) % kCheckEvery == 0 || n + 1 == p->nt) STTRY(check_level<T>(p, U(n + 1), s));
+  }
+  return OK;
+}
+
+// Reverse levels m = N_t..1 from lambda^{N_t+1} = lambda^{N_t+2} = 0 (mu, nu zero)
+// with adjoint data adj_rows (row m-1 = y^m per receiver).  grad: the float64
+// accumulator gains the pairing of lambda^{m+1} with u^m and the PML terms at the
+// steps m % r == 0 (u^m, omega^m from the kept forward levels).  lambda_out (row
+// m-1 = lambda^m, row N_t = 0) and src_trace (row m-1 = lambda^m at the sources)
+// are optional.
+template <typename T>
+Status pml3_reverse(Problem* p, const T* adj_rows, bool grad, T* lambda_out, T* src_trace, hipStream_t s) {
+  const Mesh& m = *p->mesh;
+  const int64_t N = m.n_dofs;
+  const size_t vb = (size_t)N * sizeof(T);
+  STTRY(pml3_points(p));
+  auto L = [&](int64_t lvl) { return (T*)p->d_lam[lvl & 1]; };
+  for (int k = 0; k < 2; ++k) {
+    HIPTRY(launch_fill<T>((T*)p->d_lam[k], T(0), N, s));
+    HIPTRY(launch_fill<T>((T*)p->d_p3[k], T(0), 3 * N, s));
+    HIPTRY(launch_fill<T>((T*)p->d_nu3[k], T(0), N, s));
+  }
+  if (grad) HIPTRY(launch_fill_f64(p->d_gacc, 0.0, N, s));
+  if (lambda_out) HIPTRY(launch_fill<T>(lambda_out + p->nt * N, T(0), N, s));
+  Pml3CellArgs<T> ca = pml3_cell_args<T>(p);
+  Pml3UpdateArgs<T> ua = pml3_update_args<T>(p);
+  ua.rec_ptr = p->d_rptr;
+  ua.rec_idx = p->d_ridx;
+  ua.rec_w = (const T*)p->d_rw;
+  const int64_t r = p->grad_every;
+  for (int64_t mm = p->nt; mm >= 1; --mm) {
+    const bool pair = grad && mm % r == 0;
+    STTRY(apply_t<T>(p, nullptr, L(mm + 1), (T*)p->d_ku, s));
+    ca.u = L(mm + 1);
+    ca.p = (const T*)p->d_p3[(mm + 1) & 1];  // mu^{m+1}
+    ca.uf = pair ? slot_ptr<T>(p, mm) : nullptr;
+    ca.yf = pair ? (const T*)p->d_y3 + mm * N : nullptr;
+    HIPTRY(launch_pml3_cell<T>(m.nd, true, ca, s));
+    ua.u = L(mm + 1);
+    ua.u_prev = L(mm);  // lambda^{m+2} in, lambda^m out: the same buffer
+    ua.u_out = L(mm);
+    ua.y = (const T*)p->d_nu3[(mm + 1) & 1];
+    ua.y_out = (T*)p->d_nu3[mm & 1];
+    ua.p_in = (const T*)p->d_p3[(mm + 1) & 1];
+    ua.p_io = (T*)p->d_p3[mm & 1];  // mu^{m+2} in, mu^m out
+    ua.resid_row = adj_rows + (mm - 1) * p->rec.npts;
+    ua.gacc = pair ? p->d_gacc : nullptr;
+    HIPTRY(launch_pml3_update<T>(true, ua, s));
+    if (lambda_out) HIPTRY(hipMemcpyAsync(lambda_out + (mm - 1) * N, L(mm), vb, hipMemcpyDeviceToDevice, s));
+    if (src_trace)
+      STTRY(probed(p, 4, s, [&](hipEvent_t e0, hipEvent_t e1) {
+        return launch_sample<T>(L(mm), p->src.s_dof, (const T*)p->src.s_w, p->src.npts, m.nd,
+                                src_trace + (mm - 1) * p->src.npts, s, e0, e1);
+      }));
+    if (mm % kCheckEvery == 0 || mm == 1) STTRY(check_level<T>(p, L(mm), s));
+  }
+  return OK;
 }
 
 // SplitMix64 (Steele, Lea and Flood, 2014): one step of the generator's output map.
@@ -997,7 +1201,9 @@ Problem::~Problem() {
                   d_ck_u, d_ck_du, d_resid, d_traces_tmp, d_wavelet, (void*)d_bnd_dof, (void*)d_bnd_ref,
                   (void*)d_bnd_coef, (void*)d_bnd_hb, d_ub, d_lb, (void*)d_bnd_part, d_sig, d_sig_ref, d_pml_b,
                   (void*)d_list[0], (void*)d_list[1], d_pp[0][0], d_pp[0][1], d_pp[1][0], d_pp[1][1], d_pt[0][0],
-                  d_pt[0][1], d_pt[1][0], d_pt[1][1]})
+                  d_pt[0][1], d_pt[1][0], d_pt[1][1], (void*)d_cdof, d_b3, (void*)d_csr_ptr, (void*)d_csr_slot,
+                  d_mass, d_cellout, d_ku, d_p3[0], d_p3[1], d_nu3[0], d_nu3[1], d_y3, d_svec, (void*)d_rptr,
+                  (void*)d_ridx, d_rw})
     dfree(q);
   free_sweep(fwd);
   free_sweep(adj);
@@ -1139,6 +1345,7 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
 
 Status set_absorbing_boundary(Problem* p, bool on) {
   DeviceGuard dg(p->device);
+  if (on && p->pml3) return Status{KMV_ESTATE, "the absorbing boundary term does not combine with the PML on tetrahedra"};
   if (on && p->bnd_dof.empty()) {
     const std::vector<int32_t>* d;
     const std::vector<double>* b;
@@ -1173,6 +1380,53 @@ Status set_damping(Problem* p, const double* eta) {
   return upload_coefficients(p);
 }
 
+// PML on tetrahedra: sigma [n_dofs*3] (sigma_x, sigma_y, sigma_z per DOF).  One
+// shot per problem; not with the absorbing boundary term.
+Status set_pml3(Problem* p, const double* sigma) {
+  const Mesh& m = *p->mesh;
+  const int64_t N = m.n_dofs, ne = m.n_cells;
+  const int nd = m.nd;
+  if (p->nshot != 1) return Status{KMV_EINVAL, "the PML on tetrahedra takes one shot per problem"};
+  if (p->absorb) return Status{KMV_ESTATE, "turn the absorbing boundary term off before the PML on tetrahedra"};
+  for (int64_t i = 0; i < 3 * N; ++i)
+    if (!(sigma[i] >= 0) || !std::isfinite(sigma[i]))
+      return Status{KMV_EINVAL, "PML damping functions must be finite and >= 0"};
+  if (ne * nd > INT32_MAX) return Status{KMV_EINVAL, "mesh too large for the PML's cell-node slots"};
+  std::vector<double> sc(3 * N);
+  for (int64_t i = 0; i < N; ++i)
+    for (int k = 0; k < 3; ++k) sc[k * N + i] = sigma[3 * i + k];
+  std::vector<int32_t> cdof((size_t)ne * nd), ptr(N + 1, 0), slot((size_t)ne * nd);
+  for (size_t k = 0; k < cdof.size(); ++k) {
+    cdof[k] = (int32_t)m.cell_dofs[k];
+    ptr[cdof[k] + 1]++;
+  }
+  for (int64_t i = 0; i < N; ++i) ptr[i + 1] += ptr[i];
+  {
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    for (size_t k = 0; k < cdof.size(); ++k) slot[fill[cdof[k]]++] = (int32_t)k;  // ascending (cell, node)
+  }
+  std::vector<double> b(9 * (size_t)ne);  // B_e = |det J| J^-T, entry (k, r) at 3k + r
+  for (int64_t e = 0; e < ne; ++e)
+    for (int k = 0; k < 3; ++k)
+      for (int r = 0; r < 3; ++r) b[(size_t)(3 * k + r) * ne + e] = m.absdet[e] * m.jinv[e * 9 + r * 3 + k];
+  STTRY(upload_real(&p->d_sig, sc, p->prec));
+  STTRY(upload_i(&p->d_cdof, cdof));
+  STTRY(upload_i(&p->d_csr_ptr, ptr));
+  STTRY(upload_i(&p->d_csr_slot, slot));
+  STTRY(upload_real(&p->d_b3, b, p->prec));
+  STTRY(upload_real(&p->d_mass, m.mass, p->prec));
+  STTRY(alloc(&p->d_cellout, (size_t)12 * ne * nd * p->ts));
+  STTRY(alloc(&p->d_ku, (size_t)N * p->ts));
+  for (int k = 0; k < 2; ++k) {
+    STTRY(alloc(&p->d_p3[k], (size_t)3 * N * p->ts));
+    STTRY(alloc(&p->d_nu3[k], (size_t)N * p->ts));
+  }
+  p->sigma = sc;
+  p->pml3 = true;
+  p->p3_points_dirty = true;
+  return OK;
+}
+
 Status set_pml(Problem* p, const double* sigma) {
   DeviceGuard dg(p->device);
   const Mesh& m = *p->mesh;
@@ -1190,9 +1444,16 @@ Status set_pml(Problem* p, const double* sigma) {
     p->d_sig = p->d_sig_ref = p->d_pml_b = nullptr;
     p->d_list[0] = p->d_list[1] = nullptr;
     p->n_list[0] = p->n_list[1] = 0;
+    for (void** q : {(void**)&p->d_cdof, &p->d_b3, (void**)&p->d_csr_ptr, (void**)&p->d_csr_slot, &p->d_mass,
+                     &p->d_cellout, &p->d_ku, &p->d_p3[0], &p->d_p3[1], &p->d_nu3[0], &p->d_nu3[1], &p->d_y3}) {
+      dfree(*q);
+      *q = nullptr;
+    }
+    p->n_y3 = 0;
+    p->pml3 = false;
     return upload_coefficients(p);
   }
-  if (m.dim != 2) return Status{KMV_EINVAL, "the PML is built for triangles (2D)"};
+  if (m.dim == 3) return set_pml3(p, sigma);
   for (int64_t i = 0; i < 2 * N; ++i)
     if (!(sigma[i] >= 0) || !std::isfinite(sigma[i]))
       return Status{KMV_EINVAL, "PML damping functions must be finite and >= 0"};
@@ -1295,6 +1556,7 @@ Status set_receivers(Problem* p, const double* xr, int nrec) {
 
 Status forward_noalloc(Problem* p, const double* c, void* traces, hipStream_t s) {
   DeviceGuard dg(p->device);
+  if (p->pml3) return Status{KMV_ESTATE, "the allocation-free forward does not take the PML on tetrahedra"};
   if (!p->has_src || p->rec.npts == 0) return Status{KMV_ESTATE, "sources and receivers must be set first"};
   if (!c || !traces) return Status{KMV_EINVAL, "null device pointer"};
   const size_t need = 2 * (size_t)p->ls * p->nshot * p->ts;

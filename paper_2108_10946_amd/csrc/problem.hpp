@@ -37,6 +37,8 @@ struct PointTables {
   void* pp_w = nullptr;         // [n*nd]
   int32_t* s_dof = nullptr;     // [npts*nd] global DOFs
   void* s_w = nullptr;          // [npts*nd]
+  std::vector<int32_t> h_dof;   // host copies of s_dof, s_w
+  std::vector<double> h_w;
 };
 
 // Event-based timing of sampled kernel launches (see kmv_profile_enable).
@@ -124,6 +126,24 @@ struct Problem {
   void* d_pp[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [sweep][level parity]: [n_shots][2][ls]
   void* d_pt[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [sweep][step parity]: [n_shots][2][rs]
   bool pml() const { return !sigma.empty(); }
+  // PML on tetrahedra (pml3d.hip): sigma holds sigma_x, sigma_y, sigma_z; per-cell
+  // contractions and per-DOF update rows beside the stiffness apply, one shot, the
+  // forward states (u and omega) kept for the reverse sweep
+  bool pml3 = false;
+  int32_t* d_cdof = nullptr;                    // [n_cells*nd] DOF of each cell node
+  void* d_b3 = nullptr;                         // [9*n_cells] |det J| J^-T
+  int32_t *d_csr_ptr = nullptr, *d_csr_slot = nullptr;  // DOF -> its cell-node slots
+  void* d_mass = nullptr;                       // [n_dofs] lumped mass
+  void* d_cellout = nullptr;                    // [12*n_cells*nd] cell-node values
+  void* d_ku = nullptr;                         // [n_dofs] K u
+  void* d_p3[2] = {nullptr, nullptr};           // [3*n_dofs] p (forward) or mu (reverse), by parity
+  void* d_nu3[2] = {nullptr, nullptr};          // [n_dofs] nu by parity
+  void* d_y3 = nullptr;                         // omega levels [n_y3][n_dofs]
+  int64_t n_y3 = 0;
+  void* d_svec = nullptr;                       // [n_dofs] the source's load vector
+  int32_t *d_rptr = nullptr, *d_ridx = nullptr;  // DOF -> receiver rows (transposed sampling)
+  void* d_rw = nullptr;
+  bool p3_points_dirty = true;
   // sweeps
   Sweep fwd, adj;
   void* d_lam[2] = {nullptr, nullptr};

@@ -281,14 +281,15 @@ def kmv_set_damping(p, eta):
         _check(lib().kmv_set_damping(p, _dptr(eta)))
 
 
-def kmv_set_pml(p, sigma):
-    """sigma: [n_dofs, 2] (sigma_x, sigma_z per DOF), or None (off)."""
+def kmv_set_pml(p, sigma, dim=2):
+    """sigma: [n_dofs, dim] (sigma_x, sigma_z per DOF on triangles; sigma_x, sigma_y,
+    sigma_z on tetrahedra), or None (off)."""
     if sigma is None:
         _check(lib().kmv_set_pml(p, None))
     else:
         sigma = np.ascontiguousarray(sigma, dtype=np.float64)
-        if sigma.ndim != 2 or sigma.shape[1] != 2:
-            raise ValueError("sigma must be [n_dofs, 2]")
+        if sigma.ndim != 2 or sigma.shape[1] != dim:
+            raise ValueError(f"sigma must be [n_dofs, {dim}]")
         _check(lib().kmv_set_pml(p, _dptr(sigma)))
 
 

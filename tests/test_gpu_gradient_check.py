@@ -5,7 +5,7 @@ and lower half 1.0 km/s, initial model 4.0 km/s, a 200 m absorbing layer, KMV2 o
 analogue on KMV2 tetrahedra at a reduced size (140 m boxes).
 
 * The full 2D workload against the oracle: J, traces and the gradient at 1e-10
-  (FP64), with the sponge and with the PML; the 3D one likewise with the sponge.
+  (FP64), with the sponge and with the PML; the 3D one likewise.
 * The directional derivative d^co = c~^T M G along c~ = G masked in the layer
   (eq. control_deriv) against forward differences of J (eq. discrete_fd) at
   h = 1e-3, 1e-4, 1e-5.  The discrete gradient is the exact derivative of the
@@ -74,7 +74,7 @@ def gpu_problem(w, layer, prec):
     return m, prob
 
 
-CASES = [("2d", "sponge"), ("2d", "pml"), ("3d", "sponge")]
+CASES = [("2d", "sponge"), ("2d", "pml"), ("3d", "sponge"), ("3d", "pml")]
 
 
 def workload(dim):

@@ -185,12 +185,7 @@ def test_pml_limits_and_switching(cache):
     plain.set_receivers(cs["rec"])
     assert torch.equal(a, plain.forward(c))
     plain.close()
+    # one column per axis (tetrahedra: tests/test_gpu_pml3d.py)
+    with pytest.raises(ValueError):
+        prob.set_pml(np.zeros((m.n_dofs, 3)))
     prob.close()
-    # tetrahedra: refused
-    coords, cells = configs.small_tet(2, seed=1)
-    mt = Mesh(coords, cells, 1)
-    pt = Problem(mt, 1e-3, 4, precision="fp64")
-    with pytest.raises(K.KMVError) as e:
-        pt.set_pml(np.zeros((mt.n_dofs, 2)))
-    assert e.value.code == K.KMV_EINVAL
-    pt.close()

@@ -18,9 +18,9 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 # (Kuhn-cube subdivisions, cells per patch): 64-cell patches on 750 tetrahedra (up to
-# 498 refs against a first batch of 384), and the default 128-cell patches on 2058
-# (up to 833 refs against 768)
-MESHES = [(5, 64), (7, 0)]
+# 498 refs against a first batch of 384), and 128-cell patches on 2058 (up to 833
+# refs against 768)
+MESHES = [(5, 64), (7, 128)]
 
 
 @pytest.fixture(scope="module", autouse=True)
