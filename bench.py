@@ -751,6 +751,44 @@ def gradient_check_bench(le3d=0.0):
     return out
 
 
+def pml3d_leg(le=0.05):
+    """The PML on tetrahedra against the sponge on the 3D gradient-verification box
+    (KMV2 tetrahedra of edge le, T = 1 s at dt = 0.5 ms, layer on five faces), FP32:
+    seconds per misfit + gradient with each layer (one warm-up, then one timed)."""
+    import torch
+    from paper_2108_10946_amd import Mesh, Problem
+    from synth import configs
+    w = configs.gradient_check_3d(le=le)
+    m = Mesh(w.coords, w.cells, w.degree)
+    x = m.dof_coords()
+    nt = int(round(w.T / w.dt))
+    c = torch.as_tensor(w.vp(*x.T), dtype=torch.float64, device="cuda")
+    c_obs = torch.as_tensor(w.vp_obs(*x.T), dtype=torch.float64, device="cuda")
+    out = {"workload": f"gradient_check_3d(le={le}): {len(w.cells)} KMV2 tetrahedra, {m.n_dofs} DOFs, "
+                       f"{nt} steps, FP32", "n_dofs": m.n_dofs, "n_steps": nt}
+    for layer in ("sponge", "pml"):
+        p = Problem(m, w.dt, nt, precision="fp32", mem_budget=64 << 30)
+        if layer == "pml":
+            p.set_pml(w.extra["sigma"](*x.T))
+        else:
+            p.set_damping(w.eta(*x.T))
+        p.set_sources(w.sources, f0=w.f0, t0=w.t0)
+        p.set_receivers(w.receivers)
+        obs = p.forward(c_obs)
+        p.misfit_gradient(c, obs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.misfit_gradient(c, obs)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        p.close()
+        out[layer] = {"sec_per_misfit_gradient": round(sec, 4), "value": round(m.n_dofs * nt / sec, 1)}
+        log(f"3D {layer}: {sec * 1e3:.1f} ms per misfit + gradient")
+    out["overhead_vs_sponge"] = round(out["pml"]["sec_per_misfit_gradient"] / out["sponge"]["sec_per_misfit_gradient"] - 1.0, 4)
+    m.close()
+    return out
+
+
 def copy_bandwidth(n_bytes=2 << 30, reps=10):
     """Achievable HBM bandwidth: a plain device-to-device copy of n_bytes (read +
     write = 2 n_bytes per copy, far above the 256 MB Infinity Cache), timed with
@@ -897,6 +935,7 @@ def main():
                        "layer; kernel_mean_us times the launch over the patches away from the layer"}
         if ref_sec:
             out["overhead_vs_sponge"] = round(a["sec"] / ref_sec - 1.0, 4)
+        out["tetrahedra"] = pml3d_leg()
         return out
 
     if args.pml_only:

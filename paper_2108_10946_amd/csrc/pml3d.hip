@@ -9,9 +9,9 @@
 //   (D_k v)_i      <- w_q (B g_v)_k        at node q of the cell, i = its DOF,
 //   (D_k^T v_k)_j  <- sum_q sum_r D[q][j][r] (w_q B^T v_q)_r,
 // with g_v the reference gradient of v at the node (sum_b D[q][b][.] v_b) and
-// B = |det J| J^-T.  One thread per cell writes its cell-node values; one thread per
-// DOF then sums its cell-node slots in a fixed (cell, node) order (no atomics) and
-// applies the update rows of the scheme.
+// B = |det J| J^-T.  One thread per cell writes its cell-node values, each to its
+// place in its DOF's contiguous range; one thread per DOF then sums its range in a
+// fixed (cell, node) order (no atomics) and applies the update rows of the scheme.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -42,10 +42,10 @@ struct Damp3 {
 };
 
 // w_q B g_v at every node q of the cell for the nodal values v, written to
-// components c0..c0+2 of the cell's slots.
+// components c0..c0+2 at the node's slot pos[q].
 template <typename T, int ND>
 __device__ __forceinline__ void put_grads(const T (&v)[ND], const T (&B)[9], T* out, int64_t ns, int c0,
-                                          int64_t e) {
+                                          const int32_t (&pos)[ND]) {
   using Tab = KmvTab<T, 3, ND>;
 #pragma unroll
   for (int q = 0; q < ND; ++q) {
@@ -60,7 +60,7 @@ __device__ __forceinline__ void put_grads(const T (&v)[ND], const T (&B)[9], T* 
     const T wq = Tab::W[q];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      out[(c0 + k) * ns + e * ND + q] = wq * (B[3 * k] * g[0] + B[3 * k + 1] * g[1] + B[3 * k + 2] * g[2]);
+      out[(c0 + k) * ns + pos[q]] = wq * (B[3 * k] * g[0] + B[3 * k + 1] * g[1] + B[3 * k + 2] * g[2]);
   }
 }
 
@@ -88,17 +88,21 @@ __global__ void __launch_bounds__(256) k_pml3_cell_fwd(const Pml3CellArgs<T> A) 
   if (e >= A.n_cells) return;
   const int64_t N = A.n_dofs, ns = A.n_cells * ND;
   int dof[ND];
+  int32_t pos[ND];
   T B[9], v[ND];
 #pragma unroll
-  for (int a = 0; a < ND; ++a) dof[a] = A.cdof[e * ND + a];
+  for (int a = 0; a < ND; ++a) {
+    dof[a] = A.cdof[a * A.n_cells + e];
+    pos[a] = A.cpos[a * A.n_cells + e];
+  }
 #pragma unroll
   for (int k = 0; k < 9; ++k) B[k] = A.b3[k * A.n_cells + e];
 #pragma unroll
   for (int a = 0; a < ND; ++a) v[a] = A.u[dof[a]];
-  put_grads<T, ND>(v, B, A.out, ns, 0, e);  // (D_k u^n)
+  put_grads<T, ND>(v, B, A.out, ns, 0, pos);  // (D_k u^n)
 #pragma unroll
   for (int a = 0; a < ND; ++a) v[a] = A.y[dof[a]];
-  put_grads<T, ND>(v, B, A.out, ns, 3, e);  // (D_k omega^n)
+  put_grads<T, ND>(v, B, A.out, ns, 3, pos);  // (D_k omega^n)
   T t[ND];
 #pragma unroll
   for (int j = 0; j < ND; ++j) t[j] = T(0);
@@ -110,7 +114,7 @@ __global__ void __launch_bounds__(256) k_pml3_cell_fwd(const Pml3CellArgs<T> A) 
     add_div_t<T, ND>(q, pq, B, t);  // sum_k D_k^T p_k^n
   }
 #pragma unroll
-  for (int q = 0; q < ND; ++q) A.out[6 * ns + e * ND + q] = t[q];
+  for (int q = 0; q < ND; ++q) A.out[6 * ns + pos[q]] = t[q];
 }
 
 template <typename T, int ND>
@@ -119,16 +123,20 @@ __global__ void __launch_bounds__(256) k_pml3_cell_adj(const Pml3CellArgs<T> A) 
   if (e >= A.n_cells) return;
   const int64_t N = A.n_dofs, ns = A.n_cells * ND;
   int dof[ND];
+  int32_t pos[ND];
   T B[9];
 #pragma unroll
-  for (int a = 0; a < ND; ++a) dof[a] = A.cdof[e * ND + a];
+  for (int a = 0; a < ND; ++a) {
+    dof[a] = A.cdof[a * A.n_cells + e];
+    pos[a] = A.cpos[a * A.n_cells + e];
+  }
 #pragma unroll
   for (int k = 0; k < 9; ++k) B[k] = A.b3[k * A.n_cells + e];
   {
     T l[ND];
 #pragma unroll
     for (int a = 0; a < ND; ++a) l[a] = A.u[dof[a]];  // lambda^{m+1}
-    put_grads<T, ND>(l, B, A.out, ns, 0, e);          // (D_k lambda^{m+1})
+    put_grads<T, ND>(l, B, A.out, ns, 0, pos);          // (D_k lambda^{m+1})
   }
   {
     T t1[ND], t2[ND];
@@ -151,8 +159,8 @@ __global__ void __launch_bounds__(256) k_pml3_cell_adj(const Pml3CellArgs<T> A) 
     }
 #pragma unroll
     for (int q = 0; q < ND; ++q) {
-      A.out[3 * ns + e * ND + q] = t1[q];
-      A.out[4 * ns + e * ND + q] = t2[q];
+      A.out[3 * ns + pos[q]] = t1[q];
+      A.out[4 * ns + pos[q]] = t2[q];
     }
   }
   if (A.uf == nullptr) return;
@@ -183,19 +191,20 @@ __global__ void __launch_bounds__(256) k_pml3_cell_adj(const Pml3CellArgs<T> A) 
     const T v0 = G[0] * gu[0] + G[1] * gu[1] + G[2] * gu[2];
     const T v1 = G[1] * gu[0] + G[3] * gu[1] + G[4] * gu[2];
     const T v2 = G[2] * gu[0] + G[4] * gu[1] + G[5] * gu[2];
-    A.out[5 * ns + e * ND + q] = Tab::W[q] * (gl[0] * v0 + gl[1] * v1 + gl[2] * v2);
+    A.out[5 * ns + pos[q]] = Tab::W[q] * (gl[0] * v0 + gl[1] * v1 + gl[2] * v2);
   }
-  put_grads<T, ND>(v, B, A.out, ns, 6, e);  // (D_k u^m)
+  put_grads<T, ND>(v, B, A.out, ns, 6, pos);  // (D_k u^m)
 #pragma unroll
   for (int a = 0; a < ND; ++a) v[a] = A.yf[dof[a]];
-  put_grads<T, ND>(v, B, A.out, ns, 9, e);  // (D_k omega^m)
+  put_grads<T, ND>(v, B, A.out, ns, 9, pos);  // (D_k omega^m)
 }
 
-// Sum of component c of DOF i's cell-node slots, in slot order.
+// Sum of component c of DOF i's cell-node values, which the per-cell pass wrote to
+// the DOF's own contiguous range [lo, hi), in ascending (cell, node) order.
 template <typename T>
-__device__ __forceinline__ T slot_sum(const T* x, int64_t ns, int c, int32_t lo, int32_t hi, const int32_t* slot) {
+__device__ __forceinline__ T slot_sum(const T* x, int64_t ns, int c, int32_t lo, int32_t hi) {
   T y = T(0);
-  for (int32_t k = lo; k < hi; ++k) y += x[c * ns + slot[k]];
+  for (int32_t k = lo; k < hi; ++k) y += x[c * ns + k];
   return y;
 }
 
@@ -212,10 +221,10 @@ __global__ void __launch_bounds__(256) k_pml3_fwd_update(const Pml3UpdateArgs<T>
   T du[3], dy[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    du[k] = slot_sum(A.cell_out, ns, k, lo, hi, A.csr_slot);
-    dy[k] = slot_sum(A.cell_out, ns, 3 + k, lo, hi, A.csr_slot);
+    du[k] = slot_sum(A.cell_out, ns, k, lo, hi);
+    dy[k] = slot_sum(A.cell_out, ns, 3 + k, lo, hi);
   }
-  const T dtp = slot_sum(A.cell_out, ns, 6, lo, hi, A.csr_slot);
+  const T dtp = slot_sum(A.cell_out, ns, 6, lo, hi);
   const Damp3<T> d(A.sig, N, i);
   const T M = A.mass[i], c2 = A.c2[i], dt = A.dt;
   const T a = T(0.5) * dt * d.tr;
@@ -247,9 +256,9 @@ __global__ void __launch_bounds__(256) k_pml3_adj_update(const Pml3UpdateArgs<T>
   const int32_t lo = A.csr_ptr[i], hi = A.csr_ptr[i + 1];
   T dl[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) dl[k] = slot_sum(A.cell_out, ns, k, lo, hi, A.csr_slot);
-  const T t1 = slot_sum(A.cell_out, ns, 3, lo, hi, A.csr_slot);
-  const T t2 = slot_sum(A.cell_out, ns, 4, lo, hi, A.csr_slot);
+  for (int k = 0; k < 3; ++k) dl[k] = slot_sum(A.cell_out, ns, k, lo, hi);
+  const T t1 = slot_sum(A.cell_out, ns, 3, lo, hi);
+  const T t2 = slot_sum(A.cell_out, ns, 4, lo, hi);
   const Damp3<T> d(A.sig, N, i);
   const T M = A.mass[i], dt = A.dt;
   const T a = T(0.5) * dt * d.tr;
@@ -269,11 +278,11 @@ __global__ void __launch_bounds__(256) k_pml3_adj_update(const Pml3UpdateArgs<T>
     A.p_io[k * N + i] = ((T(1) - b) * A.p_io[k * N + i] - T(2) * dt / M * dl[k]) / (T(1) + b);
   }
   if (A.gacc == nullptr) return;
-  T g = slot_sum(A.cell_out, ns, 5, lo, hi, A.csr_slot);
+  T g = slot_sum(A.cell_out, ns, 5, lo, hi);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const T duk = slot_sum(A.cell_out, ns, 6 + k, lo, hi, A.csr_slot);
-    const T dyk = slot_sum(A.cell_out, ns, 9 + k, lo, hi, A.csr_slot);
+    const T duk = slot_sum(A.cell_out, ns, 6 + k, lo, hi);
+    const T dyk = slot_sum(A.cell_out, ns, 9 + k, lo, hi);
     g += mu1[k] * (d.p2[k] * duk - d.p3[k] * dyk);
   }
   A.gacc[i] += (double)g;

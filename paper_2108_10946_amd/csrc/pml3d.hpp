@@ -12,11 +12,13 @@ namespace kmv {
 // lambda^{m+1}, p = mu^{m+1}, c2, sig; writes 0-2 (D_k lambda), 3 (sum_k D_k^T C_k
 // mu_k), 4 (sum_k D_k^T E_k mu_k) and, when uf (u^m) is set, 5 (the stiffness
 // pairing of lambda^{m+1} with u^m), 6-8 (D_k u^m), 9-11 (D_k omega^m, yf).
-// out: [component][n_cells*nd], slot e*nd + q.
+// out: [component][n_cells*nd]; node q of cell e writes to place cpos[q*n_cells + e],
+// inside its DOF's range of the per-DOF pass.
 template <typename T>
 struct Pml3CellArgs {
   int64_t n_cells = 0, n_dofs = 0;
-  const int32_t* cdof = nullptr;  // [n_cells*nd] DOF of node q of cell e
+  const int32_t* cdof = nullptr;  // [nd][n_cells] DOF of node q of cell e
+  const int32_t* cpos = nullptr;  // [nd][n_cells] its place in out
   const T* b3 = nullptr;          // [9][n_cells] |det J| J^-T, entry (k, r) at 3k + r
   const T* geom = nullptr;        // [6][n_cells] |det J| J^-1 J^-T, upper triangle
   const T* u = nullptr;
@@ -29,8 +31,8 @@ struct Pml3CellArgs {
   T* out = nullptr;
 };
 
-// Per-DOF pass: sums the cell-node slots of DOF i (csr_slot[csr_ptr[i] ..
-// csr_ptr[i+1]), ascending (cell, node)) and applies the update rows.
+// Per-DOF pass: sums DOF i's cell-node values (places csr_ptr[i] .. csr_ptr[i+1] of
+// each component, ascending (cell, node)) and applies the update rows.
 // Forward: u = u^n, u_prev = u^{n-1} (NULL: zero), y = omega^n, p_io = p^{n-1} in,
 // p^{n+1} out; u_out = u^{n+1}, y_out = omega^{n+1}; amp = w(t_n) (one value),
 // svec = the source's nodal load vector.  Adjoint: u = lambda^{m+1}, u_prev =
@@ -42,7 +44,6 @@ template <typename T>
 struct Pml3UpdateArgs {
   int64_t n_dofs = 0, n_slots = 0;
   const int32_t* csr_ptr = nullptr;
-  const int32_t* csr_slot = nullptr;
   const T* cell_out = nullptr;
   const T* sig = nullptr;
   const T* mass = nullptr;

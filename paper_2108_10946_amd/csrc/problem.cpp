@@ -988,6 +988,7 @@ Pml3CellArgs<T> pml3_cell_args(Problem* p) {
   a.n_cells = m.n_cells;
   a.n_dofs = m.n_dofs;
   a.cdof = p->d_cdof;
+  a.cpos = p->d_cpos;
   a.b3 = (const T*)p->d_b3;
   a.geom = (const T*)p->d_geom;
   a.c2 = (const T*)p->d_c2;
@@ -1003,7 +1004,6 @@ Pml3UpdateArgs<T> pml3_update_args(Problem* p) {
   a.n_dofs = m.n_dofs;
   a.n_slots = m.n_cells * m.nd;
   a.csr_ptr = p->d_csr_ptr;
-  a.csr_slot = p->d_csr_slot;
   a.cell_out = (const T*)p->d_cellout;
   a.sig = (const T*)p->d_sig;
   a.mass = (const T*)p->d_mass;
@@ -1201,7 +1201,7 @@ Problem::~Problem() {
                   d_ck_u, d_ck_du, d_resid, d_traces_tmp, d_wavelet, (void*)d_bnd_dof, (void*)d_bnd_ref,
                   (void*)d_bnd_coef, (void*)d_bnd_hb, d_ub, d_lb, (void*)d_bnd_part, d_sig, d_sig_ref, d_pml_b,
                   (void*)d_list[0], (void*)d_list[1], d_pp[0][0], d_pp[0][1], d_pp[1][0], d_pp[1][1], d_pt[0][0],
-                  d_pt[0][1], d_pt[1][0], d_pt[1][1], (void*)d_cdof, d_b3, (void*)d_csr_ptr, (void*)d_csr_slot,
+                  d_pt[0][1], d_pt[1][0], d_pt[1][1], (void*)d_cdof, d_b3, (void*)d_csr_ptr, (void*)d_cpos,
                   d_mass, d_cellout, d_ku, d_p3[0], d_p3[1], d_nu3[0], d_nu3[1], d_y3, d_svec, (void*)d_rptr,
                   (void*)d_ridx, d_rw})
     dfree(q);
@@ -1395,7 +1395,7 @@ Status set_pml3(Problem* p, const double* sigma) {
   std::vector<double> sc(3 * N);
   for (int64_t i = 0; i < N; ++i)
     for (int k = 0; k < 3; ++k) sc[k * N + i] = sigma[3 * i + k];
-  std::vector<int32_t> cdof((size_t)ne * nd), ptr(N + 1, 0), slot((size_t)ne * nd);
+  std::vector<int32_t> cdof((size_t)ne * nd), ptr(N + 1, 0), cpos((size_t)ne * nd);
   for (size_t k = 0; k < cdof.size(); ++k) {
     cdof[k] = (int32_t)m.cell_dofs[k];
     ptr[cdof[k] + 1]++;
@@ -1403,16 +1403,21 @@ Status set_pml3(Problem* p, const double* sigma) {
   for (int64_t i = 0; i < N; ++i) ptr[i + 1] += ptr[i];
   {
     std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
-    for (size_t k = 0; k < cdof.size(); ++k) slot[fill[cdof[k]]++] = (int32_t)k;  // ascending (cell, node)
+    for (size_t k = 0; k < cdof.size(); ++k)  // ascending (cell, node) within each DOF's range
+      cpos[(k % nd) * ne + k / nd] = fill[cdof[k]]++;
   }
   std::vector<double> b(9 * (size_t)ne);  // B_e = |det J| J^-T, entry (k, r) at 3k + r
   for (int64_t e = 0; e < ne; ++e)
     for (int k = 0; k < 3; ++k)
       for (int r = 0; r < 3; ++r) b[(size_t)(3 * k + r) * ne + e] = m.absdet[e] * m.jinv[e * 9 + r * 3 + k];
   STTRY(upload_real(&p->d_sig, sc, p->prec));
-  STTRY(upload_i(&p->d_cdof, cdof));
+  {
+    std::vector<int32_t> cm(cdof.size());  // node-major for the per-cell pass
+    for (size_t k = 0; k < cdof.size(); ++k) cm[(k % nd) * ne + k / nd] = cdof[k];
+    STTRY(upload_i(&p->d_cdof, cm));
+  }
   STTRY(upload_i(&p->d_csr_ptr, ptr));
-  STTRY(upload_i(&p->d_csr_slot, slot));
+  STTRY(upload_i(&p->d_cpos, cpos));
   STTRY(upload_real(&p->d_b3, b, p->prec));
   STTRY(upload_real(&p->d_mass, m.mass, p->prec));
   STTRY(alloc(&p->d_cellout, (size_t)12 * ne * nd * p->ts));
@@ -1444,7 +1449,7 @@ Status set_pml(Problem* p, const double* sigma) {
     p->d_sig = p->d_sig_ref = p->d_pml_b = nullptr;
     p->d_list[0] = p->d_list[1] = nullptr;
     p->n_list[0] = p->n_list[1] = 0;
-    for (void** q : {(void**)&p->d_cdof, &p->d_b3, (void**)&p->d_csr_ptr, (void**)&p->d_csr_slot, &p->d_mass,
+    for (void** q : {(void**)&p->d_cdof, &p->d_b3, (void**)&p->d_csr_ptr, (void**)&p->d_cpos, &p->d_mass,
                      &p->d_cellout, &p->d_ku, &p->d_p3[0], &p->d_p3[1], &p->d_nu3[0], &p->d_nu3[1], &p->d_y3}) {
       dfree(*q);
       *q = nullptr;

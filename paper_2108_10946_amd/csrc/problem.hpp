@@ -130,9 +130,9 @@ struct Problem {
   // contractions and per-DOF update rows beside the stiffness apply, one shot, the
   // forward states (u and omega) kept for the reverse sweep
   bool pml3 = false;
-  int32_t* d_cdof = nullptr;                    // [n_cells*nd] DOF of each cell node
+  int32_t* d_cdof = nullptr;                    // [nd][n_cells] DOF of each cell node
   void* d_b3 = nullptr;                         // [9*n_cells] |det J| J^-T
-  int32_t *d_csr_ptr = nullptr, *d_csr_slot = nullptr;  // DOF -> its cell-node slots
+  int32_t *d_csr_ptr = nullptr, *d_cpos = nullptr;  // DOF -> its range of cell-node values; their places
   void* d_mass = nullptr;                       // [n_dofs] lumped mass
   void* d_cellout = nullptr;                    // [12*n_cells*nd] cell-node values
   void* d_ku = nullptr;                         // [n_dofs] K u
