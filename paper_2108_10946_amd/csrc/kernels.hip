@@ -260,7 +260,7 @@ k_step(const StepArgs<T> A0) {
     gg[t] = A.sh_idx[jc[t]];
     sl[t] = reinterpret_cast<const int2*>(A.ref_slots)[jc[t]];
     cc[t] = A.c2_ref[jc[t]];
-    if (ADJ) ff[t] = A.uf[N + jc[t]];
+    if (ADJ) ff[t] = ld_once<T, DIM, NT>(A.uf + N + jc[t]);
     up[t] = ld_once<T, DIM, NT>(uref + jc[t]);
     dp[t] = ld_once<T, DIM, NT>(A.dsh_prev + jc[t]);
     gm[t] = A.gamma_ref[jc[t]];
@@ -340,7 +340,7 @@ k_step(const StepArgs<T> A0) {
     if (ADJ) {
       q0[ADJ ? t : 0] = A.partr_prev[sx];
       q1[ADJ ? t : 0] = A.partr_prev[sy2];
-      gs[ADJ ? t : 0] = A.gacc[gg[t]];
+      gs[ADJ ? t : 0] = ld_once<T, DIM, NT>(A.gacc + gg[t]);
     }
   }
   if (!damped) {
@@ -392,7 +392,7 @@ k_step(const StepArgs<T> A0) {
           rr = T(0);
           for (int k = A.shp_ptr[s]; k < A.shp_ptr[s + 1]; ++k) rr += A.partr_prev[A.shp_slot[k]];
         }
-        A.gacc[g] = gs[ADJ ? t : 0] + (double)rr;
+        st_once<T, DIM, NT>(gs[ADJ ? t : 0] + (double)rr, A.gacc + g);
       }
     }
   }
@@ -417,7 +417,7 @@ k_step(const StepArgs<T> A0) {
       s2[t] = reinterpret_cast<const int2*>(A.ref_slots)[r2[t]];
       u2[t] = ld_once<T, DIM, NT>(uref + r2[t]);
       c2v[t] = A.c2_ref[r2[t]];
-      if (ADJ) f2[t] = A.uf[N + r2[t]];
+      if (ADJ) f2[t] = ld_once<T, DIM, NT>(A.uf + N + r2[t]);
       d2[t] = ld_once<T, DIM, NT>(A.dsh_prev + r2[t]);
       gm2[t] = A.gamma_ref[r2[t]];
       b2[t] = bref[r2[t]];
@@ -492,7 +492,7 @@ k_step(const StepArgs<T> A0) {
   for (int i = tid + KO * bs; i < nbo; i += bs) {
     su[i] = A.u_in[bo0 + i];
     sc[i] = A.c2[bo0 + i];
-    if (ADJ) sf[i] = A.uf[bo0 + i];
+    if (ADJ) sf[i] = ld_once<T, DIM, NT>(A.uf + bo0 + i);
     if (GST) sg[i] = A.gacc[bo0 + i];
   }
   if (!OVL && tid == 0) {
