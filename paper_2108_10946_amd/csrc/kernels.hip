@@ -1077,7 +1077,7 @@ hipError_t launch_step_t(const StepArgs<T>& a, int np, int block, hipStream_t s,
   const size_t lds = StepLds(a.nbl_max, a.slot_stride, KmvTab<T, DIM, ND>::NB, a.glist_max, ADJ, sizeof(T),
                              DIM == 3, kStageGrad<T, ADJ, DIM, ND>, PML)
                           .total;
-  if constexpr (kStream<T, DIM> && !PML) {
+  if constexpr (kStream<T, DIM>) {
     if (a.n_shots == 1) {  // the streaming-hint instance (see ld_once)
       launch_ev(k_step<T, DIM, ND, ADJ, PML, true>, dim3(np), dim3(block), (uint32_t)lds, s, e0, e1, a);
       return hipGetLastError();
@@ -1089,7 +1089,7 @@ hipError_t launch_step_t(const StepArgs<T>& a, int np, int block, hipStream_t s,
 
 template <typename T, int DIM, int ND, bool ADJ, bool PML = false>
 hipError_t set_lds_t(int bytes) {
-  if constexpr (kStream<T, DIM> && !PML) {
+  if constexpr (kStream<T, DIM>) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step<T, DIM, ND, ADJ, PML, true>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
