@@ -209,10 +209,10 @@ int kmv_set_damping(kmv_problem p, const double* eta);
  * instance of their own; the gradient needs the forward states kept
  * (checkpoint_every = 0 with the states fitting mem_budget, or gradient_every > 1's
  * every r-th state), recomputing from checkpoints is refused with KMV_ENOMEM; device
- * memory 4 n_shots (n_dofs + shared refs) elements per sweep for p or mu, 4 n_shots
- * shared refs for their partial sums.  Tetrahedra: per-cell and per-DOF passes beside
+ * memory 4 n_shots (n_dofs + R) elements per sweep for p or mu, 4 n_shots R for
+ * their partial sums (R = the shared refs, at least 1).  Tetrahedra: per-cell and per-DOF passes beside
  * the stiffness apply; one shot per problem; the gradient keeps every forward level
- * of u and omega ((N_t + 1) (2 n_dofs + shared refs) elements within mem_budget, else
+ * of u and omega ((N_t + 1) (2 n_dofs + R) elements within mem_budget, else
  * KMV_ENOMEM); device memory 12 n_cells n_nodes elements of cell-node values and
  * 10 n_dofs of fields; not with the absorbing boundary term or kmv_forward_noalloc
  * (KMV_ESTATE).  Errors: KMV_EINVAL (negative or non-finite sigma, LDS on triangles,
@@ -263,9 +263,9 @@ int kmv_forward(kmv_problem p, const void* c_dev, void* traces_dev, void* stream
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * device allocation).  The two level buffers of the forward sweep live in the
  * library's static workspace of 64 MiB per device (held until the process ends)
- * instead of the problem's own, so the call needs 2 n_shots (n_dofs + shared refs)
- * elements of workspace; a larger problem is refused with KMV_EINVAL before any
- * work.  Everything else it uses was allocated when the problem was set up.  The
+ * instead of the problem's own, so the call needs 2 n_shots (n_dofs + R) elements of
+ * workspace, R = the shared refs (at least 1); a larger problem is refused with
+ * KMV_EINVAL before any work.  Everything else it uses was allocated when the problem was set up.  The
  * traces are bitwise those of kmv_forward.  Every call on one device shares that
  * workspace, so calls that overlap on one device (other streams, other threads)
  * race and must be serialised by the caller.  Launches are counted but not timed

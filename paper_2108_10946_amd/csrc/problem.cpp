@@ -1262,7 +1262,10 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
   p->block = step_block(m->max_patch_cells);
   p->nref = m->n_shared_refs;
   p->rs = std::max<int64_t>(1, p->nref);
-  p->ls = m->n_dofs + p->nref;
+  // a level vector: its DOFs, then a copy per shared ref; at least one such place, so
+  // that the step kernel's clamped ref loads (index 0 when the mesh has a single
+  // patch and no refs) stay inside every level buffer
+  p->ls = m->n_dofs + p->rs;
   p->nshot = n_shots;
   p->grad_every = grad_every;
   for (bool adjv : {false, true}) {
