@@ -93,6 +93,8 @@ Mesh* build_mesh(int dim, int degree, const double* coords, int64_t nv, const in
                  int64_t ne, int patch_cells) {
   if (dim != 2 && dim != 3) throw std::invalid_argument("dim must be 2 or 3");
   if (!coords || !cells || nv <= 0 || ne <= 0) throw std::invalid_argument("empty mesh");
+  // cells, DOFs and shared refs are indexed with 32-bit integers on the device
+  if (ne >= (int64_t)1 << 31 || nv >= (int64_t)1 << 31) throw std::invalid_argument("more than 2^31 cells or vertices");
   const Element& el = element(dim, degree);
   std::unique_ptr<Mesh> m(new Mesh());
   m->dim = dim;
@@ -433,6 +435,9 @@ Mesh* build_mesh(int dim, int degree, const double* coords, int64_t nv, const in
       pc[g] = 0;
       loc[g] = -1;
     }
+  }
+  if (sh_list.size() >= (size_t)1 << 31) {
+    throw std::invalid_argument("more than 2^31 shared refs (use larger patches)");
   }
   m->patch_sh_start[np] = (int32_t)sh_list.size();
   m->sh_idx = sh_list;
