@@ -92,7 +92,9 @@ int kmv_element_tables(int dim, int degree, int* n_nodes, double* nodes, double*
  *   coords [n_vertices*dim] (copied), cells [n_cells*(dim+1)] 0-based (copied).
  *   patch_cells: cells per patch, at most 256 (one GPU thread per cell; 0 = chosen
  *   from degree and dimension).
- * Errors: KMV_EINVAL, KMV_EDEGREE, KMV_EMESH (index out of range, zero volume). */
+ * Errors: KMV_EINVAL (also 2^31 or more cells, vertices, DOFs or shared refs: the
+ * device tables index them with 32-bit integers), KMV_EDEGREE, KMV_EMESH (index out
+ * of range, zero volume). */
 int kmv_mesh_create(int dim, int degree, const double* coords, int64_t n_vertices,
                     const int32_t* cells, int64_t n_cells, int patch_cells, kmv_mesh* out);
 /* Sizes: any output pointer may be NULL. */
