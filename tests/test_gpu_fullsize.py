@@ -200,3 +200,49 @@ def test_absorbing_boundary_central_differences(c2):
     assert J > 1e-6
     assert errs[-1] < 1e-6
     assert errs[-1] < errs[0] / 8
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_absorbing_boundary_window_vs_stored_oracle(c2, prec):
+    """The sponge plus the absorbing boundary term at full size (the bench's absorbing
+    leg), a 300-step window with the shot 10 m and the receivers 20 m below the top
+    boundary, against the oracle outputs stored by tests/golden/gen_absorbing_fullsize.py:
+    forward traces of the observed model, J, traces and the gradient at 400 sampled DOFs.
+    FP64 1e-10; FP32 1e-4 (traces), 1e-3 (sampled gradient), J within 1e-4 |r| |d|."""
+    import importlib.util
+    import json
+    import os
+    from scipy.spatial import cKDTree
+    from paper_2108_10946_amd import Problem
+    w, d, m, p = c2
+    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("gen_absorbing_fullsize",
+                                                  os.path.join(golden, "gen_absorbing_fullsize.py"))
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    with open(os.path.join(golden, "absorbing_fullsize_c2.json")) as f:
+        ref = json.load(f)
+    x = m.dof_coords()
+    dist, idx = cKDTree(x).query(np.array(ref["grad_coords"]))
+    assert dist.max() < 1e-9
+    say(f"full size: absorbing boundary window {prec}")
+    prob = Problem(m, ref["dt"], ref["nt"], precision=prec)
+    prob.set_damping(w.eta(*x.T))
+    prob.set_absorbing_boundary(True)
+    prob.set_sources(ref["src"], f0=ref["f0"], t0=ref["t0"])
+    prob.set_receivers(ref["rec"])
+    obs_or, tr_or = np.array(ref["observed"]), np.array(ref["traces"])
+    dd = prob.forward(cuda(w.vp_obs(*x.T))).double().cpu().numpy()
+    J, g, tr = prob.misfit_gradient(cuda(gen.current_model(w.vp_obs)(*x.T)), cuda(obs_or, prob.dtype),
+                                    keep_traces=True)
+    prob.close()
+    J_or, g_or = ref["J"], np.array(ref["grad_values"])
+    ed, et = rel_l2(dd, obs_or), rel_l2(tr.double().cpu().numpy(), tr_or)
+    eg = rel_l2(g.cpu().numpy()[idx], g_or)
+    say(f"  forward {ed:.2e}  J {J:.9e} (oracle {J_or:.9e})  traces {et:.2e}  sampled gradient {eg:.2e}")
+    if prec == "fp64":
+        assert ed < 1e-10 and et < 1e-10 and eg < 1e-10
+        assert abs(J - J_or) < 1e-10 * J_or
+    else:
+        assert ed < 1e-4 and et < 1e-4 and eg < 1e-3
+        assert abs(J - J_or) <= 1e-4 * np.sqrt(2 * J_or) * np.linalg.norm(tr_or)
