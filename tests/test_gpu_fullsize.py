@@ -246,3 +246,59 @@ def test_absorbing_boundary_window_vs_stored_oracle(c2, prec):
     else:
         assert ed < 1e-4 and et < 1e-4 and eg < 1e-3
         assert abs(J - J_or) <= 1e-4 * np.sqrt(2 * J_or) * np.linalg.norm(tr_or)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_eight_shots_window_vs_stored_oracle(c2, prec):
+    """One 8-shot problem of the 40-shot leg (shots 17-24 of the line, one launch per step
+    for the eight, checkpointed reverse sweep as that leg runs it) over a 200-step window,
+    against the oracle outputs stored by tests/golden/gen_shots_fullsize.py: every shot's
+    forward traces of the observed model and traces of the current model (every 5th
+    step), J summed over the shots, and the summed gradient at 400 sampled DOFs.  The
+    misfit takes the library's FP64 observed data, which the first check ties to the
+    oracle's.  FP64 1e-10; FP32 1e-4 (traces), 1e-3 (sampled gradient), J within
+    1e-4 |r| |d|."""
+    import importlib.util
+    import json
+    import os
+    from scipy.spatial import cKDTree
+    from paper_2108_10946_amd import Problem
+    w, d, m, p = c2
+    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("gen_shots_fullsize", os.path.join(golden, "gen_shots_fullsize.py"))
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    with open(os.path.join(golden, "shots_fullsize_c2.json")) as f:
+        ref = json.load(f)
+    x = m.dof_coords()
+    dist, idx = cKDTree(x).query(np.array(ref["grad_coords"]))
+    assert dist.max() < 1e-9
+    rows = slice(ref["row_step"] - 1, None, ref["row_step"])
+    say(f"full size: eight shots {prec}")
+
+    def make(precision, ck):
+        pr = Problem(m, ref["dt"], ref["nt"], precision=precision, n_shots=len(ref["shots"]), checkpoint_every=ck)
+        pr.set_damping(w.eta(*x.T))
+        pr.set_sources(ref["shots"], f0=ref["f0"], t0=ref["t0"])
+        pr.set_receivers(ref["rec"])
+        return pr
+
+    p64 = make("fp64", 0)
+    obs = p64.forward(cuda(w.vp_obs(*x.T)))
+    p64.close()
+    obs_or = np.array(ref["observed_rows"])
+    eo = rel_l2(obs.cpu().numpy()[:, rows], obs_or)
+    prob = make(prec, -1)
+    J, g, tr = prob.misfit_gradient(cuda(gen.current_model(w.vp_obs)(*x.T)), obs.to(prob.dtype), keep_traces=True)
+    prob.close()
+    tr_or, J_or, g_or = np.array(ref["traces_rows"]), float(np.sum(ref["J_per_shot"])), np.array(ref["grad_values"])
+    et = rel_l2(tr.double().cpu().numpy()[:, rows], tr_or)
+    eg = rel_l2(g.cpu().numpy()[idx], g_or)
+    say(f"  observed {eo:.2e}  J {J:.9e} (oracle {J_or:.9e})  traces {et:.2e}  sampled gradient {eg:.2e}")
+    assert eo < 1e-10
+    if prec == "fp64":
+        assert et < 1e-10 and eg < 1e-10
+        assert abs(J - J_or) < 1e-10 * J_or
+    else:
+        assert et < 1e-4 and eg < 1e-3
+        assert abs(J - J_or) <= 1e-4 * np.sqrt(2 * J_or) * np.linalg.norm(tr_or) * np.sqrt(ref["row_step"])
