@@ -302,3 +302,48 @@ def test_eight_shots_window_vs_stored_oracle(c2, prec):
     else:
         assert et < 1e-4 and eg < 1e-3
         assert abs(J - J_or) <= 1e-4 * np.sqrt(2 * J_or) * np.linalg.norm(tr_or) * np.sqrt(ref["row_step"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_subsampled_gradient_window_vs_stored_oracle(c2, prec):
+    """The paper's gradient subsampling at r = 10 at full size (the bench's subsampling
+    leg: every 10th state kept), a 300-step window against the oracle outputs stored by
+    tests/golden/gen_subsample_fullsize.py: J, traces and the r-scaled gradient at 400
+    sampled DOFs.  FP64 1e-10; FP32 1e-4 (traces), 1e-3 (sampled gradient), J within
+    1e-4 |r| |d|."""
+    import importlib.util
+    import json
+    import os
+    from scipy.spatial import cKDTree
+    from paper_2108_10946_amd import Problem
+    w, d, m, p = c2
+    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("gen_subsample_fullsize",
+                                                  os.path.join(golden, "gen_subsample_fullsize.py"))
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    with open(os.path.join(golden, "subsample_fullsize_c2.json")) as f:
+        ref = json.load(f)
+    x = m.dof_coords()
+    dist, idx = cKDTree(x).query(np.array(ref["grad_coords"]))
+    assert dist.max() < 1e-9
+    say(f"full size: gradient subsampling r={ref['r']} window {prec}")
+    prob = Problem(m, ref["dt"], ref["nt"], precision=prec, gradient_every=ref["r"])
+    prob.set_damping(w.eta(*x.T))
+    prob.set_sources(ref["src"], f0=ref["f0"], t0=ref["t0"])
+    prob.set_receivers(ref["rec"])
+    obs_or, tr_or = np.array(ref["observed"]), np.array(ref["traces"])
+    dd = prob.forward(cuda(w.vp_obs(*x.T))).double().cpu().numpy()
+    J, g, tr = prob.misfit_gradient(cuda(gen.current_model(w.vp_obs)(*x.T)), cuda(obs_or, prob.dtype),
+                                    keep_traces=True)
+    prob.close()
+    J_or, g_or = ref["J"], np.array(ref["grad_values"])
+    ed, et = rel_l2(dd, obs_or), rel_l2(tr.double().cpu().numpy(), tr_or)
+    eg = rel_l2(g.cpu().numpy()[idx], g_or)
+    say(f"  forward {ed:.2e}  J {J:.9e} (oracle {J_or:.9e})  traces {et:.2e}  sampled gradient {eg:.2e}")
+    if prec == "fp64":
+        assert ed < 1e-10 and et < 1e-10 and eg < 1e-10
+        assert abs(J - J_or) < 1e-10 * J_or
+    else:
+        assert ed < 1e-4 and et < 1e-4 and eg < 1e-3
+        assert abs(J - J_or) <= 1e-4 * np.sqrt(2 * J_or) * np.linalg.norm(tr_or)
