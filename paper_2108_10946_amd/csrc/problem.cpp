@@ -1270,7 +1270,9 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
   p->grad_every = grad_every;
   for (bool adjv : {false, true}) {
     const size_t bytes = step_lds_bytes(m->dim, m->nd, m->max_nbl, m->slot_stride, m->nb, m->max_glist, adjv, p->ts);
-    if (bytes > 160 * 1024) return Status{KMV_EINVAL, "patch LDS footprint above 160 KiB; use smaller patches"};
+    if (bytes > 160 * 1024)
+      return Status{KMV_EINVAL, "patch LDS footprint of " + std::to_string((bytes + 1023) / 1024) +
+                                    " KiB above the 160 KiB of a CU; use smaller patches (patch_cells)"};
     if (bytes > 64 * 1024) {
       if (prec == KMV_FP64)
         HIPTRY(set_step_lds_limit<double>(m->dim, m->nd, adjv, (int)bytes));
@@ -1468,7 +1470,9 @@ Status set_pml(Problem* p, const double* sigma) {
   for (bool adjv : {false, true}) {
     const size_t bytes =
         step_lds_bytes(m.dim, m.nd, m.max_nbl, m.slot_stride, m.nb, m.max_glist, adjv, p->ts, true);
-    if (bytes > 160 * 1024) return Status{KMV_EINVAL, "PML patch LDS footprint above 160 KiB; use smaller patches"};
+    if (bytes > 160 * 1024)
+      return Status{KMV_EINVAL, "PML patch LDS footprint of " + std::to_string((bytes + 1023) / 1024) +
+                                    " KiB above the 160 KiB of a CU; use smaller patches (patch_cells)"};
     if (bytes > 64 * 1024) {
       if (p->prec == KMV_FP64)
         HIPTRY(set_step_lds_limit<double>(m.dim, m.nd, adjv, (int)bytes, true));
