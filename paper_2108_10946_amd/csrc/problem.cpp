@@ -15,8 +15,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
+#include <tuple>
 
 #include "../../include/kmvwave.h"
 #include "boundary.hpp"
@@ -644,6 +646,23 @@ static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 void* g_scratch_ptr[kMaxDevices] = {};
+
+// The step kernels' dynamic-LDS limit is an attribute of the kernel function, shared
+// by every problem on the device: it is only raised (a problem with a smaller footprint
+// must not lower it under the launches of another), one caller at a time, and not set
+// again once it covers the request.  The device must be current.
+std::mutex g_lds_mu;
+std::map<std::tuple<int, int, int, int, bool, bool>, size_t> g_lds_limit;
+
+hipError_t raise_lds_limit(int device, int prec, int dim, int nd, bool adjoint, size_t bytes, bool pml) {
+  std::lock_guard<std::mutex> lk(g_lds_mu);
+  size_t& cur = g_lds_limit[std::make_tuple(device, prec, dim, nd, adjoint, pml)];
+  if (bytes <= cur) return hipSuccess;
+  const hipError_t e = prec == KMV_FP64 ? set_step_lds_limit<double>(dim, nd, adjoint, (int)bytes, pml)
+                                        : set_step_lds_limit<float>(dim, nd, adjoint, (int)bytes, pml);
+  if (e == hipSuccess) cur = bytes;
+  return e;
+}
 
 // Address of this device's workspace (the device must be current).
 Status scratch_ptr(int device, void** out) {
@@ -1273,12 +1292,7 @@ Status problem_create(Mesh* m, int prec, double dt, int64_t nt, int64_t ckpt_eve
     if (bytes > 160 * 1024)
       return Status{KMV_EINVAL, "patch LDS footprint of " + std::to_string((bytes + 1023) / 1024) +
                                     " KiB above the 160 KiB of a CU; use smaller patches (patch_cells)"};
-    if (bytes > 64 * 1024) {
-      if (prec == KMV_FP64)
-        HIPTRY(set_step_lds_limit<double>(m->dim, m->nd, adjv, (int)bytes));
-      else
-        HIPTRY(set_step_lds_limit<float>(m->dim, m->nd, adjv, (int)bytes));
-    }
+    if (bytes > 64 * 1024) HIPTRY(raise_lds_limit(p->device, prec, m->dim, m->nd, adjv, bytes, false));
   }
   {
     // local indices of node pairs (2q, 2q+1) of a cell packed in one 32-bit word, SoA
@@ -1473,12 +1487,7 @@ Status set_pml(Problem* p, const double* sigma) {
     if (bytes > 160 * 1024)
       return Status{KMV_EINVAL, "PML patch LDS footprint of " + std::to_string((bytes + 1023) / 1024) +
                                     " KiB above the 160 KiB of a CU; use smaller patches (patch_cells)"};
-    if (bytes > 64 * 1024) {
-      if (p->prec == KMV_FP64)
-        HIPTRY(set_step_lds_limit<double>(m.dim, m.nd, adjv, (int)bytes, true));
-      else
-        HIPTRY(set_step_lds_limit<float>(m.dim, m.nd, adjv, (int)bytes, true));
-    }
+    if (bytes > 64 * 1024) HIPTRY(raise_lds_limit(p->device, p->prec, m.dim, m.nd, adjv, bytes, true));
   }
   std::vector<double> sc(2 * N), eta(N), sr(2 * p->rs, 0.0);
   for (int64_t i = 0; i < N; ++i) {
